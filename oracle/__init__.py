@@ -1,0 +1,225 @@
+"""CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+Plain CPU reference for the constraint-checking pruner.  Only the test suite,
+the smoke check and the benchmark's CPU-baseline leg may import this package;
+the library never does, and the two share no code.
+
+`prune` runs the paper's main constraint-checking loop (generate the
+non-local constraints, initialise vertex state, LCC to a fixpoint, then for
+each constraint NLCC followed by LCC when anything changed) and finishes with
+the full-template search that makes the result exact.  `bruteforce` computes
+the plain definition of the output (union of all exact matches,
+Definition 1) by enumeration, and pins `prune` on small inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+import time
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import constraints as _cons
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C library with gcc (OpenMP)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-Wno-unused-function", src, "-o", tmp])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I64, I32 = ctypes.c_int64, ctypes.c_int
+    lib.orc_init_roles.restype = I32
+    lib.orc_init_roles.argtypes = [I64, P, I32, I32, P, P, P]
+    lib.orc_lcc.restype = I64
+    lib.orc_lcc.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64]
+    lib.orc_embed_exists.restype = I32
+    lib.orc_embed_exists.argtypes = [I64, P, P, P, I32, P, I32, ctypes.c_int32, I32,
+                                     ctypes.c_int32]
+    lib.orc_nlcc.restype = I64
+    lib.orc_nlcc.argtypes = [I64, P, P, P, I32, P, ctypes.c_uint64]
+    lib.orc_exact.restype = I32
+    lib.orc_exact.argtypes = [I64, P, P, P, I32, I32, P, P, P, P]
+    lib.orc_bruteforce.restype = I64
+    lib.orc_bruteforce.argtypes = [I64, P, P, P, I32, I32, P, P, P, P]
+    lib.orc_active_edges.restype = I32
+    lib.orc_active_edges.argtypes = [I64, P, P, P, I32, I32, P, P, P]
+    lib.orc_num_threads.restype = I32
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [I32]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def set_threads(t: int) -> None:
+    _load().orc_set_threads(int(t))
+
+
+class _G:
+    """Contiguous views of a graph in the oracle's argument types."""
+
+    def __init__(self, row_ptr, col, labels):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.labels = np.ascontiguousarray(labels, dtype=np.int32)
+        self.n = self.row_ptr.shape[0] - 1
+        self.m = int(self.row_ptr[-1])
+        if self.col.shape[0] == 0:
+            self.col = np.zeros(1, dtype=np.int32)
+
+
+class _T:
+    def __init__(self, labels, edges):
+        self.labels = np.ascontiguousarray(labels, dtype=np.int32)
+        e = np.asarray(edges, dtype=np.int32).reshape(-1, 2)
+        self.edges = np.ascontiguousarray(e if e.size else np.zeros((1, 2), np.int32))
+        self.n0 = len(labels)
+        self.m0 = int(e.shape[0])
+        self.edge_list = [(int(a), int(b)) for a, b in e]
+        self.label_list = [int(x) for x in labels]
+
+
+def nwords(m: int) -> int:
+    return (m + 63) // 64
+
+
+def init_roles(g: _G, t: _T) -> np.ndarray:
+    om = np.zeros(max(g.n, 1), dtype=np.uint64)
+    rc = _load().orc_init_roles(g.n, _p(g.labels), t.n0, t.m0, _p(t.labels), _p(t.edges), _p(om))
+    if rc:
+        raise ValueError("bad template")
+    return om[:g.n]
+
+
+def lcc(g: _G, t: _T, omega: np.ndarray, max_sweeps: int = -1) -> int:
+    sweeps = _load().orc_lcc(g.n, _p(g.row_ptr), _p(g.col), _p(g.labels), t.n0, t.m0,
+                             _p(t.labels), _p(t.edges), _p(omega), max_sweeps)
+    if sweeps < 0:
+        raise ValueError("bad template")
+    return int(sweeps)
+
+
+def nlcc(g: _G, omega: np.ndarray, c: _cons.Constraint) -> int:
+    se = np.ascontiguousarray(np.asarray(c.edges, dtype=np.int32).reshape(-1, 2))
+    ch = _load().orc_nlcc(g.n, _p(g.row_ptr), _p(g.col), _p(omega), se.shape[0], _p(se),
+                          ctypes.c_uint64(c.heads))
+    if ch < 0:
+        raise ValueError("bad constraint")
+    return int(ch)
+
+
+def exact(g: _G, t: _T, omega: np.ndarray):
+    role = np.zeros(max(g.n, 1), dtype=np.uint64)
+    edge = np.zeros(max(nwords(g.m), 1), dtype=np.uint64)
+    rc = _load().orc_exact(g.n, _p(g.row_ptr), _p(g.col), _p(omega), t.n0, t.m0,
+                           _p(t.labels), _p(t.edges), _p(role), _p(edge))
+    if rc:
+        raise ValueError("bad template")
+    return role[:g.n], edge[:nwords(g.m)]
+
+
+def active_edges(g: _G, t: _T, omega: np.ndarray) -> np.ndarray:
+    edge = np.zeros(max(nwords(g.m), 1), dtype=np.uint64)
+    _load().orc_active_edges(g.n, _p(g.row_ptr), _p(g.col), _p(omega), t.n0, t.m0,
+                             _p(t.labels), _p(t.edges), _p(edge))
+    return edge[:nwords(g.m)]
+
+
+def embed_exists(row_ptr, col, omega, sub_edges, qa, va, qb=-1, vb=-1) -> bool:
+    g = _G(row_ptr, col, np.zeros(len(row_ptr) - 1, np.int32))
+    om = np.ascontiguousarray(omega, dtype=np.uint64)
+    se = np.ascontiguousarray(np.asarray(sub_edges, dtype=np.int32).reshape(-1, 2))
+    if se.size == 0:
+        se = np.zeros((1, 2), np.int32)
+        me = 0
+    else:
+        me = se.shape[0]
+    return bool(_load().orc_embed_exists(g.n, _p(g.row_ptr), _p(g.col), _p(om), me, _p(se),
+                                         qa, va, qb, vb))
+
+
+@dataclasses.dataclass
+class Result:
+    role_mask: np.ndarray          # uint64[n]
+    edge_bits: np.ndarray          # uint64[ceil(m/64)]
+    lcc_sweeps: List[int]          # Jacobi sweeps per LCC call
+    constraint_changes: List[int]  # vertices shrunk by each constraint
+    order: List[int]
+    seconds: float = 0.0
+
+
+def constraints_for(labels, edges) -> List[_cons.Constraint]:
+    return _cons.non_local_constraints(list(labels), [tuple(e) for e in edges])
+
+
+def prune(row_ptr, col, labels, t_labels, t_edges, order: Optional[Sequence[int]] = None,
+          stop_after: Optional[int] = None) -> Result:
+    """Main constraint-checking loop plus the exact final step.
+
+    order: permutation of the constraint list (default: generated order).
+    stop_after: if given, stop after that many constraints (0 = after the
+    first LCC fixpoint) and return omega with the derived edge state instead
+    of running the exact step.
+    """
+    t0 = time.perf_counter()
+    g = _G(row_ptr, col, labels)
+    t = _T(t_labels, t_edges)
+    K0 = constraints_for(t.label_list, t.edge_list)
+    seq = list(range(len(K0))) if order is None else list(order)
+    omega = init_roles(g, t)
+    sweeps = [lcc(g, t, omega)]
+    changes = []
+    for k, ci in enumerate(seq):
+        if stop_after is not None and k >= stop_after:
+            break
+        ch = nlcc(g, omega, K0[ci])
+        changes.append(ch)
+        if ch:
+            sweeps.append(lcc(g, t, omega))
+    if stop_after is not None:
+        role, edge = omega.copy(), active_edges(g, t, omega)
+    else:
+        role, edge = exact(g, t, omega)
+    return Result(role, edge, sweeps, changes, seq, time.perf_counter() - t0)
+
+
+def bruteforce(row_ptr, col, labels, t_labels, t_edges):
+    """Union of all exact matches (Definition 1) by enumeration.
+    Returns (role_mask uint64[n], edge_bits uint64[ceil(m/64)], n_maps)."""
+    g = _G(row_ptr, col, labels)
+    t = _T(t_labels, t_edges)
+    role = np.zeros(max(g.n, 1), dtype=np.uint64)
+    edge = np.zeros(max(nwords(g.m), 1), dtype=np.uint64)
+    cnt = _load().orc_bruteforce(g.n, _p(g.row_ptr), _p(g.col), _p(g.labels), t.n0, t.m0,
+                                 _p(t.labels), _p(t.edges), _p(role), _p(edge))
+    if cnt < 0:
+        raise ValueError("bad or disconnected template")
+    return role[:g.n], edge[:nwords(g.m)], int(cnt)
