@@ -1,0 +1,172 @@
+/*
+ * pm.h -- C ABI of the constraint-checking pruner for AMD MI355X (gfx950).
+ *
+ * Problem (Preliminaries, Definition 1 of the paper): given a simple,
+ * undirected, vertex-labeled background graph G(V, E) and a small connected
+ * labeled template G0(V0, E0), compute the complete set: every (vertex,
+ * template role) pair and every edge that takes part in at least one exact
+ * match of G0 (an injective, label-preserving map phi of V0 into V that maps
+ * every template edge onto an edge of G; non-induced).
+ *
+ * Method (main constraint-checking loop): initialise each vertex's candidate
+ * roles omega(v) from its label (vertex state and initialisation algorithm),
+ * run local constraint checking (LCC) to a fixpoint, then for each
+ * non-local constraint (cycle, path and template-driven-search constraints
+ * generated per the constraint-generation table) run non-local constraint
+ * checking (NLCC) followed by LCC when anything changed, and finish with a
+ * full-template search that certifies every surviving role and edge.
+ *
+ * Conventions
+ *  - All functions return PM_OK (0) or a negative PM_ERR_* code; the message
+ *    of the last error on the calling thread is returned by pm_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - Device pointers are HIP device addresses on the context's device.
+ *  - A context is bound to one device and one HIP stream and must not be used
+ *    from two threads at once.  Calls on one context are serialised on its
+ *    stream; pm_prune returns after its work has completed.
+ *  - Role bit q of a role mask is template vertex q in the order given to
+ *    pm_load_templates.  Edge bit e (bit e % 64 of word e / 64, least
+ *    significant bit first) is CSR entry e of the loaded graph; the edge set
+ *    is symmetric.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PM_OK               0
+#define PM_ERR_INVALID_ARG (-1)   /* null pointer, bad size or flag         */
+#define PM_ERR_HIP         (-2)   /* a HIP runtime call failed              */
+#define PM_ERR_GRAPH       (-3)   /* graph violates the CSR contract        */
+#define PM_ERR_TEMPLATE    (-4)   /* template invalid or over the limits    */
+#define PM_ERR_NO_GRAPH    (-5)   /* pm_prune before pm_load_graph          */
+#define PM_ERR_CAPACITY    (-6)   /* an internal bound was exceeded         */
+#define PM_ERR_OOM         (-7)   /* device memory exhausted                */
+#define PM_ERR_NOT_FOUND   (-8)   /* unknown template id                    */
+
+/* ---- limits -------------------------------------------------------------- */
+#define PM_MAX_TEMPLATE_VERTICES 64   /* role masks are 64-bit              */
+#define PM_MAX_COUNT_RULES       32   /* per-label distinct-count rules     */
+#define PM_MAX_CONSTRAINTS       64   /* non-local constraints per template */
+
+/* ---- flags for pm_load_graph ---------------------------------------------- */
+#define PM_HOST_PTRS  1u   /* row_ptr/col/labels are host memory: copied      */
+#define PM_VALIDATE   2u   /* check the CSR contract (costs a host pass)      */
+
+typedef struct pm_ctx pm_ctx;
+
+/* Template: n0 vertices with labels[n0], m0 undirected edges given as
+   edges[2*i], edges[2*i+1] (vertex indices < n0).  Host memory, copied. */
+typedef struct {
+    uint32_t n0;
+    uint32_t m0;
+    const uint16_t *labels;
+    const uint32_t *edges;
+} pm_template;
+
+/* Order of the non-local constraints. */
+#define PM_ORDER_FIXED   0   /* generation order (ordering heuristics)      */
+#define PM_ORDER_GIVEN   1   /* options.order[] permutation                  */
+
+typedef struct {
+    int32_t order_mode;            /* PM_ORDER_FIXED or PM_ORDER_GIVEN        */
+    int32_t n_order;               /* entries in order[] for PM_ORDER_GIVEN   */
+    int32_t order[PM_MAX_CONSTRAINTS];
+    int32_t stop_after;            /* -1: full prune.  k >= 0: stop after k
+                                      constraints (0 = after the first LCC
+                                      fixpoint); outputs are then omega and
+                                      the edge state it implies, without the
+                                      final search                            */
+    int32_t reserved[7];
+} pm_options;
+
+/* Per-call statistics (valid when pm_prune returns PM_OK). */
+typedef struct {
+    double ms_total;               /* whole prune, device time                */
+    double ms_init;                /* role initialisation                     */
+    double ms_lcc;                 /* all LCC sweeps                          */
+    double ms_compact;             /* candidate-subgraph compaction           */
+    double ms_nlcc;                /* all non-local constraint checks         */
+    double ms_exact;               /* final full-template search              */
+    double ms_first_sweep;         /* first LCC sweep over the full graph     */
+    int64_t lcc_sweeps;            /* LCC sweeps run                          */
+    int64_t constraints;           /* non-local constraints checked           */
+    int64_t first_sweep_vertices;  /* active vertices in the first sweep      */
+    int64_t first_sweep_entries;   /* their CSR entries                       */
+    int64_t candidate_entries;     /* entries of the compacted subgraph       */
+    int64_t vertex_queries;        /* full-template searches from a vertex    */
+    int64_t edge_queries;          /* full-template searches from an edge     */
+    int64_t result_vertices;       /* vertices with a non-empty role mask     */
+    int64_t reserved[6];
+} pm_stats;
+
+/* Returns the message for the last error on this thread ("" if none). */
+const char *pm_last_error(void);
+
+/* Library version string. */
+const char *pm_version(void);
+
+/* Create a context on HIP device `device` using `hip_stream` (a hipStream_t,
+   NULL for the default stream).  *out receives the context. */
+int pm_create(pm_ctx **out, int device, void *hip_stream);
+
+/* Release the context and all device memory the library allocated. */
+int pm_destroy(pm_ctx *ctx);
+
+/* Load the background graph (Preliminaries: simple, undirected,
+   vertex-labeled): n vertices, m CSR entries (both directions of every
+   edge), row_ptr int64[n+1], col int32[m] with sorted rows, no self-loops
+   and no duplicate entries, labels[n] of label_bytes (1 or 2) bytes each.
+   The arrays are borrowed -- they must stay valid and unchanged until
+   pm_unload_graph/pm_destroy -- unless PM_HOST_PTRS is set, in which case
+   they are copied to device memory owned by the context.  PM_VALIDATE
+   checks symmetry, ordering, loops and id range and returns PM_ERR_GRAPH on
+   a violation. */
+int pm_load_graph(pm_ctx *ctx, int64_t n, int64_t m, const int64_t *row_ptr,
+                  const int32_t *col, const void *labels, int label_bytes, uint32_t flags);
+
+/* Forget the loaded graph (and free copies made under PM_HOST_PTRS). */
+int pm_unload_graph(pm_ctx *ctx);
+
+/* Compile `count` templates (constraint generation per the paper's table of
+   Steps 1-5 and the TDS-generation algorithm; search plans; LCC tables).
+   Templates must be connected (Preliminaries), have 1..64 vertices, no
+   self-loops or duplicate edges, and at most PM_MAX_COUNT_RULES
+   distinct-count rules.  *first_id receives the id of the first template;
+   the others follow consecutively.  PM_ERR_TEMPLATE on a violation; no
+   template is added then. */
+int pm_load_templates(pm_ctx *ctx, int32_t count, const pm_template *t, int32_t *first_id);
+
+/* Number of non-local constraints of template `id` and their kinds
+   (0 cycle, 1 path, 2 TDS-cycle, 3 TDS-path), edge counts and head masks, in
+   generation order.  Arrays must hold PM_MAX_CONSTRAINTS entries; edges_out
+   receives, for constraint i, its edges at edges_out[i*2*64 ...] as pairs
+   (a < b) sorted ascending, up to 64 pairs. */
+int pm_template_constraints(pm_ctx *ctx, int32_t id, int32_t *count, int32_t *kinds,
+                            int32_t *n_edges, uint64_t *heads, uint32_t *edges_out);
+
+/* Same as pm_template_constraints for a template that is compiled on the
+   host only (no context, no device): validation and constraint generation.
+   Returns PM_ERR_TEMPLATE for an invalid template. */
+int pm_inspect_template(const pm_template *t, int32_t *count, int32_t *kinds, int32_t *n_edges,
+                        uint64_t *heads, uint32_t *edges_out);
+
+/* Prune the loaded graph against templates first_id .. first_id+count-1.
+   role_mask: device uint64[count][n]; edge_bits: device
+   uint64[count][ceil(m/64)]; both caller-owned and fully overwritten.
+   opt may be NULL (fixed order, full prune).  stats may be NULL; with count
+   > 1 it receives the sums over the templates. */
+int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
+             uint64_t *edge_bits, const pm_options *opt, pm_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

@@ -7,9 +7,12 @@ check and the benchmark's CPU baseline may use it.
 
 Readings of passages the paper leaves open (each is also listed in the design
 notes):
-  * FIND_CIRCLES: every simple cycle of G'0, canonicalised as the vertex
+  * FIND_CIRCLES: the simple cycles of G'0, canonicalised as the vertex
     sequence that starts at its smallest vertex and whose second vertex is
-    smaller than its last; sorted by (length, sequence); at most 32 kept.
+    smaller than its last; sorted by (length, sequence); at most 32 kept,
+    enumerated length by length so only the lengths that contribute are
+    explored (a template with more than 100000 cycles of one length is
+    refused).
   * FIND_SHORTEST_PATH(G0, qi, qj, 3): breadth-first search over G0 from qi,
     neighbours in ascending index, first discoverer is the parent; the path
     is used only if it has at least 3 hops (Step 4).  Step 4(ii) drops a path
@@ -73,28 +76,41 @@ def _norm(a, b):
     return (a, b) if a < b else (b, a)
 
 
+MAX_CYCLES_PER_LENGTH = 100000
+
+
 def simple_cycles(n0: int, edges: Sequence[Tuple[int, int]], allowed: int) -> List[Tuple[int, ...]]:
-    """All simple cycles (length >= 3) of the subgraph induced on `allowed`."""
+    """Simple cycles (length >= 3) of the subgraph induced on `allowed`, by
+    increasing length; enumeration stops after the first length at which at
+    least MAX_CYCLES cycles have been found (only the first MAX_CYCLES in
+    (length, sequence) order are used)."""
     adj = _adj(n0, [e for e in edges if (allowed >> e[0]) & 1 and (allowed >> e[1]) & 1])
     out = []
-    for s in range(n0):
-        if not (allowed >> s) & 1:
-            continue
-        path = [s]
-        on = {s}
+    for length in range(3, n0 + 1):
+        found = []
+        for s in range(n0):
+            if not (allowed >> s) & 1:
+                continue
+            path = [s]
+            on = {s}
 
-        def dfs(x):
-            for y in adj[x]:
-                if y == s and len(path) >= 3 and path[1] < path[-1]:
-                    out.append(tuple(path))
-                elif y > s and y not in on:
-                    path.append(y); on.add(y)
-                    dfs(y)
-                    path.pop(); on.discard(y)
-        dfs(s)
-    out.sort(key=lambda c: (len(c), c))
+            def dfs(x):
+                for y in adj[x]:
+                    if len(path) == length:
+                        if y == s and path[1] < path[-1]:
+                            found.append(tuple(path))
+                            if len(found) > MAX_CYCLES_PER_LENGTH:
+                                raise ValueError("too many cycles in template")
+                    elif y > s and y not in on:
+                        path.append(y); on.add(y)
+                        dfs(y)
+                        path.pop(); on.discard(y)
+            dfs(s)
+        found.sort()
+        out += found
+        if len(out) >= MAX_CYCLES:
+            break
     return out
-
 
 def shortest_path(n0: int, edges, src: int, dst: int) -> List[int]:
     adj = _adj(n0, edges)

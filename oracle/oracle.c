@@ -199,18 +199,27 @@ static void make_plan(plan_t *P, uint64_t vmask, const uint64_t *sadj, int qa, i
     }
 }
 
+/* Step `pos` proposes images for template vertex q[pos] among the neighbours
+   of an already-mapped template neighbour's image -- the one with the
+   fewest neighbours, which changes only how many proposals are made -- and
+   accepts x if q[pos] is in omega(x) (so l(x) = l(q)), x is not yet used,
+   and x is adjacent to the images of all mapped template neighbours. */
 static int extend(const graph_t *G, const uint64_t *omega, const plan_t *P, int pos,
                   int32_t *img) {
     if (pos == P->k) return 1;
     const int q = P->q[pos];
-    const int32_t p = img[P->parent[pos]];
+    int32_t p = img[P->parent[pos]];
+    for (int j = 0; j < pos; ++j)
+        if (((P->back[pos] >> j) & 1) &&
+            G->row_ptr[img[j] + 1] - G->row_ptr[img[j]] < G->row_ptr[p + 1] - G->row_ptr[p])
+            p = img[j];
     for (int64_t e = G->row_ptr[p]; e < G->row_ptr[p + 1]; ++e) {
         const int32_t x = G->col[e];
         if (!((omega[x] >> q) & 1)) continue;            /* role / label check */
         int ok = 1;
         for (int j = 0; j < pos && ok; ++j) if (img[j] == x) ok = 0;   /* injective */
         for (int j = 0; j < pos && ok; ++j)
-            if (((P->back[pos] >> j) & 1) && find_edge(G, x, img[j]) < 0) ok = 0;
+            if (((P->back[pos] >> j) & 1) && img[j] != p && find_edge(G, img[j], x) < 0) ok = 0;
         if (!ok) continue;
         img[pos] = x;
         if (extend(G, omega, P, pos + 1, img)) return 1;

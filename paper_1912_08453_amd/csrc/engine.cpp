@@ -1,0 +1,724 @@
+// Host engine and C ABI of libpm: context, graph and template loading, and
+// the pruning driver (main constraint-checking loop of the paper: generate
+// the non-local constraints, initialise vertex state, LCC to a fixpoint,
+// then for each constraint NLCC and, when it changed anything, LCC again;
+// finally the full-template search that certifies roles and edges).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "pm.h"
+#include "pm_internal.h"
+
+namespace pm {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+static thread_local std::string g_last_error;
+
+#define PM_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t _e = (call);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            throw Error(_e == hipErrorOutOfMemory ? PM_ERR_OOM : PM_ERR_HIP,                  \
+                        std::string(#call) + ": " + hipGetErrorString(_e));                  \
+    } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t want) {
+        if (want <= bytes) return;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t alloc = std::max<size_t>(want, 256);
+        PM_HIP(hipMalloc(&p, alloc));
+        bytes = alloc;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct Timer {
+    hipEvent_t a{}, b{};
+    hipStream_t s{};
+    explicit Timer(hipStream_t st) : s(st) {
+        PM_HIP(hipEventCreate(&a));
+        PM_HIP(hipEventCreate(&b));
+        PM_HIP(hipEventRecord(a, s));
+    }
+    double stop() {
+        PM_HIP(hipEventRecord(b, s));
+        PM_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        PM_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace pm
+
+using namespace pm;
+
+struct pm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // graph
+    bool has_graph = false;
+    int64_t n = 0, m = 0;
+    const int64_t *rp = nullptr;
+    const int32_t *col = nullptr;
+    const void *labels = nullptr;
+    int label_bytes = 1;
+    DevBuf own_rp, own_col, own_labels;
+    std::vector<int64_t> label_freq;
+    int64_t hub_cap = 0, seg_cap = 0;
+    // templates
+    std::vector<std::unique_ptr<CompiledTemplate>> templates;
+    // scratch
+    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
+    DevBuf eu, ew, eidx, edge_plan_ids;
+    int grid_search = 2048;
+};
+
+namespace {
+
+void set_device(pm_ctx *c) { PM_HIP(hipSetDevice(c->device)); }
+
+template <typename T>
+void d2h(hipStream_t s, T *dst, const T *src, size_t count) {
+    PM_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+}
+
+// Counter block layout (int32 unless noted).
+enum : int {
+    C_BINS = 0,        // [4]
+    C_NSEG = 4,
+    C_CHANGED = 5,
+    C_TASK = 6,
+    C_ACTIVE = 7,
+    C_NOUT = 8,
+    C_QUERIES_U64 = 16,   // byte offset 64: unsigned long long
+    C_ENTRIES_U64 = 18,   // byte offset 72: unsigned long long
+    C_TOTAL_BYTES = 128,
+};
+
+struct Graph {
+    const int64_t *rp;
+    const int32_t *col;
+};
+
+template <typename M>
+struct Pruner {
+    pm_ctx *c;
+    const CompiledTemplate &T;
+    hipStream_t s;
+    M *om;
+    M *sat;
+    int32_t *A;              // active list
+    int32_t *Aalt;
+    int64_t nA = 0;
+    Worklists wl{};
+    int32_t *ctr;
+    unsigned long long *queries;
+    int64_t hc[4] = {0, 0, 0, 0};
+    int64_t nseg = 0;
+    // compacted candidate subgraph
+    int64_t *c_rp = nullptr;
+    int32_t *c_col = nullptr;
+    int32_t *c_off = nullptr;
+    int64_t c_m = 0;
+    pm_stats st{};
+
+    Pruner(pm_ctx *ctx, const CompiledTemplate &t) : c(ctx), T(t), s(ctx->stream) {
+        const int64_t n = c->n;
+        c->omega.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
+        c->sat.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
+        c->alist[0].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+        c->alist[1].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+        c->bins.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1) * kNumBins);
+        c->counters.ensure(C_TOTAL_BYTES);
+        const int64_t hubs = std::max<int64_t>(c->hub_cap, 1), segs = std::max<int64_t>(c->seg_cap, 1);
+        size_t hub_bytes = (size_t)segs * (4 + 8 + 8 + 4) + (size_t)hubs * (4 + 4 + 8 + 4 * kMaxCount + 4);
+        c->hub.ensure(hub_bytes + 256);
+        c->segcnt.ensure(sizeof(int64_t) * (size_t)segs);
+        om = c->omega.as<M>();
+        sat = c->sat.as<M>();
+        A = c->alist[0].as<int32_t>();
+        Aalt = c->alist[1].as<int32_t>();
+        ctr = c->counters.as<int32_t>();
+        queries = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 64);
+        for (int b = 0; b < kNumBins; ++b) wl.list[b] = c->bins.as<int32_t>() + (size_t)b * n;
+        wl.count = ctr + C_BINS;
+        wl.entries = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 72);
+        wl.n_seg = ctr + C_NSEG;
+        char *h = c->hub.as<char>();
+        wl.hub_seg_begin = reinterpret_cast<int64_t *>(h); h += 8 * (size_t)segs;
+        wl.hub_seg_end = reinterpret_cast<int64_t *>(h); h += 8 * (size_t)segs;
+        wl.hub_cover = reinterpret_cast<uint64_t *>(h); h += 8 * (size_t)hubs;
+        wl.hub_seg_v = reinterpret_cast<int32_t *>(h); h += 4 * (size_t)segs;
+        wl.hub_seg_slot = reinterpret_cast<int32_t *>(h); h += 4 * (size_t)segs;
+        wl.hub_nseg = reinterpret_cast<int32_t *>(h); h += 4 * (size_t)hubs;
+        wl.hub_seg_first = reinterpret_cast<int32_t *>(h); h += 4 * (size_t)hubs;
+        wl.hub_ticket = reinterpret_cast<int32_t *>(h); h += 4 * (size_t)hubs;
+        wl.hub_count = reinterpret_cast<int32_t *>(h);
+        wl.capacity = n;
+        wl.hub_capacity = hubs;
+        wl.seg_capacity = segs;
+    }
+
+    void zero_counters() { PM_HIP(hipMemsetAsync(ctr, 0, C_TOTAL_BYTES, s)); }
+
+    int32_t read_ctr(int idx) {
+        int32_t v = 0;
+        d2h(s, &v, ctr + idx, 1);
+        return v;
+    }
+
+    // Active list <- vertices of the current list whose role set is non-empty.
+    void collect(bool from_all) {
+        PM_HIP(hipMemsetAsync(ctr + C_ACTIVE, 0, sizeof(int32_t), s));
+        if (from_all) {
+            launch_collect<M>(s, nullptr, c->n, om, A, ctr + C_ACTIVE);
+        } else {
+            launch_collect<M>(s, A, nA, om, Aalt, ctr + C_ACTIVE);
+            std::swap(A, Aalt);
+        }
+        nA = read_ctr(C_ACTIVE);
+    }
+
+    // Degree bins of the active list in graph g, hub segments, host counts.
+    int64_t binned_entries = 0;
+    void bin(const Graph &g) {
+        PM_HIP(hipMemsetAsync(ctr + C_BINS, 0, sizeof(int32_t) * 5, s));
+        PM_HIP(hipMemsetAsync(wl.entries, 0, sizeof(unsigned long long), s));
+        launch_bin<M>(s, A, nA, g.rp, om, wl);
+        launch_hub_segments(s, g.rp, wl, 0);
+        int32_t h[5];
+        d2h(s, h, ctr + C_BINS, 5);
+        for (int b = 0; b < 4; ++b) hc[b] = h[b];
+        nseg = h[4];
+        unsigned long long ent = 0;
+        d2h(s, &ent, wl.entries, 1);
+        binned_entries = (int64_t)ent;
+        if (hc[3] > wl.hub_capacity || nseg > wl.seg_capacity)
+            throw Error(PM_ERR_CAPACITY, "hub segment capacity exceeded");
+    }
+
+    int32_t sweep(const Graph &g) {
+        PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
+        launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, T.lcc, ctr + C_CHANGED);
+        st.lcc_sweeps++;
+        return read_ctr(C_CHANGED);
+    }
+
+    // LCC to the fixpoint on graph g, starting from the current active list.
+    void lcc_fixpoint(const Graph &g) {
+        Timer t(s);
+        for (;;) {
+            bin(g);
+            int32_t ch = sweep(g);
+            if (!ch) break;
+            collect(false);
+            if (nA == 0) break;
+        }
+        st.ms_lcc += t.stop();
+    }
+
+    // Compacted candidate subgraph of the current state (edge elimination).
+    void compact() {
+        Timer t(s);
+        const int64_t n = c->n;
+        Graph full{c->rp, c->col};
+        bin(full);
+        c->cdeg.ensure(sizeof(int64_t) * (size_t)(n + 1));
+        c->crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
+        int64_t *deg = c->cdeg.as<int64_t>();
+        PM_HIP(hipMemsetAsync(deg, 0, sizeof(int64_t) * (size_t)(n + 1), s));
+        launch_compact_count<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, deg,
+                                c->segcnt.as<int64_t>());
+        int64_t sl = scan_scratch_len(n);
+        c->scan_scratch.ensure(sizeof(int64_t) * (size_t)sl);
+        c_rp = c->crp.as<int64_t>();
+        launch_exclusive_scan(s, deg, c_rp, n, c->scan_scratch.as<int64_t>(), sl);
+        d2h(s, &c_m, c_rp + n, 1);
+        c->ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
+        c->coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
+        c_col = c->ccol.as<int32_t>();
+        c_off = c->coff.as<int32_t>();
+        launch_compact_fill<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, c_rp,
+                               c->segcnt.as<int64_t>(), c_col, c_off);
+        st.candidate_entries = c_m;
+        st.ms_compact += t.stop();
+    }
+
+    SearchArgs search_args(int mode, uint64_t heads, const int32_t *plan_of_head,
+                           uint64_t *edge_bits) {
+        SearchArgs a{};
+        a.c_rp = c_rp;
+        a.c_col = c_col;
+        a.c_off = c_off;
+        a.rp = c->rp;
+        a.col = c->col;
+        a.plans = T.d_plans;
+        a.plan_edges = T.d_plan_edges;
+        a.m0 = T.m0;
+        a.mode = mode;
+        a.heads = heads;
+        for (int i = 0; i < kMaxK; ++i) a.plan_of_head[i] = plan_of_head[i];
+        a.edge_bits = edge_bits;
+        a.task_counter = ctr + C_TASK;
+        a.n_queries = queries;
+        return a;
+    }
+
+    // One non-local constraint (snapshot semantics); returns vertices changed.
+    int32_t nlcc(const Constraint &k) {
+        Timer t(s);
+        PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
+        SearchArgs a = search_args(0, k.heads, k.plan_of_head, nullptr);
+        launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
+        PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
+        launch_apply<M>(s, A, nA, om, sat, k.heads, ctr + C_CHANGED);
+        int32_t ch = read_ctr(C_CHANGED);
+        st.constraints++;
+        st.ms_nlcc += t.stop();
+        return ch;
+    }
+
+    void exact(uint64_t *role_out, uint64_t *edge_out) {
+        Timer t(s);
+        const int64_t n = c->n;
+        // cert lives in sat (cleared by every apply and at start)
+        const uint64_t all = T.n0 == 64 ? ~0ull : ((1ull << T.n0) - 1ull);
+        unsigned long long q0 = 0, q1 = 0;
+        PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
+        PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
+        SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
+        launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
+        d2h(s, &q0, queries, 1);
+        // edge part over vertices with certified roles
+        std::swap(om, sat);   // collect() reads `om`: use the certified sets
+        collect(false);
+        std::swap(om, sat);
+        const int64_t cap = c_m / 2 + 1;
+        c->eu.ensure(sizeof(int32_t) * (size_t)cap);
+        c->ew.ensure(sizeof(int32_t) * (size_t)cap);
+        c->eidx.ensure(sizeof(int64_t) * (size_t)cap);
+        PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
+        launch_edge_candidates<M>(s, A, nA, c_rp, c_col, c_off, c->rp, sat, T.lcc, edge_out,
+                                  c->eu.as<int32_t>(), c->ew.as<int32_t>(),
+                                  c->eidx.as<int64_t>(), ctr + C_NOUT, cap);
+        int64_t ne = read_ctr(C_NOUT);
+        if (ne > cap) throw Error(PM_ERR_CAPACITY, "edge candidate capacity exceeded");
+        if (ne > 0) {
+            c->edge_plan_ids.ensure(sizeof(int32_t) * std::max<size_t>(T.edge_plans.size(), 1));
+            PM_HIP(hipMemcpyAsync(c->edge_plan_ids.p, T.edge_plans.data(),
+                                  sizeof(int32_t) * T.edge_plans.size(), hipMemcpyHostToDevice, s));
+            PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
+            PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
+            launch_edge_search<M>(s, c->eu.as<int32_t>(), c->ew.as<int32_t>(),
+                                  c->eidx.as<int64_t>(), ne, sat, sat,
+                                  c->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
+                                  a, c->grid_search);
+            d2h(s, &q1, queries, 1);
+        }
+        launch_widen<M>(s, n, sat, role_out);
+        st.vertex_queries += (int64_t)q0;
+        st.edge_queries += (int64_t)q1;
+        st.ms_exact += t.stop();
+    }
+
+    void run(uint64_t *role_out, uint64_t *edge_out, const pm_options *opt) {
+        Timer total(s);
+        const int64_t n = c->n, m = c->m;
+        zero_counters();
+        launch_fill_u64(s, edge_out, (m + 63) / 64, 0ull);
+        {
+            Timer t(s);
+            launch_init_roles<M>(s, n, c->labels, c->label_bytes, T.d_init_lut, T.init_lut_len, om);
+            PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
+            collect(true);
+            st.ms_init += t.stop();
+        }
+        Graph full{c->rp, c->col};
+        if (T.n0 > 1 && nA > 0) {
+            // first sweep over the full graph
+            Timer t(s);
+            bin(full);
+            st.first_sweep_vertices = nA;
+            st.first_sweep_entries = binned_entries;
+            int32_t ch = sweep(full);
+            st.ms_first_sweep = t.stop();
+            st.ms_lcc += st.ms_first_sweep;
+            if (ch) collect(false);
+        }
+        // candidate subgraph (edge elimination) and the rest of LCC on it
+        compact();
+        Graph cand{c_rp, c_col};
+        if (T.n0 > 1 && nA > 0) lcc_fixpoint(cand);
+        int stop_after = opt ? opt->stop_after : -1;
+        std::vector<int> order;
+        if (opt && opt->order_mode == PM_ORDER_GIVEN) {
+            if (opt->n_order != (int)T.constraints.size())
+                throw Error(PM_ERR_INVALID_ARG, "order length differs from the constraint count");
+            std::vector<char> seen(T.constraints.size(), 0);
+            for (int i = 0; i < opt->n_order; ++i) {
+                int k = opt->order[i];
+                if (k < 0 || k >= (int)T.constraints.size() || seen[k])
+                    throw Error(PM_ERR_INVALID_ARG, "order is not a permutation");
+                seen[k] = 1;
+                order.push_back(k);
+            }
+        } else {
+            for (size_t i = 0; i < T.constraints.size(); ++i) order.push_back((int)i);
+        }
+        int done = 0;
+        for (int k : order) {
+            if (stop_after >= 0 && done >= stop_after) break;
+            if (nA == 0) break;
+            int32_t ch = nlcc(T.constraints[k]);
+            ++done;
+            if (ch) {
+                collect(false);
+                if (nA > 0) lcc_fixpoint(cand);
+            }
+        }
+        if (stop_after >= 0 || T.acyclic_unique || T.n0 == 1) {
+            // omega and its implied edge state (exact for acyclic unique-label
+            // templates: LCC alone suffices)
+            launch_widen<M>(s, n, om, role_out);
+            if (T.n0 > 1)
+                launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, T.lcc, edge_out);
+        } else {
+            if (nA > 0) compact();
+            exact(role_out, edge_out);
+        }
+        st.ms_total = total.stop();
+    }
+};
+
+void load_template_device(pm_ctx *c, CompiledTemplate &T) {
+    PM_HIP(hipMalloc(&T.d_plans, sizeof(SearchPlan) * std::max<size_t>(T.plans.size(), 1)));
+    PM_HIP(hipMemcpy(T.d_plans, T.plans.data(), sizeof(SearchPlan) * T.plans.size(),
+                     hipMemcpyHostToDevice));
+    PM_HIP(hipMalloc(&T.d_plan_edges, sizeof(PlanEdge) * std::max<size_t>(T.plan_edges.size(), 1)));
+    if (!T.plan_edges.empty())
+        PM_HIP(hipMemcpy(T.d_plan_edges, T.plan_edges.data(), sizeof(PlanEdge) * T.plan_edges.size(),
+                         hipMemcpyHostToDevice));
+    int maxl = 0;
+    for (int q = 0; q < T.n0; ++q) maxl = std::max(maxl, T.labels[q]);
+    std::vector<uint64_t> lut((size_t)maxl + 1, 0);
+    for (int q = 0; q < T.n0; ++q) lut[T.labels[q]] |= 1ull << q;
+    T.init_lut_len = (int64_t)lut.size();
+    PM_HIP(hipMalloc(&T.d_init_lut, sizeof(uint64_t) * lut.size()));
+    PM_HIP(hipMemcpy(T.d_init_lut, lut.data(), sizeof(uint64_t) * lut.size(), hipMemcpyHostToDevice));
+    (void)c;
+}
+
+void free_template_device(CompiledTemplate &T) {
+    if (T.d_plans) (void)hipFree(T.d_plans);
+    if (T.d_plan_edges) (void)hipFree(T.d_plan_edges);
+    if (T.d_init_lut) (void)hipFree(T.d_init_lut);
+    T.d_plans = nullptr;
+    T.d_plan_edges = nullptr;
+    T.d_init_lut = nullptr;
+}
+
+void validate_graph(int64_t n, int64_t m, const int64_t *rp, const int32_t *col) {
+    if (rp[0] != 0 || rp[n] != m) throw Error(PM_ERR_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] = m");
+    for (int64_t v = 0; v < n; ++v) {
+        if (rp[v + 1] < rp[v]) throw Error(PM_ERR_GRAPH, "row_ptr not monotone");
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            int32_t w = col[e];
+            if (w < 0 || w >= n) throw Error(PM_ERR_GRAPH, "column index out of range");
+            if (w == v) throw Error(PM_ERR_GRAPH, "self-loop");
+            if (e > rp[v] && col[e - 1] >= w) throw Error(PM_ERR_GRAPH, "row not strictly sorted");
+            // symmetric: v must appear in row w
+            const int32_t *b = col + rp[w], *en = col + rp[w + 1];
+            if (!std::binary_search(b, en, (int32_t)v)) throw Error(PM_ERR_GRAPH, "graph not symmetric");
+        }
+    }
+}
+
+template <typename F>
+int guarded(F &&f) {
+    try {
+        f();
+        g_last_error.clear();
+        return PM_OK;
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return PM_ERR_OOM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return PM_ERR_HIP;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pm_last_error(void) { return g_last_error.c_str(); }
+
+const char *pm_version(void) { return "pm 0.1 gfx950"; }
+
+int pm_create(pm_ctx **out, int device, void *hip_stream) {
+    return guarded([&] {
+        if (!out) throw Error(PM_ERR_INVALID_ARG, "out is null");
+        int ndev = 0;
+        PM_HIP(hipGetDeviceCount(&ndev));
+        if (device < 0 || device >= ndev) throw Error(PM_ERR_INVALID_ARG, "bad device index");
+        auto *c = new pm_ctx();
+        c->device = device;
+        c->stream = (hipStream_t)hip_stream;
+        try {
+            set_device(c);
+            hipDeviceProp_t prop;
+            PM_HIP(hipGetDeviceProperties(&prop, device));
+            c->grid_search = std::max(256, prop.multiProcessorCount * 8);
+        } catch (...) {
+            delete c;
+            throw;
+        }
+        *out = c;
+    });
+}
+
+int pm_destroy(pm_ctx *c) {
+    return guarded([&] {
+        if (!c) return;
+        (void)hipSetDevice(c->device);
+        for (auto &t : c->templates) free_template_device(*t);
+        for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->omega, &c->sat, &c->alist[0],
+                          &c->alist[1], &c->bins, &c->counters, &c->hub, &c->cdeg, &c->crp,
+                          &c->ccol, &c->coff, &c->segcnt, &c->scan_scratch, &c->eu, &c->ew,
+                          &c->eidx, &c->edge_plan_ids})
+            b->release();
+        delete c;
+    });
+}
+
+int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                  const void *labels, int label_bytes, uint32_t flags) {
+    return guarded([&] {
+        if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
+        if (n < 0 || m < 0 || n >= (int64_t)INT32_MAX) throw Error(PM_ERR_INVALID_ARG, "bad n or m");
+        if (!row_ptr || (m > 0 && !col) || (n > 0 && !labels))
+            throw Error(PM_ERR_INVALID_ARG, "null graph array");
+        if (label_bytes != 1 && label_bytes != 2) throw Error(PM_ERR_INVALID_ARG, "label_bytes must be 1 or 2");
+        set_device(c);
+        const bool host = (flags & PM_HOST_PTRS) != 0;
+        // host copy of row_ptr (hub sizing; validation)
+        std::vector<int64_t> h_rp((size_t)n + 1);
+        if (host) {
+            std::memcpy(h_rp.data(), row_ptr, sizeof(int64_t) * (size_t)(n + 1));
+        } else {
+            PM_HIP(hipMemcpy(h_rp.data(), row_ptr, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToHost));
+        }
+        if (h_rp[0] != 0 || h_rp[n] != m) throw Error(PM_ERR_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] = m");
+        if (flags & PM_VALIDATE) {
+            std::vector<int32_t> h_col;
+            const int32_t *hc = col;
+            if (!host) {
+                h_col.resize((size_t)std::max<int64_t>(m, 1));
+                if (m) PM_HIP(hipMemcpy(h_col.data(), col, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost));
+                hc = h_col.data();
+            }
+            validate_graph(n, m, h_rp.data(), hc);
+        }
+        c->has_graph = false;
+        c->own_rp.release();
+        c->own_col.release();
+        c->own_labels.release();
+        if (host) {
+            c->own_rp.ensure(sizeof(int64_t) * (size_t)(n + 1));
+            c->own_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1));
+            c->own_labels.ensure((size_t)label_bytes * (size_t)std::max<int64_t>(n, 1));
+            PM_HIP(hipMemcpy(c->own_rp.p, row_ptr, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice));
+            if (m) PM_HIP(hipMemcpy(c->own_col.p, col, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice));
+            if (n) PM_HIP(hipMemcpy(c->own_labels.p, labels, (size_t)label_bytes * (size_t)n, hipMemcpyHostToDevice));
+            c->rp = c->own_rp.as<int64_t>();
+            c->col = c->own_col.as<int32_t>();
+            c->labels = c->own_labels.p;
+        } else {
+            c->rp = row_ptr;
+            c->col = col;
+            c->labels = labels;
+        }
+        c->n = n;
+        c->m = m;
+        c->label_bytes = label_bytes;
+        // hub capacity for the LCC sweep and compaction
+        int64_t hubs = 0, segs = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            int64_t d = h_rp[v + 1] - h_rp[v];
+            if (d > kBinWaveMaxDeg) {
+                ++hubs;
+                segs += (d + kHubSegment - 1) / kHubSegment;
+            }
+        }
+        c->hub_cap = hubs;
+        c->seg_cap = segs;
+        // label frequencies (search-order heuristic)
+        const int64_t hl = label_bytes == 1 ? 256 : 65536;
+        DevBuf hist;
+        hist.ensure(sizeof(unsigned long long) * (size_t)hl);
+        PM_HIP(hipMemsetAsync(hist.p, 0, sizeof(unsigned long long) * (size_t)hl, c->stream));
+        launch_label_hist(c->stream, n, c->labels, label_bytes, hist.as<unsigned long long>(), hl);
+        std::vector<unsigned long long> h((size_t)hl);
+        PM_HIP(hipMemcpyAsync(h.data(), hist.p, sizeof(unsigned long long) * (size_t)hl,
+                              hipMemcpyDeviceToHost, c->stream));
+        PM_HIP(hipStreamSynchronize(c->stream));
+        hist.release();
+        c->label_freq.assign(h.begin(), h.end());
+        c->has_graph = true;
+    });
+}
+
+int pm_unload_graph(pm_ctx *c) {
+    return guarded([&] {
+        if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
+        set_device(c);
+        c->has_graph = false;
+        c->own_rp.release();
+        c->own_col.release();
+        c->own_labels.release();
+        c->rp = nullptr;
+        c->col = nullptr;
+        c->labels = nullptr;
+    });
+}
+
+int pm_load_templates(pm_ctx *c, int32_t count, const pm_template *t, int32_t *first_id) {
+    return guarded([&] {
+        if (!c || !t || !first_id || count <= 0) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        set_device(c);
+        std::vector<std::unique_ptr<CompiledTemplate>> made;
+        for (int i = 0; i < count; ++i) {
+            auto T = std::make_unique<CompiledTemplate>();
+            std::string err = compile_template((int)t[i].n0, (int)t[i].m0, t[i].labels, t[i].edges,
+                                               c->label_freq, *T);
+            if (!err.empty()) {
+                for (auto &x : made) free_template_device(*x);
+                throw Error(PM_ERR_TEMPLATE, "template " + std::to_string(i) + ": " + err);
+            }
+            load_template_device(c, *T);
+            made.push_back(std::move(T));
+        }
+        *first_id = (int32_t)c->templates.size();
+        for (auto &x : made) c->templates.push_back(std::move(x));
+    });
+}
+
+int pm_template_constraints(pm_ctx *c, int32_t id, int32_t *count, int32_t *kinds,
+                            int32_t *n_edges, uint64_t *heads, uint32_t *edges_out) {
+    return guarded([&] {
+        if (!c || !count) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        if (id < 0 || id >= (int32_t)c->templates.size()) throw Error(PM_ERR_NOT_FOUND, "unknown template id");
+        const CompiledTemplate &T = *c->templates[(size_t)id];
+        *count = (int32_t)T.constraints.size();
+        for (size_t i = 0; i < T.constraints.size(); ++i) {
+            const Constraint &k = T.constraints[i];
+            if (kinds) kinds[i] = k.kind;
+            if (n_edges) n_edges[i] = (int32_t)k.edges.size();
+            if (heads) heads[i] = k.heads;
+            if (edges_out)
+                for (size_t j = 0; j < k.edges.size() && j < 64; ++j) {
+                    edges_out[i * 128 + 2 * j] = (uint32_t)k.edges[j].first;
+                    edges_out[i * 128 + 2 * j + 1] = (uint32_t)k.edges[j].second;
+                }
+        }
+    });
+}
+
+int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, uint64_t *edge_bits,
+             const pm_options *opt, pm_stats *stats) {
+    return guarded([&] {
+        if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
+        if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
+        if (count <= 0 || first_id < 0 || first_id + count > (int32_t)c->templates.size())
+            throw Error(PM_ERR_NOT_FOUND, "template id range out of bounds");
+        if (!role_mask || !edge_bits) throw Error(PM_ERR_INVALID_ARG, "null output");
+        set_device(c);
+        pm_stats total{};
+        const int64_t words = (c->m + 63) / 64;
+        for (int32_t i = 0; i < count; ++i) {
+            const CompiledTemplate &T = *c->templates[(size_t)(first_id + i)];
+            uint64_t *ro = role_mask + (size_t)i * (size_t)c->n;
+            uint64_t *eo = edge_bits + (size_t)i * (size_t)words;
+            pm_stats st{};
+            switch (T.mask_bytes) {
+            case 1: { Pruner<uint8_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
+            case 2: { Pruner<uint16_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
+            case 4: { Pruner<uint32_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
+            default: { Pruner<uint64_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
+            }
+            total.ms_total += st.ms_total;
+            total.ms_init += st.ms_init;
+            total.ms_lcc += st.ms_lcc;
+            total.ms_compact += st.ms_compact;
+            total.ms_nlcc += st.ms_nlcc;
+            total.ms_exact += st.ms_exact;
+            total.ms_first_sweep += st.ms_first_sweep;
+            total.lcc_sweeps += st.lcc_sweeps;
+            total.constraints += st.constraints;
+            total.first_sweep_vertices += st.first_sweep_vertices;
+            total.first_sweep_entries += st.first_sweep_entries;
+            total.candidate_entries += st.candidate_entries;
+            total.vertex_queries += st.vertex_queries;
+            total.edge_queries += st.edge_queries;
+        }
+        PM_HIP(hipStreamSynchronize(c->stream));
+        if (stats) *stats = total;
+    });
+}
+
+}  // extern "C"
+
+extern "C" int pm_inspect_template(const pm_template *t, int32_t *count, int32_t *kinds,
+                                   int32_t *n_edges, uint64_t *heads, uint32_t *edges_out) {
+    return guarded([&] {
+        if (!t || !count) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        CompiledTemplate T;
+        std::string err = compile_template((int)t->n0, (int)t->m0, t->labels, t->edges, {}, T);
+        if (!err.empty()) throw Error(PM_ERR_TEMPLATE, err);
+        *count = (int32_t)T.constraints.size();
+        for (size_t i = 0; i < T.constraints.size(); ++i) {
+            const Constraint &k = T.constraints[i];
+            if (kinds) kinds[i] = k.kind;
+            if (n_edges) n_edges[i] = (int32_t)k.edges.size();
+            if (heads) heads[i] = k.heads;
+            if (edges_out)
+                for (size_t j = 0; j < k.edges.size() && j < 64; ++j) {
+                    edges_out[i * 128 + 2 * j] = (uint32_t)k.edges[j].first;
+                    edges_out[i * 128 + 2 * j + 1] = (uint32_t)k.edges[j].second;
+                }
+        }
+    });
+}

@@ -1,0 +1,688 @@
+// Local constraint checking kernels for gfx950: role initialisation, degree
+// binning with wavefront prefix-sum compaction, the LCC sweep, the
+// candidate-subgraph compaction (edge elimination) and a device-wide scan.
+//
+// LCC (the paper's LCC algorithm and its visitor): a vertex v keeps role q
+// iff every template neighbour of q is a role of some neighbour of v
+// (coverage) and, for every label L, at least as many distinct neighbours of
+// label L carry a role adjacent to q as q has template neighbours of label L
+// (distinct-count rule).  The visitor's alive messages become gathers of the
+// neighbours' role masks straight from HBM; an edge counts only when the two
+// role sets are adjacent in G0, which is exactly what the coverage and count
+// tests read, so the edge state is derived and never stored.  Updates are
+// made in place: the local rule is monotone in the neighbours' role sets and
+// only ever removes roles, so in-place (chaotic) sweeps reach the same
+// greatest fixpoint as synchronous sweeps.
+#include "device_util.h"
+#include "pm_internal.h"
+
+namespace pm {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------- helpers
+template <typename M>
+__device__ __forceinline__ uint64_t reach_of(uint64_t w, const LccTable &tab) {
+    uint64_t r = 0;
+    for (int q = 0; q < tab.n0; ++q)
+        if ((w >> q) & 1ull) r |= tab.adj[q];
+    return r;
+}
+
+template <bool CNT>
+__device__ __forceinline__ uint64_t evaluate(uint64_t w, uint64_t cover, const int *cnt,
+                                             const LccTable &tab) {
+    uint64_t nw = w;
+    for (int q = 0; q < tab.n0; ++q)
+        if (((w >> q) & 1ull) && (tab.adj[q] & ~cover)) nw &= ~(1ull << q);
+    if constexpr (CNT) {
+#pragma unroll
+        for (int c = 0; c < kMaxCount; ++c)
+            if (c < tab.ncount && ((w >> tab.cq[c]) & 1ull) && cnt[c] < tab.cneed[c])
+                nw &= ~(1ull << tab.cq[c]);
+    }
+    return nw;
+}
+
+// ------------------------------------------------------- role initialisation
+// omega0(v) = { q : l(q) = l(v) } (vertex state and initialisation algorithm)
+template <typename M>
+__global__ __launch_bounds__(kBlock) void init_roles_kernel(int64_t n, const void *labels,
+                                                            int label_bytes, const uint64_t *lut,
+                                                            int64_t lut_len, M *omega) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int64_t L = label_bytes == 1 ? (int64_t)((const uint8_t *)labels)[v]
+                                 : (int64_t)((const uint16_t *)labels)[v];
+    omega[v] = (M)(L < lut_len ? lut[L] : 0ull);
+}
+
+template <typename M>
+void launch_init_roles(hipStream_t s, int64_t n, const void *labels, int label_bytes,
+                       const uint64_t *lut, int64_t lut_len, M *omega) {
+    if (n <= 0) return;
+    int64_t grid = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(init_roles_kernel<M>, dim3((unsigned)grid), dim3(kBlock), 0, s, n, labels,
+                       label_bytes, lut, lut_len, omega);
+}
+
+// ---------------------------------------------------------------- binning
+__device__ __forceinline__ int degree_bin(int64_t d) {
+    return d <= kBinSmallMaxDeg ? 0 : d <= kBinMidMaxDeg ? 1 : d <= kBinWaveMaxDeg ? 2 : 3;
+}
+
+// Append v to list b with one atomic per wavefront (ballot + prefix count).
+__device__ __forceinline__ void wave_append(bool pred, int32_t v, int32_t *list, int32_t *counter) {
+    uint64_t m = ballot64(pred);
+    if (!m) return;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(m & lanemask_lt())] = v;
+}
+
+template <typename M>
+__global__ __launch_bounds__(kBlock) void bin_kernel(const int32_t *in, int64_t n_in,
+                                                     const int64_t *rp, const M *omega,
+                                                     Worklists wl) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = i < n_in;
+    int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
+    bool act = valid && omega[v] != 0;
+    const int64_t d = act ? rp[v + 1] - rp[v] : 0;
+    int b = act ? degree_bin(d) : -1;
+#pragma unroll
+    for (int k = 0; k < kNumBins; ++k) wave_append(b == k, v, wl.list[k], wl.count + k);
+    unsigned long long tot = (unsigned long long)d;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+    if (lane_id() == 0 && tot) atomicAdd(wl.entries, tot);
+}
+
+// Active list: the vertices of `in` (or 0..n-1) whose role set is not empty.
+template <typename M>
+__global__ __launch_bounds__(kBlock) void collect_kernel(const int32_t *in, int64_t n_in,
+                                                         const M *omega, int32_t *out,
+                                                         int32_t *counter) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = i < n_in;
+    int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
+    wave_append(valid && omega[v] != 0, v, out, counter);
+}
+
+template <typename M>
+void launch_collect(hipStream_t s, const int32_t *in, int64_t n_in, const M *omega,
+                    int32_t *out, int32_t *counter) {
+    if (n_in <= 0) return;
+    int64_t grid = (n_in + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(collect_kernel<M>, dim3((unsigned)grid), dim3(kBlock), 0, s, in, n_in,
+                       omega, out, counter);
+}
+
+template <typename M>
+void launch_bin(hipStream_t s, const int32_t *in, int64_t n_in, const int64_t *rp,
+                const M *omega, Worklists &wl) {
+    if (n_in <= 0) return;
+    int64_t grid = (n_in + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(bin_kernel<M>, dim3((unsigned)grid), dim3(kBlock), 0, s, in, n_in, rp,
+                       omega, wl);
+}
+
+// Hub vertices are split into segments of kHubSegment entries, one wavefront
+// each; a single block assigns segments with a block-wide exclusive scan.
+__global__ __launch_bounds__(1024) void hub_segments_kernel(const int64_t *rp, Worklists wl) {
+    __shared__ int64_t sc[1024];
+    __shared__ int64_t running_s;
+    const int tid = threadIdx.x;
+    const int64_t n_hubs = wl.count[3];
+    if (tid == 0) running_s = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n_hubs; base += 1024) {
+        int64_t i = base + tid;
+        int32_t v = 0;
+        int64_t b = 0, d = 0, ns = 0;
+        if (i < n_hubs) {
+            v = wl.list[3][i];
+            b = rp[v];
+            d = rp[v + 1] - b;
+            ns = (d + kHubSegment - 1) / kHubSegment;
+        }
+        sc[tid] = ns;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int64_t t = tid >= off ? sc[tid - off] : 0;
+            __syncthreads();
+            sc[tid] += t;
+            __syncthreads();
+        }
+        int64_t first = running_s + sc[tid] - ns;
+        if (i < n_hubs && i < wl.hub_capacity) {
+            for (int64_t k = 0; k < ns; ++k) {
+                int64_t seg = first + k;
+                if (seg < wl.seg_capacity) {
+                    wl.hub_seg_v[seg] = v;
+                    wl.hub_seg_begin[seg] = b + k * kHubSegment;
+                    wl.hub_seg_end[seg] = (k + 1) * kHubSegment < d ? b + (k + 1) * kHubSegment : b + d;
+                    wl.hub_seg_slot[seg] = (int32_t)i;
+                }
+            }
+            wl.hub_nseg[i] = (int32_t)ns;
+            wl.hub_seg_first[i] = (int32_t)first;
+            wl.hub_cover[i] = 0;
+            wl.hub_ticket[i] = 0;
+            for (int c = 0; c < kMaxCount; ++c) wl.hub_count[i * kMaxCount + c] = 0;
+        }
+        __syncthreads();
+        if (tid == 1023) running_s += sc[1023];
+        __syncthreads();
+    }
+    if (tid == 0) *wl.n_seg = (int32_t)running_s;
+}
+
+void launch_hub_segments(hipStream_t s, const int64_t *rp, Worklists &wl, int64_t) {
+    hipLaunchKernelGGL(hub_segments_kernel, dim3(1), dim3(1024), 0, s, rp, wl);
+}
+
+// ------------------------------------------------------------- LCC sweep
+// G lanes per vertex (G = 4, 16, 64) for vertices of the three lower bins.
+template <typename M, int G, bool CNT>
+__global__ __launch_bounds__(kBlock) void lcc_group_kernel(const int64_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           M *omega,
+                                                           const int32_t *__restrict__ list,
+                                                           int64_t count, LccTable tab,
+                                                           int32_t *changed) {
+    const int lane = lane_id();
+    const int sl = lane & (G - 1);
+    const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const bool valid = idx < count;
+    const int32_t v = valid ? list[idx] : 0;
+    const uint64_t w = valid ? (uint64_t)omega[v] : 0ull;
+    int64_t s = 0, e = 0;
+    if (w) {
+        s = rp[v];
+        e = rp[v + 1];
+    }
+    uint64_t cover = 0;
+    int cnt[CNT ? kMaxCount : 1];
+#pragma unroll
+    for (int c = 0; c < (CNT ? kMaxCount : 1); ++c) cnt[c] = 0;
+    for (int64_t k = s + sl; k < e; k += G) {
+        const uint64_t x = (uint64_t)omega[col[k]];
+        cover |= x;
+        if constexpr (CNT) {
+#pragma unroll
+            for (int c = 0; c < kMaxCount; ++c)
+                if (c < tab.ncount) cnt[c] += (x & tab.cmask[c]) != 0ull;
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        cover |= shfl_xor_u64(cover, off, G);
+        if constexpr (CNT) {
+#pragma unroll
+            for (int c = 0; c < kMaxCount; ++c)
+                if (c < tab.ncount) cnt[c] += __shfl_xor(cnt[c], off, G);
+        }
+    }
+    bool ch = false;
+    if (w && sl == 0) {
+        uint64_t nw = evaluate<CNT>(w, cover, cnt, tab);
+        if (nw != w) {
+            omega[v] = (M)nw;
+            ch = true;
+        }
+    }
+    if (ballot64(ch) && lane == 0) atomicAdd(changed, 1);
+}
+
+// One wavefront per hub segment; partial coverage and counts are combined
+// with atomics and the last segment of a vertex (ticket) applies the rule.
+template <typename M, bool CNT>
+__global__ __launch_bounds__(kBlock) void lcc_hub_kernel(const int64_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col, M *omega,
+                                                         Worklists wl, int64_t n_seg,
+                                                         LccTable tab, int32_t *changed) {
+    const int lane = lane_id();
+    const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (seg >= n_seg) return;
+    const int32_t v = wl.hub_seg_v[seg];
+    const int32_t slot = wl.hub_seg_slot[seg];
+    const int64_t b = wl.hub_seg_begin[seg], e = wl.hub_seg_end[seg];
+    uint64_t cover = 0;
+    int cnt[CNT ? kMaxCount : 1];
+#pragma unroll
+    for (int c = 0; c < (CNT ? kMaxCount : 1); ++c) cnt[c] = 0;
+    for (int64_t k = b + lane; k < e; k += kWave) {
+        const uint64_t x = (uint64_t)omega[col[k]];
+        cover |= x;
+        if constexpr (CNT) {
+#pragma unroll
+            for (int c = 0; c < kMaxCount; ++c)
+                if (c < tab.ncount) cnt[c] += (x & tab.cmask[c]) != 0ull;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        cover |= shfl_xor_u64(cover, off, 64);
+        if constexpr (CNT) {
+#pragma unroll
+            for (int c = 0; c < kMaxCount; ++c)
+                if (c < tab.ncount) cnt[c] += __shfl_xor(cnt[c], off, 64);
+        }
+    }
+    if (lane == 0) {
+        atomicOr((unsigned long long *)&wl.hub_cover[slot], (unsigned long long)cover);
+        if constexpr (CNT) {
+            for (int c = 0; c < tab.ncount; ++c)
+                atomicAdd(&wl.hub_count[slot * kMaxCount + c], cnt[c]);
+        }
+        __threadfence();
+        int t = atomicAdd(&wl.hub_ticket[slot], 1);
+        if (t == wl.hub_nseg[slot] - 1) {
+            __threadfence();
+            uint64_t cov = atomicOr((unsigned long long *)&wl.hub_cover[slot], 0ull);
+            int tot[CNT ? kMaxCount : 1];
+            if constexpr (CNT) {
+#pragma unroll
+                for (int c = 0; c < kMaxCount; ++c)
+                    tot[c] = c < tab.ncount ? atomicAdd(&wl.hub_count[slot * kMaxCount + c], 0) : 0;
+            }
+            const uint64_t w = (uint64_t)omega[v];
+            const uint64_t nw = evaluate<CNT>(w, cov, tot, tab);
+            wl.hub_cover[slot] = 0;
+            wl.hub_ticket[slot] = 0;
+            if constexpr (CNT) {
+                for (int c = 0; c < tab.ncount; ++c) wl.hub_count[slot * kMaxCount + c] = 0;
+            }
+            if (nw != w) {
+                omega[v] = (M)nw;
+                atomicAdd(changed, 1);
+            }
+        }
+    }
+}
+
+template <typename M, bool CNT>
+static void sweep_impl(hipStream_t s, const int64_t *rp, const int32_t *col, M *omega,
+                       const Worklists &wl, const int64_t *hc, int64_t n_seg,
+                       const LccTable &tab, int32_t *changed) {
+    if (hc[0] > 0)
+        hipLaunchKernelGGL((lcc_group_kernel<M, 4, CNT>),
+                           dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           rp, col, omega, wl.list[0], hc[0], tab, changed);
+    if (hc[1] > 0)
+        hipLaunchKernelGGL((lcc_group_kernel<M, 16, CNT>),
+                           dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl.list[1], hc[1], tab, changed);
+    if (hc[2] > 0)
+        hipLaunchKernelGGL((lcc_group_kernel<M, 64, CNT>),
+                           dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl.list[2], hc[2], tab, changed);
+    if (n_seg > 0)
+        hipLaunchKernelGGL((lcc_hub_kernel<M, CNT>),
+                           dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl, n_seg, tab, changed);
+}
+
+template <typename M>
+void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *omega,
+                      const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
+                      const LccTable &tab, int32_t *changed) {
+    if (tab.ncount > 0)
+        sweep_impl<M, true>(s, rp, col, omega, wl, host_counts, n_seg, tab, changed);
+    else
+        sweep_impl<M, false>(s, rp, col, omega, wl, host_counts, n_seg, tab, changed);
+}
+
+// ---------------------------------------------------- subgraph compaction
+// Entry u->w is kept iff omega(w) meets the roles adjacent to omega(u): the
+// edge elimination of the LCC description (edges to eliminated neighbours
+// and to neighbours of non-adjacent roles are dropped).
+template <typename M, int G>
+__global__ __launch_bounds__(kBlock) void compact_count_group(const int64_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ col,
+                                                              const M *__restrict__ omega,
+                                                              const int32_t *__restrict__ list,
+                                                              int64_t count, LccTable tab,
+                                                              int64_t *deg_out) {
+    const int sl = lane_id() & (G - 1);
+    const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const bool valid = idx < count;
+    const int32_t v = valid ? list[idx] : 0;
+    const uint64_t w = valid ? (uint64_t)omega[v] : 0ull;
+    const uint64_t reach = reach_of<M>(w, tab);
+    int64_t s = 0, e = 0;
+    if (reach) {
+        s = rp[v];
+        e = rp[v + 1];
+    }
+    int c = 0;
+    for (int64_t k = s + sl; k < e; k += G) c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, G);
+    if (valid && sl == 0) deg_out[v] = c;
+}
+
+template <typename M>
+__global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            const M *__restrict__ omega,
+                                                            Worklists wl, int64_t n_seg,
+                                                            LccTable tab, int64_t *deg_out,
+                                                            int64_t *seg_count) {
+    const int lane = lane_id();
+    const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (seg >= n_seg) return;
+    const int32_t v = wl.hub_seg_v[seg];
+    const uint64_t reach = reach_of<M>((uint64_t)omega[v], tab);
+    int c = 0;
+    if (reach)
+        for (int64_t k = wl.hub_seg_begin[seg] + lane; k < wl.hub_seg_end[seg]; k += kWave)
+            c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) {
+        seg_count[seg] = c;
+        atomicAdd((unsigned long long *)&deg_out[v], (unsigned long long)c);
+    }
+}
+
+template <typename M, int G>
+__global__ __launch_bounds__(kBlock) void compact_fill_group(
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
+    const int32_t *__restrict__ list, int64_t count, LccTable tab, const int64_t *__restrict__ c_rp,
+    int32_t *c_col, int32_t *c_off) {
+    const int lane = lane_id();
+    const int sl = lane & (G - 1);
+    const int sub_shift = lane & ~(G - 1);
+    const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const bool valid = idx < count;
+    const int32_t v = valid ? list[idx] : 0;
+    const uint64_t w = valid ? (uint64_t)omega[v] : 0ull;
+    const uint64_t reach = reach_of<M>(w, tab);
+    int64_t s = 0, e = 0, pos = 0;
+    if (reach) {
+        s = rp[v];
+        e = rp[v + 1];
+        pos = c_rp[v];
+    }
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << sub_shift);
+    // every lane of the wavefront runs the same number of iterations so the
+    // ballots stay convergent
+    int64_t my_iters = (e - s + G - 1) / G;
+    int64_t iters = my_iters;
+    for (int off = 32; off > 0; off >>= 1) {
+        int64_t o = __shfl_xor(iters, off, 64);
+        iters = o > iters ? o : iters;
+    }
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t k = s + it * G + sl;
+        bool keep = false;
+        int32_t x = 0;
+        if (k < e) {
+            x = col[k];
+            keep = ((uint64_t)omega[x] & reach) != 0ull;
+        }
+        const uint64_t m = ballot64(keep) & gmask;
+        if (keep) {
+            const int64_t p = pos + __popcll(m & lanemask_lt());
+            c_col[p] = x;
+            c_off[p] = (int32_t)(k - s);
+        }
+        pos += __popcll(m);
+    }
+}
+
+template <typename M>
+__global__ __launch_bounds__(kBlock) void compact_fill_hub(
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
+    Worklists wl, int64_t n_seg, LccTable tab, const int64_t *__restrict__ c_rp,
+    const int64_t *__restrict__ seg_count, int32_t *c_col, int32_t *c_off) {
+    const int lane = lane_id();
+    const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (seg >= n_seg) return;
+    const int32_t v = wl.hub_seg_v[seg];
+    const int32_t slot = wl.hub_seg_slot[seg];
+    const uint64_t reach = reach_of<M>((uint64_t)omega[v], tab);
+    if (!reach) return;
+    int64_t pos = c_rp[v];
+    for (int64_t j = wl.hub_seg_first[slot]; j < seg; ++j) pos += seg_count[j];
+    const int64_t row0 = rp[v];
+    const int64_t b = wl.hub_seg_begin[seg], e = wl.hub_seg_end[seg];
+    for (int64_t base = b; base < e; base += kWave) {
+        const int64_t k = base + lane;
+        bool keep = false;
+        int32_t x = 0;
+        if (k < e) {
+            x = col[k];
+            keep = ((uint64_t)omega[x] & reach) != 0ull;
+        }
+        const uint64_t m = ballot64(keep);
+        if (keep) {
+            const int64_t p = pos + __popcll(m & lanemask_lt());
+            c_col[p] = x;
+            c_off[p] = (int32_t)(k - row0);
+        }
+        pos += __popcll(m);
+    }
+}
+
+template <typename M>
+void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
+                          const Worklists &wl, const int64_t *hc, int64_t n_seg,
+                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count) {
+    if (hc[0] > 0)
+        hipLaunchKernelGGL((compact_count_group<M, 4>),
+                           dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           rp, col, omega, wl.list[0], hc[0], tab, deg_out);
+    if (hc[1] > 0)
+        hipLaunchKernelGGL((compact_count_group<M, 16>),
+                           dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl.list[1], hc[1], tab, deg_out);
+    if (hc[2] > 0)
+        hipLaunchKernelGGL((compact_count_group<M, 64>),
+                           dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl.list[2], hc[2], tab, deg_out);
+    if (n_seg > 0)
+        hipLaunchKernelGGL((compact_count_hub<M>),
+                           dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl, n_seg, tab, deg_out, seg_count);
+}
+
+template <typename M>
+void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
+                         const Worklists &wl, const int64_t *hc, int64_t n_seg,
+                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_count,
+                         int32_t *c_col, int32_t *c_off) {
+    if (hc[0] > 0)
+        hipLaunchKernelGGL((compact_fill_group<M, 4>),
+                           dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           rp, col, omega, wl.list[0], hc[0], tab, c_rp, c_col, c_off);
+    if (hc[1] > 0)
+        hipLaunchKernelGGL((compact_fill_group<M, 16>),
+                           dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl.list[1], hc[1], tab, c_rp, c_col, c_off);
+    if (hc[2] > 0)
+        hipLaunchKernelGGL((compact_fill_group<M, 64>),
+                           dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl.list[2], hc[2], tab, c_rp, c_col, c_off);
+    if (n_seg > 0)
+        hipLaunchKernelGGL((compact_fill_hub<M>),
+                           dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, rp, col, omega, wl, n_seg, tab, c_rp, seg_count, c_col, c_off);
+}
+
+// --------------------------------------------------------- exclusive scan
+// out[i] = in[0] + ... + in[i-1] for i in [0, n]; three passes over tiles of
+// kScanTile elements.
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__global__ __launch_bounds__(kBlock) void scan_tile_sums(const int64_t *in, int64_t n,
+                                                         int64_t *sums) {
+    __shared__ int64_t red[kBlock / kWave];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t acc = 0;
+    for (int j = 0; j < kScanPer; ++j) {
+        int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t *sums, int64_t nb, int64_t *total) {
+    __shared__ int64_t sc[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        int64_t i = base + threadIdx.x;
+        int64_t x = i < nb ? sums[i] : 0;
+        sc[threadIdx.x] = x;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int64_t t = threadIdx.x >= (unsigned)off ? sc[threadIdx.x - off] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) sums[i] = carry + sc[threadIdx.x] - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sc[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_apply(const int64_t *in, int64_t n,
+                                                     const int64_t *sums, int64_t *out) {
+    __shared__ int64_t ts[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int64_t v[kScanPer];
+    int64_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        int64_t i = base + j;
+        v[j] = i < n ? in[i] : 0;
+        acc += v[j];
+    }
+    ts[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int64_t t = threadIdx.x >= (unsigned)off ? ts[threadIdx.x - off] : 0;
+        __syncthreads();
+        ts[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t run = sums[blockIdx.x] + ts[threadIdx.x] - acc;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+void launch_exclusive_scan(hipStream_t s, const int64_t *in, int64_t *out, int64_t n,
+                           int64_t *scratch, int64_t) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, scratch, nb, out + n);
+    hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch, out);
+}
+
+int64_t scan_scratch_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+// ---------------------------------------------------------------- fills
+__global__ void fill_u64_kernel(uint64_t *p, int64_t n, uint64_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t n, uint64_t v) {
+    if (n <= 0) return;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)g), dim3(kBlock), 0, s, p, n, v);
+}
+void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v) {
+    if (n <= 0) return;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)g), dim3(kBlock), 0, s, p, n, v);
+}
+
+__global__ void label_hist_kernel(int64_t n, const void *labels, int label_bytes,
+                                  unsigned long long *hist, int64_t hist_len) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t L = label_bytes == 1 ? (int64_t)((const uint8_t *)labels)[v]
+                                     : (int64_t)((const uint16_t *)labels)[v];
+        if (L < hist_len) atomicAdd(&hist[L], 1ull);
+    }
+}
+
+void launch_label_hist(hipStream_t s, int64_t n, const void *labels, int label_bytes,
+                       unsigned long long *hist, int64_t hist_len) {
+    if (n <= 0) return;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(label_hist_kernel, dim3((unsigned)g), dim3(kBlock), 0, s, n, labels,
+                       label_bytes, hist, hist_len);
+}
+
+template <typename M>
+__global__ void widen_kernel(int64_t n, const M *src, uint64_t *dst) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        dst[v] = (uint64_t)src[v];
+}
+
+template <typename M>
+void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
+    if (n <= 0) return;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(widen_kernel<M>, dim3((unsigned)g), dim3(kBlock), 0, s, n, src, dst);
+}
+
+#define PM_INSTANTIATE_LCC(M)                                                                     \
+    template void launch_init_roles<M>(hipStream_t, int64_t, const void *, int, const uint64_t *, \
+                                       int64_t, M *);                                             \
+    template void launch_bin<M>(hipStream_t, const int32_t *, int64_t, const int64_t *,            \
+                                const M *, Worklists &);                                          \
+    template void launch_lcc_sweep<M>(hipStream_t, const int64_t *, const int32_t *, M *,          \
+                                      const Worklists &, const int64_t *, int64_t,                \
+                                      const LccTable &, int32_t *);                               \
+    template void launch_compact_count<M>(hipStream_t, const int64_t *, const int32_t *,           \
+                                          const M *, const Worklists &, const int64_t *, int64_t, \
+                                          const LccTable &, int64_t *, int64_t *);                \
+    template void launch_compact_fill<M>(hipStream_t, const int64_t *, const int32_t *, const M *, \
+                                         const Worklists &, const int64_t *, int64_t,             \
+                                         const LccTable &, const int64_t *, const int64_t *,      \
+                                         int32_t *, int32_t *);                                   \
+    template void launch_widen<M>(hipStream_t, int64_t, const M *, uint64_t *);                  \
+    template void launch_collect<M>(hipStream_t, const int32_t *, int64_t, const M *, int32_t *,  \
+                                    int32_t *);
+
+PM_INSTANTIATE_LCC(uint8_t)
+PM_INSTANTIATE_LCC(uint16_t)
+PM_INSTANTIATE_LCC(uint32_t)
+PM_INSTANTIATE_LCC(uint64_t)
+
+}  // namespace pm

@@ -1,0 +1,211 @@
+// Internal declarations shared by the host engine and the HIP kernels of
+// libpm.  Nothing here is part of the public ABI (include/pm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace pm {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kMaxK = 64;            // template vertices
+constexpr int kMaxCount = 32;        // distinct-count rules per template
+
+// Degree bins of the LCC sweep: lanes cooperating on one vertex.
+constexpr int kBinSmallMaxDeg = 8;   // 4 lanes per vertex
+constexpr int kBinMidMaxDeg = 64;    // 16 lanes per vertex
+constexpr int kBinWaveMaxDeg = 4096; // one wavefront per vertex
+constexpr int kHubSegment = 4096;    // entries per wavefront for larger vertices
+constexpr int kNumBins = 4;          // small, mid, wave, hub
+
+// Local-rule tables of one template (LCC algorithm; distinct-count rule of
+// the LCC description).  Passed by value as a kernel argument.
+struct LccTable {
+    int32_t n0;
+    int32_t ncount;
+    uint64_t adj[kMaxK];            // adj(q)
+    uint64_t cmask[kMaxCount];      // adj(q) restricted to one label L
+    int32_t cq[kMaxCount];          // q of the rule
+    int32_t cneed[kMaxCount];       // |cmask| >= 2
+};
+
+// One search plan: an ordered walk over a substructure of G0 whose first
+// npin positions are pinned (the head vertex, or both ends of an edge).
+struct SearchPlan {
+    int32_t k;                      // substructure vertices
+    int32_t npin;                   // 1 or 2
+    int32_t q[kMaxK];               // template vertex at each position
+    uint64_t back[kMaxK];           // earlier positions adjacent in the substructure
+    uint64_t same[kMaxK];           // earlier positions with the same label
+    uint64_t certify;               // roles certified by a successful search
+};
+
+// A template-edge pair of plan positions, used to certify witness edges.
+struct PlanEdge {
+    int32_t pa, pb;
+};
+
+// Compiled non-local constraint.
+struct Constraint {
+    int32_t kind;                   // 0 CC, 1 PC, 2 TDS_CC, 3 TDS_PC
+    int32_t gen_index;
+    uint64_t vmask;                 // substructure vertices
+    uint64_t heads;                 // head roles (token sources)
+    std::vector<std::pair<int, int>> edges;   // sorted (a < b)
+    int32_t plan_base;              // index of the plan of its first head
+    int32_t plan_of_head[kMaxK];    // -1 if not a head
+};
+
+struct CompiledTemplate {
+    int32_t n0 = 0, m0 = 0;
+    std::vector<int32_t> labels;
+    std::vector<std::pair<int, int>> edges;
+    int mask_bytes = 1;             // 1, 2, 4 or 8
+    bool acyclic_unique = false;    // LCC alone is exact
+    LccTable lcc{};
+    std::vector<Constraint> constraints;     // generation order
+    std::vector<SearchPlan> plans;            // all plans of this template
+    int32_t vertex_plan[kMaxK];               // full template, pinned at q
+    std::vector<int32_t> edge_plans;          // 2*m0 plans: (a->b), (b->a)
+    std::vector<PlanEdge> plan_edges;         // per plan: m0 position pairs
+    uint64_t label_mask_of[kMaxK];            // roles sharing q's label
+    // device copies
+    SearchPlan *d_plans = nullptr;
+    PlanEdge *d_plan_edges = nullptr;         // [plans][m0]
+    uint64_t *d_init_lut = nullptr;           // label -> initial roles
+    int64_t init_lut_len = 0;
+};
+
+// Template compiler (host).  Returns an empty string on success, otherwise
+// the error message.  label_freq[L] is the number of background vertices of
+// label L (may be empty), used only to order search positions.
+std::string compile_template(int n0, int m0, const uint16_t *labels, const uint32_t *edges,
+                             const std::vector<int64_t> &label_freq, CompiledTemplate &out);
+
+// ---- kernel launchers (explicitly instantiated for M = uint8_t, uint16_t,
+// uint32_t, uint64_t) ---------------------------------------------------------
+struct Worklists {
+    int32_t *list[kNumBins];        // vertex ids per degree bin
+    int32_t *count;                 // [kNumBins] device counters
+    int32_t *hub_seg_v;             // hub segments: vertex
+    int64_t *hub_seg_begin;         // segment [begin, end)
+    int64_t *hub_seg_end;
+    int32_t *hub_seg_slot;          // accumulator slot of the vertex
+    int32_t *hub_nseg;              // [n_hubs] segments per hub slot
+    int32_t *hub_seg_first;         // [n_hubs] index of the slot's first segment
+    uint64_t *hub_cover;            // [n_hubs]
+    int32_t *hub_count;             // [n_hubs][kMaxCount]
+    int32_t *hub_ticket;            // [n_hubs]
+    int32_t *n_seg;                 // device scalar
+    unsigned long long *entries;    // device scalar: CSR entries of binned vertices
+    int64_t capacity;               // per list
+    int64_t hub_capacity;           // hub slots
+    int64_t seg_capacity;
+};
+
+template <typename M>
+void launch_init_roles(hipStream_t s, int64_t n, const void *labels, int label_bytes,
+                       const uint64_t *lut, int64_t lut_len, M *omega);
+
+// Active list: vertices of `in` (or 0..n_in-1 when in == nullptr) whose role
+// set is not empty, appended to out via *counter (zeroed by the caller).
+template <typename M>
+void launch_collect(hipStream_t s, const int32_t *in, int64_t n_in, const M *omega,
+                    int32_t *out, int32_t *counter);
+
+// Bin the vertices of `in` (or 0..n-1 when in == nullptr) with omega != 0 by
+// their degree in the CSR rp; counts go to wl.count (zeroed by the caller).
+template <typename M>
+void launch_bin(hipStream_t s, const int32_t *in, int64_t n_in, const int64_t *rp,
+                const M *omega, Worklists &wl);
+
+void launch_hub_segments(hipStream_t s, const int64_t *rp, Worklists &wl, int64_t n_hubs);
+
+// One LCC sweep over the binned vertices; changed (device int) is
+// incremented once per wavefront that shrank at least one role set.
+template <typename M>
+void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *omega,
+                      const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
+                      const LccTable &tab, int32_t *changed);
+
+// Candidate-subgraph compaction: keep the entries u->w of active u whose
+// roles are adjacent (edge elimination).  Count pass writes deg_out[v] for
+// binned v (deg_out must be zeroed; hubs accumulate per segment into
+// seg_count), then an exclusive scan gives c_rp (n+1), then the fill pass
+// writes c_col and c_off (offset of the entry within the original row).
+template <typename M>
+void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
+                          const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
+                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count);
+void launch_exclusive_scan(hipStream_t s, const int64_t *in, int64_t *out, int64_t n,
+                           int64_t *scratch, int64_t scratch_len);
+int64_t scan_scratch_len(int64_t n);
+template <typename M>
+void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
+                         const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
+                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_count,
+                         int32_t *c_col, int32_t *c_off);
+
+// Vertex-rooted searches.  mode 0: NLCC (certify head roles into sat);
+// mode 1: exact step (certify all roles into sat and edges into edge_bits).
+struct SearchArgs {
+    const int64_t *c_rp;
+    const int32_t *c_col;
+    const int32_t *c_off;
+    const int64_t *rp;              // original CSR (edge bit indices)
+    const int32_t *col;
+    const SearchPlan *plans;
+    const PlanEdge *plan_edges;
+    int32_t m0;
+    int32_t mode;
+    uint64_t heads;
+    int32_t plan_of_head[kMaxK];
+    uint64_t *edge_bits;
+    int32_t *task_counter;
+    unsigned long long *n_queries;
+};
+
+template <typename M>
+void launch_vertex_search(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,
+                          M *sat, const SearchArgs &a, int grid);
+
+// NLCC application: omega &= ~heads | sat; sat cleared; changed counter.
+template <typename M>
+void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega, M *sat,
+                  uint64_t heads, int32_t *changed);
+
+// Exact step, edge part: candidate edges u < w of the compacted subgraph
+// with adjacent certified roles and no certified bit yet.
+template <typename M>
+void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
+                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
+                            const int64_t *rp, const M *cert, const LccTable &tab,
+                            const uint64_t *edge_bits, int32_t *eu, int32_t *ew,
+                            int64_t *e_idx, int32_t *n_out, int64_t cap);
+
+template <typename M>
+void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
+                        const int64_t *e_idx, int64_t n_edges, const M *omega, M *cert,
+                        const int32_t *edge_plan_dev, int32_t n_edge_plans, const SearchArgs &a,
+                        int grid);
+
+// Edge state implied by omega (acyclic unique-label templates and
+// intermediate outputs): sets the bits of active entries, both directions.
+template <typename M>
+void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
+                         const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
+                         const int64_t *rp, const M *omega, const LccTable &tab,
+                         uint64_t *edge_bits);
+
+template <typename M>
+void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst);
+
+void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t n, uint64_t v);
+void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
+void launch_label_hist(hipStream_t s, int64_t n, const void *labels, int label_bytes,
+                       unsigned long long *hist, int64_t hist_len);
+
+}  // namespace pm

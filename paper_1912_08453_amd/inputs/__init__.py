@@ -241,12 +241,107 @@ def _degrees(n0: int, edges) -> List[int]:
 CFG2_EDGES = [(0, 1), (1, 2), (0, 2), (1, 3), (3, 4), (4, 0), (3, 5)]
 
 
-def template_cfg2(label_hist: np.ndarray, seed: int) -> Template:
+def template_cfg2(graph: "Graph", seed: int) -> Template:
     """Triangle (q0,q1,q2) and 4-cycle (q0,q1,q3,q4) sharing edge q0-q1, a
-    pendant q5 on q3, and the repeated label l(q5) = l(q2)."""
+    pendant q5 on q3, and the repeated label l(q5) = l(q2); the labels are
+    those of an occurrence of this shape found from a seeded random start
+    vertex, so the template has at least one match."""
+    return extract_template(graph, 6, CFG2_EDGES, seed, repeat_pairs=[(2, 5)],
+                            name=f"tri+sq+pendant/s{seed}")
+
+
+def frequent_labels(labels: np.ndarray, frac: float = 0.01) -> List[int]:
+    """Labels carried by at least `frac` of the non-isolated vertices (label 0
+    is the isolated class of degree labels).  The paper's R-MAT templates use
+    labels among the most frequent in the graph."""
+    h = label_histogram(labels)
+    nz = int(h[1:].sum())
+    return [L for L in range(1, h.shape[0]) if h[L] >= frac * nz]
+
+
+def extract_template(graph: "Graph", n0: int, edges, seed: int, repeat_pairs=(),
+                     allowed_labels=None, name: str = "", max_attempts: int = 20000,
+                     fanout: int = 24, budget: int = 4000) -> Template:
+    """Labels for a template shape taken from one occurrence of the shape in
+    the background graph (query generation by seeded random search, as is
+    usual for subgraph-matching workloads).  Vertices in repeat_pairs share a
+    label; all other template vertices get pairwise distinct labels.
+
+    The search proposes, from a random start vertex, images for the shape's
+    vertices in breadth-first order, each among a random sample of at most
+    `fanout` neighbours of its parent's image, checking injectivity, the
+    shape's other edges and the label pattern; it gives up on a start after
+    `budget` proposals.  If allowed_labels is given, only vertices with those
+    labels are used."""
     rng = np.random.Generator(np.random.Philox(seed))
-    labels = draw_labels(rng, _degrees(6, CFG2_EDGES), label_hist, repeat_pairs=[(2, 5)])
-    return Template(labels, list(CFG2_EDGES), f"tri+sq+pendant/s{seed}")
+    rp, col, lab = graph.row_ptr, graph.col, graph.labels
+    ok_lab = np.ones(int(lab.max()) + 1 if lab.size else 1, dtype=bool)
+    if allowed_labels is not None:
+        ok_lab[:] = False
+        ok_lab[list(allowed_labels)] = True
+    adj = [[] for _ in range(n0)]
+    for a, b in edges:
+        adj[a].append(b); adj[b].append(a)
+    tdeg = [len(x) for x in adj]
+    order, parent = [0], {0: -1}
+    for x in order:
+        for y in sorted(adj[x]):
+            if y not in parent:
+                parent[y] = x; order.append(y)
+    pos = {q: i for i, q in enumerate(order)}
+    same = {}
+    for a, b in repeat_pairs:
+        same.setdefault(a, set()).add(b); same.setdefault(b, set()).add(a)
+    deg = np.diff(rp)
+    starts = np.nonzero((deg >= tdeg[0]) & ok_lab[lab])[0]
+    if starts.shape[0] == 0:
+        raise ValueError("no start vertex of sufficient degree")
+
+    def has_edge(u, w):
+        row = col[rp[u]:rp[u + 1]]
+        i = np.searchsorted(row, w)
+        return i < row.shape[0] and row[i] == w
+
+    for _ in range(max_attempts):
+        img = {0: int(starts[rng.integers(0, starts.shape[0])])}
+        work = [0]
+
+        def extend(i):
+            if i == n0:
+                return True
+            q = order[i]
+            p = img[parent[q]]
+            row = col[rp[p]:rp[p + 1]]
+            if row.shape[0] > fanout:
+                row = row[rng.choice(row.shape[0], size=fanout, replace=False)]
+            else:
+                row = row[rng.permutation(row.shape[0])]
+            used = set(img.values())
+            for x in row.tolist():
+                work[0] += 1
+                if work[0] > budget:
+                    return False
+                if x in used or deg[x] < tdeg[q] or not ok_lab[lab[x]]:
+                    continue
+                ok = True
+                for r, v in img.items():
+                    if r in adj[q] and r != parent[q] and not has_edge(x, v):
+                        ok = False; break
+                    eq = lab[x] == lab[v]
+                    if (r in same.get(q, ())) != eq:
+                        ok = False; break
+                if not ok:
+                    continue
+                img[q] = x
+                if extend(i + 1):
+                    return True
+                del img[q]
+            return False
+
+        if extend(1):
+            labels = [int(lab[img[q]]) for q in range(n0)]
+            return Template(labels, [tuple(e) for e in edges], name)
+    raise RuntimeError("no occurrence found for template shape")
 
 
 def _prufer_tree(rng, n0):
@@ -369,10 +464,10 @@ def _all_pairs_hops(n0, edges):
     return dist
 
 
-def templates_batch(label_hist: np.ndarray, seed: int, count: int = 64) -> List[Template]:
+def templates_batch(graph: "Graph", seed: int, count: int = 64) -> List[Template]:
     """Mixed batch: 1/4 paths/trees, 3/8 one cycle, 1/4 two cycles, 1/8
     4-cliques (16/24/16/8 of 64), 3..8 vertices, ~20% with one repeated-label
-    pair."""
+    pair (at least 2 hops apart); labels from an occurrence in the graph."""
     rng = np.random.Generator(np.random.Philox(seed))
     kinds = (["tree"] * (count // 4) + ["one"] * (3 * count // 8) + ["two"] * (count // 4))
     kinds += ["k4"] * (count - len(kinds))
@@ -380,36 +475,50 @@ def templates_batch(label_hist: np.ndarray, seed: int, count: int = 64) -> List[
     rep_idx = set(int(x) for x in rng.choice(count, size=n_rep, replace=False))
     out = []
     for i, kind in enumerate(kinds):
-        if kind == "tree":
-            n0 = int(rng.integers(3, 9)); edges = shape_tree(rng, n0)
-        elif kind == "one":
-            n0 = int(rng.integers(3, 9)); edges = shape_one_cycle(rng, n0)
-        elif kind == "two":
-            n0 = int(rng.integers(5, 9)); edges = shape_two_cycles(rng, n0)
+        for attempt in range(50):
+            if kind == "tree":
+                n0 = int(rng.integers(3, 9)); edges = shape_tree(rng, n0)
+            elif kind == "one":
+                n0 = int(rng.integers(3, 9)); edges = shape_one_cycle(rng, n0)
+            elif kind == "two":
+                n0 = int(rng.integers(5, 9)); edges = shape_two_cycles(rng, n0)
+            else:
+                n0 = int(rng.integers(4, 9)); edges = shape_k4(rng, n0)
+            rep = _repeat_pair(rng, n0, edges, 2) if i in rep_idx else []
+            try:
+                t = extract_template(graph, n0, edges, int(rng.integers(0, 2 ** 62)),
+                                     repeat_pairs=rep, name=f"{kind}{n0}/{i}",
+                                     max_attempts=400)
+            except RuntimeError:
+                continue
+            out.append(t)
+            break
         else:
-            n0 = int(rng.integers(4, 9)); edges = shape_k4(rng, n0)
-        rep = _repeat_pair(rng, n0, edges, 2) if i in rep_idx else []
-        labels = draw_labels(rng, _degrees(n0, edges), label_hist, repeat_pairs=rep)
-        out.append(Template(labels, edges, f"{kind}{n0}/{i}"))
+            raise RuntimeError(f"could not draw template {i} ({kind})")
     return out
 
 
-def templates_multicycle(label_hist: np.ndarray, seed: int, count: int = 64) -> List[Template]:
-    """7-8 vertex templates with cyclomatic number >= 2."""
+def templates_multicycle(graph: "Graph", seed: int, count: int = 64) -> List[Template]:
+    """7-8 vertex templates with cyclomatic number >= 2, labels from an
+    occurrence in the graph; about 30% carry one repeated-label pair."""
     rng = np.random.Generator(np.random.Philox(seed))
     out = []
     while len(out) < count:
         n0 = int(rng.integers(7, 9))
         edges = shape_two_cycles(rng, n0)
-        if len(edges) - n0 + 1 < 2:
-            continue
         if rng.random() < 0.5:
-            # extra chord to raise the cyclomatic number
             a, b = (int(x) for x in rng.choice(n0, size=2, replace=False))
             edges = _norm_edges(edges + [(a, b)])
+        if len(edges) - n0 + 1 < 2:
+            continue
         rep = _repeat_pair(rng, n0, edges, 2) if rng.random() < 0.3 else []
-        labels = draw_labels(rng, _degrees(n0, edges), label_hist, repeat_pairs=rep)
-        out.append(Template(labels, edges, f"mc{n0}/{len(out)}"))
+        try:
+            t = extract_template(graph, n0, edges, int(rng.integers(0, 2 ** 62)),
+                                 repeat_pairs=rep, name=f"mc{n0}/{len(out)}",
+                                 max_attempts=400)
+        except RuntimeError:
+            continue
+        out.append(t)
     return out
 
 

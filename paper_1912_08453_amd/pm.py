@@ -1,0 +1,261 @@
+"""Python binding of libpm (argument marshalling only).
+
+Every step of the pruning runs in libpm's HIP kernels; this module only
+turns torch tensors into device pointers, fills the option and template
+structs and checks status codes.  PyTorch provides device memory and the
+stream.  There is no fallback: if libpm.so is missing or fails to load, the
+constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpm.so")
+
+PM_OK = 0
+PM_HOST_PTRS = 1
+PM_VALIDATE = 2
+PM_ORDER_FIXED = 0
+PM_ORDER_GIVEN = 1
+MAX_CONSTRAINTS = 64
+
+ERRORS = {
+    -1: "PM_ERR_INVALID_ARG", -2: "PM_ERR_HIP", -3: "PM_ERR_GRAPH", -4: "PM_ERR_TEMPLATE",
+    -5: "PM_ERR_NO_GRAPH", -6: "PM_ERR_CAPACITY", -7: "PM_ERR_OOM", -8: "PM_ERR_NOT_FOUND",
+}
+
+# exported symbols declared in include/pm.h
+SYMBOLS = ["pm_last_error", "pm_version", "pm_create", "pm_destroy", "pm_load_graph",
+           "pm_unload_graph", "pm_load_templates", "pm_template_constraints",
+           "pm_inspect_template", "pm_prune"]
+
+
+class PMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class pm_template(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_uint32), ("m0", ctypes.c_uint32),
+                ("labels", ctypes.POINTER(ctypes.c_uint16)),
+                ("edges", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class pm_options(ctypes.Structure):
+    _fields_ = [("order_mode", ctypes.c_int32), ("n_order", ctypes.c_int32),
+                ("order", ctypes.c_int32 * MAX_CONSTRAINTS), ("stop_after", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class pm_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("ms_total", "ms_init", "ms_lcc", "ms_compact", "ms_nlcc", "ms_exact",
+                 "ms_first_sweep")] + \
+               [(k, ctypes.c_int64) for k in
+                ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
+                 "candidate_entries", "vertex_queries", "edge_queries", "result_vertices")] + \
+               [("reserved", ctypes.c_int64 * 6)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpm.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpm.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.pm_last_error.restype = ctypes.c_char_p
+    lib.pm_version.restype = ctypes.c_char_p
+    lib.pm_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    lib.pm_destroy.argtypes = [P]
+    lib.pm_load_graph.argtypes = [P, I64, I64, P, P, P, ctypes.c_int, ctypes.c_uint32]
+    lib.pm_unload_graph.argtypes = [P]
+    lib.pm_load_templates.argtypes = [P, I32, ctypes.POINTER(pm_template), ctypes.POINTER(I32)]
+    lib.pm_template_constraints.argtypes = [P, I32, ctypes.POINTER(I32), P, P, P, P]
+    lib.pm_inspect_template.argtypes = [ctypes.POINTER(pm_template), ctypes.POINTER(I32), P, P,
+                                        P, P]
+    lib.pm_prune.argtypes = [P, I32, I32, P, P, ctypes.POINTER(pm_options),
+                             ctypes.POINTER(pm_stats)]
+    for name in SYMBOLS[2:]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(lib, rc: int):
+    if rc != PM_OK:
+        raise PMError(rc, lib.pm_last_error().decode())
+
+
+class PM:
+    """One libpm context on a CUDA (HIP) device and torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.pm_create(ctypes.byref(h), device,
+                                            ctypes.c_void_p(stream.cuda_stream)))
+        self.h = h
+        self.n = 0
+        self.m = 0
+        self._graph_refs = None
+        self.templates: List = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- graph
+    def load_graph(self, row_ptr, col, labels, validate: bool = False):
+        """row_ptr int64[n+1], col int32[m], labels uint8/int16-as-uint16[n]:
+        torch tensors on the context's device (borrowed), or numpy arrays
+        (copied by the library)."""
+        torch = self.torch
+        flags = PM_VALIDATE if validate else 0
+        if isinstance(row_ptr, np.ndarray):
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            lb = np.ascontiguousarray(labels)
+            lbytes = lb.dtype.itemsize
+            flags |= PM_HOST_PTRS
+            ptrs = [a.ctypes.data if a.size else 0 for a in (rp, cl, lb)]
+            refs = (rp, cl, lb)
+        else:
+            rp, cl, lb = row_ptr, col, labels
+            assert rp.dtype == torch.int64 and cl.dtype == torch.int32
+            assert rp.is_contiguous() and cl.is_contiguous() and lb.is_contiguous()
+            lbytes = lb.element_size()
+            ptrs = [t.data_ptr() for t in (rp, cl, lb)]
+            refs = (rp, cl, lb)
+        n = int(rp.shape[0]) - 1
+        m = int(cl.shape[0])
+        _check(self.lib, self.lib.pm_load_graph(self.h, n, m, ctypes.c_void_p(ptrs[0]),
+                                                ctypes.c_void_p(ptrs[1]), ctypes.c_void_p(ptrs[2]),
+                                                lbytes, flags))
+        self.n, self.m = n, m
+        self._graph_refs = refs if not (flags & PM_HOST_PTRS) else None
+
+    # --------------------------------------------------------- templates
+    def load_templates(self, templates: Sequence) -> int:
+        """templates: objects with .labels (list[int]) and .edges (list of
+        pairs).  Returns the id of the first."""
+        arr = (pm_template * len(templates))()
+        keep = []
+        for i, t in enumerate(templates):
+            lab = np.ascontiguousarray(np.asarray(t.labels, dtype=np.uint16))
+            e = np.ascontiguousarray(np.asarray(t.edges, dtype=np.uint32).reshape(-1))
+            if e.size == 0:
+                e = np.zeros(2, dtype=np.uint32)
+            keep += [lab, e]
+            arr[i].n0 = len(t.labels)
+            arr[i].m0 = len(t.edges)
+            arr[i].labels = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))
+            arr[i].edges = e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        first = ctypes.c_int32()
+        _check(self.lib, self.lib.pm_load_templates(self.h, len(templates), arr,
+                                                    ctypes.byref(first)))
+        self.templates += list(templates)
+        return int(first.value)
+
+    def constraints(self, tid: int):
+        """[(kind, edges tuple, heads mask)] in generation order."""
+        cnt = ctypes.c_int32()
+        kinds = np.zeros(MAX_CONSTRAINTS, np.int32)
+        ne = np.zeros(MAX_CONSTRAINTS, np.int32)
+        heads = np.zeros(MAX_CONSTRAINTS, np.uint64)
+        edges = np.zeros(MAX_CONSTRAINTS * 128, np.uint32)
+        _check(self.lib, self.lib.pm_template_constraints(
+            self.h, tid, ctypes.byref(cnt), kinds.ctypes.data_as(ctypes.c_void_p),
+            ne.ctypes.data_as(ctypes.c_void_p), heads.ctypes.data_as(ctypes.c_void_p),
+            edges.ctypes.data_as(ctypes.c_void_p)))
+        return _unpack_constraints(cnt.value, kinds, ne, heads, edges)
+
+    # ------------------------------------------------------------- prune
+    def prune(self, first_id: int, count: int = 1, order: Optional[Sequence[int]] = None,
+              stop_after: int = -1, role_mask=None, edge_bits=None):
+        """Returns (role_mask uint64-as-int64 tensor [count, n], edge_bits
+        [count, ceil(m/64)], stats dict)."""
+        torch = self.torch
+        words = (self.m + 63) // 64
+        if role_mask is None:
+            role_mask = torch.empty((count, max(self.n, 1)), dtype=torch.int64, device=self.device)
+        if edge_bits is None:
+            edge_bits = torch.empty((count, max(words, 1)), dtype=torch.int64, device=self.device)
+        opt = pm_options()
+        opt.stop_after = stop_after
+        if order is not None:
+            opt.order_mode = PM_ORDER_GIVEN
+            opt.n_order = len(order)
+            for i, k in enumerate(order):
+                opt.order[i] = int(k)
+        st = pm_stats()
+        _check(self.lib, self.lib.pm_prune(self.h, first_id, count,
+                                           ctypes.c_void_p(role_mask.data_ptr()),
+                                           ctypes.c_void_p(edge_bits.data_ptr()),
+                                           ctypes.byref(opt), ctypes.byref(st)))
+        return role_mask[:, :self.n], edge_bits[:, :words], st.as_dict()
+
+
+def _unpack_constraints(cnt, kinds, ne, heads, edges):
+    out = []
+    for i in range(cnt):
+        es = tuple((int(edges[i * 128 + 2 * j]), int(edges[i * 128 + 2 * j + 1]))
+                   for j in range(int(ne[i])))
+        out.append((int(kinds[i]), es, int(heads[i])))
+    return out
+
+
+def inspect_template(t):
+    """Constraint list of a template compiled on the host only (no device):
+    [(kind, edges tuple, heads mask)] in generation order."""
+    lib = load_library()
+    lab = np.ascontiguousarray(np.asarray(t.labels, dtype=np.uint16))
+    e = np.ascontiguousarray(np.asarray(t.edges, dtype=np.uint32).reshape(-1))
+    if e.size == 0:
+        e = np.zeros(2, dtype=np.uint32)
+    tt = pm_template(len(t.labels), len(t.edges),
+                     lab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                     e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    cnt = ctypes.c_int32()
+    kinds = np.zeros(MAX_CONSTRAINTS, np.int32)
+    ne = np.zeros(MAX_CONSTRAINTS, np.int32)
+    heads = np.zeros(MAX_CONSTRAINTS, np.uint64)
+    edges = np.zeros(MAX_CONSTRAINTS * 128, np.uint32)
+    _check(lib, lib.pm_inspect_template(ctypes.byref(tt), ctypes.byref(cnt),
+                                        kinds.ctypes.data_as(ctypes.c_void_p),
+                                        ne.ctypes.data_as(ctypes.c_void_p),
+                                        heads.ctypes.data_as(ctypes.c_void_p),
+                                        edges.ctypes.data_as(ctypes.c_void_p)))
+    return _unpack_constraints(cnt.value, kinds, ne, heads, edges)
+
+
+def to_u64(t) -> np.ndarray:
+    """Device int64 tensor -> host uint64 numpy view."""
+    return t.detach().cpu().numpy().view(np.uint64)
