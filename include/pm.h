@@ -94,7 +94,9 @@ typedef struct {
     double ms_compact;             /* candidate-subgraph compaction           */
     double ms_nlcc;                /* all non-local constraint checks         */
     double ms_exact;               /* final full-template search              */
-    double ms_first_sweep;         /* first LCC sweep over the full graph     */
+    double ms_first_sweep;         /* first LCC sweep over the full graph,
+                                      including its binning                   */
+    double ms_sweep_kernel;        /* the first sweep's kernel alone          */
     int64_t lcc_sweeps;            /* LCC sweeps run                          */
     int64_t constraints;           /* non-local constraints checked           */
     int64_t first_sweep_vertices;  /* active vertices in the first sweep      */

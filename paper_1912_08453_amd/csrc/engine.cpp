@@ -226,9 +226,25 @@ struct Pruner {
             throw Error(PM_ERR_CAPACITY, "hub segment capacity exceeded");
     }
 
-    int32_t sweep(const Graph &g) {
+    int32_t sweep(const Graph &g, bool full = false) {
         PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
-        launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, T.lcc, ctr + C_CHANGED);
+        if (full) {
+            // device time of the sweep kernel alone (the HBM-bound step)
+            hipEvent_t a, b;
+            PM_HIP(hipEventCreate(&a));
+            PM_HIP(hipEventCreate(&b));
+            PM_HIP(hipEventRecord(a, s));
+            launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, T.lcc, ctr + C_CHANGED, true);
+            PM_HIP(hipEventRecord(b, s));
+            PM_HIP(hipEventSynchronize(b));
+            float ms = 0;
+            PM_HIP(hipEventElapsedTime(&ms, a, b));
+            st.ms_sweep_kernel += ms;
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        } else {
+            launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, T.lcc, ctr + C_CHANGED, false);
+        }
         st.lcc_sweeps++;
         return read_ctr(C_CHANGED);
     }
@@ -369,7 +385,7 @@ struct Pruner {
             bin(full);
             st.first_sweep_vertices = nA;
             st.first_sweep_entries = binned_entries;
-            int32_t ch = sweep(full);
+            int32_t ch = sweep(full, true);
             st.ms_first_sweep = t.stop();
             st.ms_lcc += st.ms_first_sweep;
             if (ch) collect(false);
@@ -686,6 +702,7 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.ms_nlcc += st.ms_nlcc;
             total.ms_exact += st.ms_exact;
             total.ms_first_sweep += st.ms_first_sweep;
+            total.ms_sweep_kernel += st.ms_sweep_kernel;
             total.lcc_sweeps += st.lcc_sweeps;
             total.constraints += st.constraints;
             total.first_sweep_vertices += st.first_sweep_vertices;
@@ -693,6 +710,7 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.candidate_entries += st.candidate_entries;
             total.vertex_queries += st.vertex_queries;
             total.edge_queries += st.edge_queries;
+            total.result_vertices += st.result_vertices;
         }
         PM_HIP(hipStreamSynchronize(c->stream));
         if (stats) *stats = total;

@@ -184,17 +184,19 @@ void launch_hub_segments(hipStream_t s, const int64_t *rp, Worklists &wl, int64_
 }
 
 // ------------------------------------------------------------- LCC sweep
-// G lanes per vertex (G = 4, 16, 64) for vertices of the three lower bins.
+// One launch per sweep.  Blocks are assigned to degree bins by blockIdx
+// ranges: G = 4, 16 or 64 lanes per vertex for the three lower bins, one
+// wavefront per segment of kHubSegment entries for the hub bin, whose
+// partial coverage and counts are combined with atomics; the last segment
+// of a vertex (ticket) applies the rule.
 template <typename M, int G, bool CNT>
-__global__ __launch_bounds__(kBlock) void lcc_group_kernel(const int64_t *__restrict__ rp,
-                                                           const int32_t *__restrict__ col,
-                                                           M *omega,
-                                                           const int32_t *__restrict__ list,
-                                                           int64_t count, LccTable tab,
-                                                           int32_t *changed) {
+__device__ __forceinline__ void lcc_group_body(int64_t local_block, const int64_t *__restrict__ rp,
+                                               const int32_t *__restrict__ col, M *omega,
+                                               const int32_t *__restrict__ list, int64_t count,
+                                               const LccTable &tab, int32_t *changed) {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
-    const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t idx = (local_block * blockDim.x + threadIdx.x) / G;
     const bool valid = idx < count;
     const int32_t v = valid ? list[idx] : 0;
     const uint64_t w = valid ? (uint64_t)omega[v] : 0ull;
@@ -236,15 +238,13 @@ __global__ __launch_bounds__(kBlock) void lcc_group_kernel(const int64_t *__rest
     if (ballot64(ch) && lane == 0) atomicAdd(changed, 1);
 }
 
-// One wavefront per hub segment; partial coverage and counts are combined
-// with atomics and the last segment of a vertex (ticket) applies the rule.
 template <typename M, bool CNT>
-__global__ __launch_bounds__(kBlock) void lcc_hub_kernel(const int64_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ col, M *omega,
-                                                         Worklists wl, int64_t n_seg,
-                                                         LccTable tab, int32_t *changed) {
+__device__ __forceinline__ void lcc_hub_body(int64_t local_block, const int64_t *__restrict__ rp,
+                                             const int32_t *__restrict__ col, M *omega,
+                                             const Worklists &wl, int64_t n_seg,
+                                             const LccTable &tab, int32_t *changed) {
     const int lane = lane_id();
-    const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t seg = (local_block * blockDim.x + threadIdx.x) / kWave;
     if (seg >= n_seg) return;
     const int32_t v = wl.hub_seg_v[seg];
     const int32_t slot = wl.hub_seg_slot[seg];
@@ -303,36 +303,66 @@ __global__ __launch_bounds__(kBlock) void lcc_hub_kernel(const int64_t *__restri
     }
 }
 
+struct SweepGrid {
+    int64_t count[3];        // vertices in bins 0..2
+    int64_t n_seg;           // hub segments
+    int64_t start[5];        // first block of each bin; start[4] = total blocks
+};
+
+static SweepGrid sweep_grid(const int64_t *hc, int64_t n_seg) {
+    SweepGrid g{};
+    const int per[4] = {kBlock / 4, kBlock / 16, kBlock / 64, kBlock / 64};
+    int64_t items[4] = {hc[0], hc[1], hc[2], n_seg};
+    g.start[0] = 0;
+    for (int b = 0; b < 4; ++b) g.start[b + 1] = g.start[b] + (items[b] + per[b] - 1) / per[b];
+    for (int b = 0; b < 3; ++b) g.count[b] = hc[b];
+    g.n_seg = n_seg;
+    return g;
+}
+
+// FULL distinguishes the first sweep over the whole graph (its own kernel
+// symbol, so that profiles report it separately) from the sweeps over the
+// compacted candidate subgraph.
+template <typename M, bool CNT, bool FULL>
+__global__ __launch_bounds__(kBlock) void lcc_sweep_kernel(const int64_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           M *omega, Worklists wl, SweepGrid sg,
+                                                           LccTable tab, int32_t *changed) {
+    const int64_t b = blockIdx.x;
+    if (b < sg.start[1])
+        lcc_group_body<M, 4, CNT>(b, rp, col, omega, wl.list[0], sg.count[0], tab, changed);
+    else if (b < sg.start[2])
+        lcc_group_body<M, 16, CNT>(b - sg.start[1], rp, col, omega, wl.list[1], sg.count[1], tab,
+                                   changed);
+    else if (b < sg.start[3])
+        lcc_group_body<M, 64, CNT>(b - sg.start[2], rp, col, omega, wl.list[2], sg.count[2], tab,
+                                   changed);
+    else
+        lcc_hub_body<M, CNT>(b - sg.start[3], rp, col, omega, wl, sg.n_seg, tab, changed);
+}
+
 template <typename M, bool CNT>
 static void sweep_impl(hipStream_t s, const int64_t *rp, const int32_t *col, M *omega,
                        const Worklists &wl, const int64_t *hc, int64_t n_seg,
-                       const LccTable &tab, int32_t *changed) {
-    if (hc[0] > 0)
-        hipLaunchKernelGGL((lcc_group_kernel<M, 4, CNT>),
-                           dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           rp, col, omega, wl.list[0], hc[0], tab, changed);
-    if (hc[1] > 0)
-        hipLaunchKernelGGL((lcc_group_kernel<M, 16, CNT>),
-                           dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[1], hc[1], tab, changed);
-    if (hc[2] > 0)
-        hipLaunchKernelGGL((lcc_group_kernel<M, 64, CNT>),
-                           dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[2], hc[2], tab, changed);
-    if (n_seg > 0)
-        hipLaunchKernelGGL((lcc_hub_kernel<M, CNT>),
-                           dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl, n_seg, tab, changed);
+                       const LccTable &tab, int32_t *changed, bool full) {
+    SweepGrid sg = sweep_grid(hc, n_seg);
+    if (sg.start[4] == 0) return;
+    if (full)
+        hipLaunchKernelGGL((lcc_sweep_kernel<M, CNT, true>), dim3((unsigned)sg.start[4]),
+                           dim3(kBlock), 0, s, rp, col, omega, wl, sg, tab, changed);
+    else
+        hipLaunchKernelGGL((lcc_sweep_kernel<M, CNT, false>), dim3((unsigned)sg.start[4]),
+                           dim3(kBlock), 0, s, rp, col, omega, wl, sg, tab, changed);
 }
 
 template <typename M>
 void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *omega,
                       const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
-                      const LccTable &tab, int32_t *changed) {
+                      const LccTable &tab, int32_t *changed, bool full) {
     if (tab.ncount > 0)
-        sweep_impl<M, true>(s, rp, col, omega, wl, host_counts, n_seg, tab, changed);
+        sweep_impl<M, true>(s, rp, col, omega, wl, host_counts, n_seg, tab, changed, full);
     else
-        sweep_impl<M, false>(s, rp, col, omega, wl, host_counts, n_seg, tab, changed);
+        sweep_impl<M, false>(s, rp, col, omega, wl, host_counts, n_seg, tab, changed, full);
 }
 
 // ---------------------------------------------------- subgraph compaction
@@ -668,7 +698,7 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
                                 const M *, Worklists &);                                          \
     template void launch_lcc_sweep<M>(hipStream_t, const int64_t *, const int32_t *, M *,          \
                                       const Worklists &, const int64_t *, int64_t,                \
-                                      const LccTable &, int32_t *);                               \
+                                      const LccTable &, int32_t *, bool);                         \
     template void launch_compact_count<M>(hipStream_t, const int64_t *, const int32_t *,           \
                                           const M *, const Worklists &, const int64_t *, int64_t, \
                                           const LccTable &, int64_t *, int64_t *);                \

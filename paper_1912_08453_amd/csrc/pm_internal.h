@@ -124,12 +124,14 @@ void launch_bin(hipStream_t s, const int32_t *in, int64_t n_in, const int64_t *r
 
 void launch_hub_segments(hipStream_t s, const int64_t *rp, Worklists &wl, int64_t n_hubs);
 
-// One LCC sweep over the binned vertices; changed (device int) is
-// incremented once per wavefront that shrank at least one role set.
+// One LCC sweep over the binned vertices, one kernel launch; changed
+// (device int) is incremented once per wavefront that shrank at least one
+// role set.  full selects the kernel symbol used for the first sweep over
+// the whole graph.
 template <typename M>
 void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *omega,
                       const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
-                      const LccTable &tab, int32_t *changed);
+                      const LccTable &tab, int32_t *changed, bool full);
 
 // Candidate-subgraph compaction: keep the entries u->w of active u whose
 // roles are adjacent (edge elimination).  Count pass writes deg_out[v] for

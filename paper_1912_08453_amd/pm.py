@@ -56,7 +56,7 @@ class pm_options(ctypes.Structure):
 class pm_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("ms_total", "ms_init", "ms_lcc", "ms_compact", "ms_nlcc", "ms_exact",
-                 "ms_first_sweep")] + \
+                 "ms_first_sweep", "ms_sweep_kernel")] + \
                [(k, ctypes.c_int64) for k in
                 ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
                  "candidate_entries", "vertex_queries", "edge_queries", "result_vertices")] + \
@@ -76,6 +76,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libpm.so not built at {path}; run __graft_entry__.build()")
+    # torch ships its own HIP runtime; loading it first makes libpm bind to
+    # that same runtime (matched by soname), so one process has one runtime
+    # and libpm can use torch's streams and allocations.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.pm_last_error.restype = ctypes.c_char_p

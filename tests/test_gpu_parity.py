@@ -165,13 +165,15 @@ def test_given_orders_same_final_output(pmmod, torch_dev, seed):
 def test_wider_role_masks(pmmod, torch_dev, n0):
     """Templates of 10/20/40 vertices exercise 16/32/64-bit role masks."""
     rng = np.random.Generator(np.random.Philox(n0))
-    g = I.random_graph(300, 0.04, 3, n0)
+    nl = n0 // 2 + 1
+    g = I.random_graph(400, 0.05, nl, n0)
     edges = I.shape_one_cycle(rng, n0)
-    labels = [int(x) for x in rng.integers(0, 3, size=n0)]
+    labels = [q % nl for q in range(n0)]
     t = I.Template(labels, edges)
     ctx = load(pmmod, torch_dev, g)
     tid = ctx.load_templates([t])
     compare(pmmod, ctx, tid, g, t, stop_after=0, what=f"n0={n0} lcc")
+    compare(pmmod, ctx, tid, g, t, what=f"n0={n0} full")
     ctx.close()
 
 
