@@ -103,12 +103,10 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": int(alg_bytes), "ms_per_launch": round(k_ms, 5)}
 
-    phases = {k: round(avg(k), 4) for k in ("ms_total", "ms_init", "ms_lcc", "ms_compact",
-                                              "ms_nlcc", "ms_exact", "ms_first_sweep",
-                                              "ms_sweep_kernel")}
-    counts = {k: stats[-1][k] for k in ("lcc_sweeps", "constraints", "first_sweep_vertices",
-                                         "first_sweep_entries", "candidate_entries",
-                                         "vertex_queries", "edge_queries")}
+    phases = {k: round(avg(k), 4) for k in stats[-1] if k.startswith("ms_")}
+    search = {k: round(avg(k), 3) for k in stats[-1] if k.startswith("wave_ms_")}
+    counts = {k: stats[-1][k] for k in stats[-1]
+              if not k.startswith("ms_") and not k.startswith("wave_ms_")}
     r = pm.to_u64(role[0])
     counts["result_vertices"] = int((r != 0).sum())
     counts["result_entries"] = int(np.unpackbits(pm.to_u64(edge[0]).view(np.uint8)).sum())
@@ -138,6 +136,7 @@ def main():
         "time_to_fixpoint_ms": round(ms_per_step, 4),
         "phases_ms": phases,
         "counts": counts,
+        "search_wave_ms": search,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

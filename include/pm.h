@@ -97,6 +97,10 @@ typedef struct {
     double ms_first_sweep;         /* first LCC sweep over the full graph,
                                       including its binning                   */
     double ms_sweep_kernel;        /* the first sweep's kernel alone          */
+    double wave_ms_vq_pos;         /* summed wavefront time of successful and */
+    double wave_ms_vq_neg;         /* failed vertex-rooted searches, and of   */
+    double wave_ms_eq_pos;         /* successful and failed edge-rooted       */
+    double wave_ms_eq_neg;         /* searches (exact step)                   */
     int64_t lcc_sweeps;            /* LCC sweeps run                          */
     int64_t constraints;           /* non-local constraints checked           */
     int64_t first_sweep_vertices;  /* active vertices in the first sweep      */
@@ -105,6 +109,9 @@ typedef struct {
     int64_t vertex_queries;        /* full-template searches from a vertex    */
     int64_t edge_queries;          /* full-template searches from an edge     */
     int64_t result_vertices;       /* vertices with a non-empty role mask     */
+    int64_t edge_candidates;       /* edges left for edge-rooted searches     */
+    int64_t vq_pos, vq_neg;        /* vertex-rooted searches found / failed   */
+    int64_t eq_pos, eq_neg;        /* edge-rooted searches found / failed     */
     int64_t reserved[6];
 } pm_stats;
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -97,8 +98,10 @@ struct pm_ctx {
     std::vector<std::unique_ptr<CompiledTemplate>> templates;
     // scratch
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
-    DevBuf eu, ew, eidx, edge_plan_ids;
+    DevBuf eu, ew, eidx, edge_plan_ids, crev, ccert, expdone;
     int grid_search = 2048;
+    int expand = 1;
+    int64_t wall_khz = 0;
 };
 
 namespace {
@@ -121,7 +124,7 @@ enum : int {
     C_NOUT = 8,
     C_QUERIES_U64 = 16,   // byte offset 64: unsigned long long
     C_ENTRIES_U64 = 18,   // byte offset 72: unsigned long long
-    C_TOTAL_BYTES = 128,
+    C_TOTAL_BYTES = 256,      // bytes 128..191: query statistics [8]
 };
 
 struct Graph {
@@ -142,6 +145,7 @@ struct Pruner {
     Worklists wl{};
     int32_t *ctr;
     unsigned long long *queries;
+    unsigned long long *qstats;
     int64_t hc[4] = {0, 0, 0, 0};
     int64_t nseg = 0;
     // compacted candidate subgraph
@@ -169,6 +173,7 @@ struct Pruner {
         Aalt = c->alist[1].as<int32_t>();
         ctr = c->counters.as<int32_t>();
         queries = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 64);
+        qstats = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 128);
         for (int b = 0; b < kNumBins; ++b) wl.list[b] = c->bins.as<int32_t>() + (size_t)b * n;
         wl.count = ctr + C_BINS;
         wl.entries = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 72);
@@ -306,6 +311,11 @@ struct Pruner {
         a.edge_bits = edge_bits;
         a.task_counter = ctr + C_TASK;
         a.n_queries = queries;
+        a.c_rev = nullptr;
+        a.c_cert = nullptr;
+        a.exp_done = nullptr;
+        a.qstats = nullptr;
+        a.expand = 0;
         return a;
     }
 
@@ -326,12 +336,27 @@ struct Pruner {
     void exact(uint64_t *role_out, uint64_t *edge_out) {
         Timer t(s);
         const int64_t n = c->n;
-        // cert lives in sat (cleared by every apply and at start)
+        // certified roles live in sat (cleared by every apply and at start)
         const uint64_t all = T.n0 == 64 ? ~0ull : ((1ull << T.n0) - 1ull);
         unsigned long long q0 = 0, q1 = 0;
+        c->crev.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
+        const int64_t cwords = (c_m + 63) / 64;
+        c->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
+        c->expdone.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(n, 1));
+        int32_t *c_rev = c->crev.as<int32_t>();
+        uint64_t *c_cert = c->ccert.as<uint64_t>();
+        launch_reverse_index(s, A, nA, c_rp, c_col, c_rev);
+        launch_fill_u64(s, c_cert, cwords, 0ull);
+        launch_fill_u64(s, c->expdone.as<uint64_t>(), n, 0ull);
+        PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 8, s));
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
         SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
+        a.c_rev = c_rev;
+        a.c_cert = c_cert;
+        a.exp_done = c->expdone.as<uint64_t>();
+        a.qstats = qstats;
+        a.expand = c->expand;
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
         d2h(s, &q0, queries, 1);
         // edge part over vertices with certified roles
@@ -343,11 +368,12 @@ struct Pruner {
         c->ew.ensure(sizeof(int32_t) * (size_t)cap);
         c->eidx.ensure(sizeof(int64_t) * (size_t)cap);
         PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
-        launch_edge_candidates<M>(s, A, nA, c_rp, c_col, c_off, c->rp, sat, T.lcc, edge_out,
+        launch_edge_candidates<M>(s, A, nA, c_rp, c_col, c_rev, sat, T.lcc, c_cert,
                                   c->eu.as<int32_t>(), c->ew.as<int32_t>(),
                                   c->eidx.as<int64_t>(), ctr + C_NOUT, cap);
         int64_t ne = read_ctr(C_NOUT);
         if (ne > cap) throw Error(PM_ERR_CAPACITY, "edge candidate capacity exceeded");
+        st.edge_candidates = ne;
         if (ne > 0) {
             c->edge_plan_ids.ensure(sizeof(int32_t) * std::max<size_t>(T.edge_plans.size(), 1));
             PM_HIP(hipMemcpyAsync(c->edge_plan_ids.p, T.edge_plans.data(),
@@ -360,9 +386,21 @@ struct Pruner {
                                   a, c->grid_search);
             d2h(s, &q1, queries, 1);
         }
+        launch_edges_from_cert(s, A, nA, c_rp, c_off, c_rev, c->rp, c_cert, edge_out);
         launch_widen<M>(s, n, sat, role_out);
+        unsigned long long qs[8];
+        d2h(s, qs, qstats, 8);
+        const double tick_ms = c->wall_khz > 0 ? 1.0 / (double)c->wall_khz : 0.0;
         st.vertex_queries += (int64_t)q0;
         st.edge_queries += (int64_t)q1;
+        st.vq_pos += (int64_t)qs[0];
+        st.vq_neg += (int64_t)qs[1];
+        st.wave_ms_vq_pos += (double)qs[2] * tick_ms;
+        st.wave_ms_vq_neg += (double)qs[3] * tick_ms;
+        st.eq_pos += (int64_t)qs[4];
+        st.eq_neg += (int64_t)qs[5];
+        st.wave_ms_eq_pos += (double)qs[6] * tick_ms;
+        st.wave_ms_eq_neg += (double)qs[7] * tick_ms;
         st.ms_exact += t.stop();
     }
 
@@ -518,6 +556,11 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             hipDeviceProp_t prop;
             PM_HIP(hipGetDeviceProperties(&prop, device));
             c->grid_search = std::max(256, prop.multiProcessorCount * 8);
+            int khz = 0;
+            if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess)
+                c->wall_khz = khz;
+            const char *ex = getenv("PM_EXPAND");
+            if (ex) c->expand = atoi(ex);
         } catch (...) {
             delete c;
             throw;
@@ -534,7 +577,7 @@ int pm_destroy(pm_ctx *c) {
         for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->omega, &c->sat, &c->alist[0],
                           &c->alist[1], &c->bins, &c->counters, &c->hub, &c->cdeg, &c->crp,
                           &c->ccol, &c->coff, &c->segcnt, &c->scan_scratch, &c->eu, &c->ew,
-                          &c->eidx, &c->edge_plan_ids})
+                          &c->eidx, &c->edge_plan_ids, &c->crev, &c->ccert, &c->expdone})
             b->release();
         delete c;
     });
@@ -711,6 +754,15 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.vertex_queries += st.vertex_queries;
             total.edge_queries += st.edge_queries;
             total.result_vertices += st.result_vertices;
+            total.edge_candidates += st.edge_candidates;
+            total.vq_pos += st.vq_pos;
+            total.vq_neg += st.vq_neg;
+            total.eq_pos += st.eq_pos;
+            total.eq_neg += st.eq_neg;
+            total.wave_ms_vq_pos += st.wave_ms_vq_pos;
+            total.wave_ms_vq_neg += st.wave_ms_vq_neg;
+            total.wave_ms_eq_pos += st.wave_ms_eq_pos;
+            total.wave_ms_eq_neg += st.wave_ms_eq_neg;
         }
         PM_HIP(hipStreamSynchronize(c->stream));
         if (stats) *stats = total;

@@ -123,18 +123,27 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
     }
 }
 
-// Certify the roles (and, for full-template plans, the edges) of a found
-// embedding.
+// Certify the head roles of a found embedding (NLCC).
 template <typename M>
-__device__ void certify(const SearchArgs &a, const SearchPlan *__restrict__ P, int plan_idx,
-                        int32_t img_r, M *sat, bool edges) {
+__device__ void certify_roles(const SearchPlan *__restrict__ P, int32_t img_r, M *sat) {
     const int lane = lane_id();
-    const int k = P->k;
-    if (lane < k) {
+    if (lane < P->k) {
         const int q = P->q[lane];
         if ((P->certify >> q) & 1ull) atomic_or_elem<M>(sat, img_r, 1ull << q);
     }
-    if (!edges) return;
+}
+
+__device__ __forceinline__ bool test_bit(const uint64_t *bits, int64_t k) {
+    return (bits[k >> 6] >> (k & 63)) & 1ull;
+}
+
+// Certify a full match: every role, and every template edge as an entry of
+// the compacted subgraph (one direction; the output ORs in the reverse).
+template <typename M>
+__device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict__ P, int plan_idx,
+                              int32_t img_r, M *cert) {
+    const int lane = lane_id();
+    if (lane < P->k) atomic_or_elem<M>(cert, img_r, 1ull << P->q[lane]);
     for (int base = 0; base < a.m0; base += kWave) {
         const int i = base + lane;
         int pa = 0, pb = 0;
@@ -145,10 +154,74 @@ __device__ void certify(const SearchArgs &a, const SearchPlan *__restrict__ P, i
         const int32_t u = __shfl(img_r, pa);
         const int32_t w = __shfl(img_r, pb);
         if (i < a.m0) {
-            const int64_t e1 = find_sorted(a.col, a.rp[u], a.rp[u + 1], w);
-            const int64_t e2 = find_sorted(a.col, a.rp[w], a.rp[w + 1], u);
-            if (e1 >= 0) set_bit(a.edge_bits, e1);
-            if (e2 >= 0) set_bit(a.edge_bits, e2);
+            const int64_t k = find_sorted(a.c_col, a.c_rp[u], a.c_rp[u + 1], w);
+            if (k >= 0) set_bit(a.c_cert, k);
+        }
+    }
+}
+
+// Single-vertex swaps of a found match: for each position i, every x that
+// can replace phi(i) with all other images fixed (role q_i, adjacent to the
+// images of all template neighbours of q_i, distinct from the images of
+// same-label positions) gives another match, whose role (x, q_i) and edges
+// at x are certified.  Purely a saving: anything it misses is queried later.
+template <typename M>
+__device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__ P,
+                             int32_t img_r, const M *__restrict__ om, M *cert) {
+    const int lane = lane_id();
+    const int k = P->k;
+    const int64_t *__restrict__ crp = a.c_rp;
+    const int32_t *__restrict__ ccol = a.c_col;
+    for (int i = 0; i < k; ++i) {
+        const uint64_t nb = P->nbr[i];
+        if (!nb) continue;
+        const int q = P->q[i];
+        int js = -1;
+        int64_t bd = INT64_MAX;
+        for (uint64_t m = nb; m; m &= m - 1) {
+            const int j = __builtin_ctzll(m);
+            const int32_t y = read_lane32(img_r, j);
+            const int64_t d = crp[y + 1] - crp[y];
+            if (d < bd) {
+                bd = d;
+                js = j;
+            }
+        }
+        const int32_t ys = read_lane32(img_r, js);
+        if (__popcll(nb) == 1) {
+            // a pendant position depends (up to identity checks) only on its
+            // neighbour's image: expand it once per (vertex, role)
+            unsigned long long old = 0;
+            if (lane == 0) old = atomicOr((unsigned long long *)&a.exp_done[ys], 1ull << q);
+            old = __shfl(old, 0);
+            if ((old >> q) & 1ull) continue;
+        }
+        const uint64_t others = nb & ~(1ull << js);
+        const uint64_t samel = P->samel[i];
+        const int64_t s = crp[ys], e = crp[ys + 1];
+        for (int64_t base = s; base < e; base += kWave) {
+            const int64_t kk = base + lane;
+            const bool in = kk < e;
+            const int32_t x = in ? ccol[kk] : -1;
+            bool ok = in && (((uint64_t)om[x] >> q) & 1ull);
+            for (uint64_t m = samel; m; m &= m - 1) {
+                const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
+                ok = ok && (x != y);
+            }
+            for (uint64_t m = others; m; m &= m - 1) {
+                const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
+                const int64_t y0 = crp[y], y1 = crp[y + 1];
+                if (ok) ok = find_sorted(ccol, y0, y1, x) >= 0;
+            }
+            if (ok) {
+                atomic_or_elem<M>(cert, x, 1ull << q);
+                set_bit(a.c_cert, kk);
+                for (uint64_t m = others; m; m &= m - 1) {
+                    const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
+                    const int64_t kj = find_sorted(ccol, crp[y], crp[y + 1], x);
+                    if (kj >= 0) set_bit(a.c_cert, kj);
+                }
+            }
         }
     }
 }
@@ -163,7 +236,7 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                                                                      int64_t n_tasks, const M *om,
                                                                      M *sat, SearchArgs a) {
     const int lane = lane_id();
-    unsigned long long queries = 0;
+    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0;
     for (;;) {
         int t0 = 0;
         if (lane == 0) t0 = atomicAdd(a.task_counter, kTaskChunk);
@@ -181,11 +254,33 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                 const SearchPlan *P = a.plans + pidx;
                 int32_t img = 0;
                 ++queries;
-                if (dfs_search<M>(a, P, om, v, -1, img)) certify<M>(a, P, pidx, img, sat, a.mode == 1);
+                const uint64_t c0 = wall_clock64();
+                const bool found = dfs_search<M>(a, P, om, v, -1, img);
+                const uint64_t dt = wall_clock64() - c0;
+                if (found) {
+                    ++npos;
+                    tpos += dt;
+                    if (a.mode == 1) {
+                        certify_match<M>(a, P, pidx, img, sat);
+                        if (a.expand) expand_match<M>(a, P, img, om, sat);
+                    } else {
+                        certify_roles<M>(P, img, sat);
+                    }
+                } else {
+                    tneg += dt;
+                }
             }
         }
     }
-    if (lane == 0 && queries) atomicAdd(a.n_queries, queries);
+    if (lane == 0 && queries) {
+        atomicAdd(a.n_queries, queries);
+        if (a.qstats) {
+            atomicAdd(a.qstats + 0, npos);
+            atomicAdd(a.qstats + 1, queries - npos);
+            atomicAdd(a.qstats + 2, tpos);
+            atomicAdd(a.qstats + 3, tneg);
+        }
+    }
 }
 
 template <typename M>
@@ -234,14 +329,13 @@ __device__ __forceinline__ uint64_t reach_mask(uint64_t w, const LccTable &tab) 
     return r;
 }
 
-// Candidate edges: u < w in the compacted subgraph, certified roles of u and
-// w adjacent in G0, edge bit not set by an earlier witness.
+// Candidate edges: entries a -> b (a < b) of the compacted subgraph whose
+// certified roles are adjacent in G0 and that no found match certified yet.
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
     const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
-    const int32_t *c_off, const int64_t *rp, const M *cert, LccTable tab,
-    const uint64_t *edge_bits, int32_t *eu, int32_t *ew, int64_t *e_idx, int32_t *n_out,
-    int64_t cap) {
+    const int32_t *c_rev, const M *cert, LccTable tab, const uint64_t *c_cert, int32_t *eu,
+    int32_t *ew, int64_t *e_idx, int32_t *n_out, int64_t cap) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -250,17 +344,15 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
         const uint64_t cu = (uint64_t)cert[u];
         if (!cu) continue;
         const uint64_t reach = reach_mask<M>(cu, tab);
-        const int64_t s = c_rp[u], e = c_rp[u + 1], r0 = rp[u];
+        const int64_t s = c_rp[u], e = c_rp[u + 1];
         for (int64_t base = s; base < e; base += kWave) {
             const int64_t k = base + lane;
             bool p = false;
             int32_t w = 0;
-            int64_t orig = 0;
             if (k < e) {
                 w = c_col[k];
-                orig = r0 + c_off[k];
-                p = w > u && ((uint64_t)cert[w] & reach) != 0ull &&
-                    !((edge_bits[orig >> 6] >> (orig & 63)) & 1ull);
+                p = w > u && ((uint64_t)cert[w] & reach) != 0ull && !test_bit(c_cert, k) &&
+                    !test_bit(c_cert, c_rev[k]);
             }
             const uint64_t m = ballot64(p);
             if (!m) continue;
@@ -272,7 +364,7 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
                 if (o < cap) {
                     eu[o] = u;
                     ew[o] = w;
-                    e_idx[o] = orig;
+                    e_idx[o] = k;
                 }
             }
         }
@@ -281,16 +373,16 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
 
 template <typename M>
 void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
-                            const int64_t *rp, const M *cert, const LccTable &tab,
-                            const uint64_t *edge_bits, int32_t *eu, int32_t *ew, int64_t *e_idx,
-                            int32_t *n_out, int64_t cap) {
+                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_rev,
+                            const M *cert, const LccTable &tab, const uint64_t *c_cert,
+                            int32_t *eu, int32_t *ew, int64_t *e_idx, int32_t *n_out,
+                            int64_t cap) {
     if (n_tasks <= 0) return;
     int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(edge_candidates_kernel<M>, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       tasks, n_tasks, c_rp, c_col, c_off, rp, cert, tab, edge_bits, eu, ew,
-                       e_idx, n_out, cap);
+                       tasks, n_tasks, c_rp, c_col, c_rev, cert, tab, c_cert, eu, ew, e_idx,
+                       n_out, cap);
 }
 
 template <typename M>
@@ -298,7 +390,7 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
     const int32_t *eu, const int32_t *ew, const int64_t *e_idx, int64_t n_edges, const M *om,
     M *cert, const int32_t *edge_plan, int32_t n_edge_plans, SearchArgs a) {
     const int lane = lane_id();
-    unsigned long long queries = 0;
+    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0;
     for (;;) {
         int t0 = 0;
         if (lane == 0) t0 = atomicAdd(a.task_counter, kTaskChunk);
@@ -307,23 +399,41 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
         const int64_t t1 = (int64_t)t0 + kTaskChunk < n_edges ? (int64_t)t0 + kTaskChunk : n_edges;
         for (int64_t t = t0; t < t1; ++t) {
             const int32_t u = eu[t], w = ew[t];
-            const int64_t e = e_idx[t];
+            const int64_t k = e_idx[t];
+            const int64_t kr = a.c_rev[k];
             const uint64_t cu = (uint64_t)om[u], cw = (uint64_t)om[w];
             for (int i = 0; i < n_edge_plans; ++i) {
-                if ((load_fresh(a.edge_bits + (e >> 6)) >> (e & 63)) & 1ull) break;
+                if (((load_fresh(a.c_cert + (k >> 6)) >> (k & 63)) & 1ull) ||
+                    ((load_fresh(a.c_cert + (kr >> 6)) >> (kr & 63)) & 1ull))
+                    break;
                 const int pidx = edge_plan[i];
                 const SearchPlan *P = a.plans + pidx;
                 if (!((cu >> P->q[0]) & 1ull) || !((cw >> P->q[1]) & 1ull)) continue;
                 int32_t img = 0;
                 ++queries;
-                if (dfs_search<M>(a, P, om, u, w, img)) {
-                    certify<M>(a, P, pidx, img, cert, true);
+                const uint64_t c0 = wall_clock64();
+                const bool found = dfs_search<M>(a, P, om, u, w, img);
+                const uint64_t dt = wall_clock64() - c0;
+                if (found) {
+                    ++npos;
+                    tpos += dt;
+                    certify_match<M>(a, P, pidx, img, cert);
+                    if (a.expand) expand_match<M>(a, P, img, om, cert);
                     break;
                 }
+                tneg += dt;
             }
         }
     }
-    if (lane == 0 && queries) atomicAdd(a.n_queries, queries);
+    if (lane == 0 && queries) {
+        atomicAdd(a.n_queries, queries);
+        if (a.qstats) {
+            atomicAdd(a.qstats + 4, npos);
+            atomicAdd(a.qstats + 5, queries - npos);
+            atomicAdd(a.qstats + 6, tpos);
+            atomicAdd(a.qstats + 7, tneg);
+        }
+    }
 }
 
 template <typename M>
@@ -334,6 +444,55 @@ void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
     if (n_edges <= 0) return;
     hipLaunchKernelGGL(edge_search_kernel<M>, dim3(grid), dim3(kSearchBlock), 0, s, eu, ew,
                        e_idx, n_edges, omega, cert, edge_plan_dev, n_edge_plans, a);
+}
+
+__global__ __launch_bounds__(kSearchBlock) void reverse_index_kernel(
+    const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
+    int32_t *c_rev) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t t = wave; t < n_tasks; t += nwaves) {
+        const int32_t u = tasks[t];
+        const int64_t s = c_rp[u], e = c_rp[u + 1];
+        for (int64_t k = s + lane; k < e; k += kWave) {
+            const int32_t w = c_col[k];
+            c_rev[k] = (int32_t)find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
+        }
+    }
+}
+
+void launch_reverse_index(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
+                          const int64_t *c_rp, const int32_t *c_col, int32_t *c_rev) {
+    if (n_tasks <= 0) return;
+    int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(reverse_index_kernel, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
+                       tasks, n_tasks, c_rp, c_col, c_rev);
+}
+
+__global__ __launch_bounds__(kSearchBlock) void edges_from_cert_kernel(
+    const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_off,
+    const int32_t *c_rev, const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t t = wave; t < n_tasks; t += nwaves) {
+        const int32_t u = tasks[t];
+        const int64_t s = c_rp[u], e = c_rp[u + 1], r0 = rp[u];
+        for (int64_t k = s + lane; k < e; k += kWave)
+            if (test_bit(c_cert, k) || test_bit(c_cert, c_rev[k])) set_bit(edge_bits, r0 + c_off[k]);
+    }
+}
+
+void launch_edges_from_cert(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
+                            const int64_t *c_rp, const int32_t *c_off, const int32_t *c_rev,
+                            const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
+    if (n_tasks <= 0) return;
+    int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(edges_from_cert_kernel, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
+                       tasks, n_tasks, c_rp, c_off, c_rev, rp, c_cert, edge_bits);
 }
 
 // Edge state implied by role sets (edge elimination rule): bit of entry
@@ -374,9 +533,8 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                                   int32_t *);                                                     \
     template void launch_edge_candidates<M>(hipStream_t, const int32_t *, int64_t,                \
                                             const int64_t *, const int32_t *, const int32_t *,    \
-                                            const int64_t *, const M *, const LccTable &,         \
-                                            const uint64_t *, int32_t *, int32_t *, int64_t *,    \
-                                            int32_t *, int64_t);                                  \
+                                            const M *, const LccTable &, const uint64_t *,        \
+                                            int32_t *, int32_t *, int64_t *, int32_t *, int64_t); \
     template void launch_edge_search<M>(hipStream_t, const int32_t *, const int32_t *,            \
                                         const int64_t *, int64_t, const M *, M *,                 \
                                         const int32_t *, int32_t, const SearchArgs &, int);       \

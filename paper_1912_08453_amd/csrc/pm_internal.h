@@ -40,6 +40,8 @@ struct SearchPlan {
     int32_t q[kMaxK];               // template vertex at each position
     uint64_t back[kMaxK];           // earlier positions adjacent in the substructure
     uint64_t same[kMaxK];           // earlier positions with the same label
+    uint64_t nbr[kMaxK];            // all positions adjacent in the substructure
+    uint64_t samel[kMaxK];          // all other positions with the same label
     uint64_t certify;               // roles certified by a successful search
 };
 
@@ -168,7 +170,26 @@ struct SearchArgs {
     uint64_t *edge_bits;
     int32_t *task_counter;
     unsigned long long *n_queries;
+    // exact step: certified entries of the compacted subgraph (bit k = entry
+    // k), reverse entry index, per-vertex expansion flags (bit t = oriented
+    // template edge t expanded from this vertex), query statistics
+    const int32_t *c_rev;
+    uint64_t *c_cert;
+    uint64_t *exp_done;
+    unsigned long long *qstats;     // [8]: vpos, vneg, vpos_t, vneg_t, epos, eneg, epos_t, eneg_t
+    int32_t expand;                 // run the single-vertex swap expansion
 };
+
+// Reverse entry of every compacted entry (the compacted subgraph is
+// symmetric): rows of the vertices in tasks.
+void launch_reverse_index(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
+                          const int64_t *c_rp, const int32_t *c_col, int32_t *c_rev);
+
+// Output edge bits from certified compacted entries: entry k of row a is
+// in the complete set iff k or its reverse is certified.
+void launch_edges_from_cert(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
+                            const int64_t *c_rp, const int32_t *c_off, const int32_t *c_rev,
+                            const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits);
 
 template <typename M>
 void launch_vertex_search(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,
@@ -183,10 +204,10 @@ void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega
 // with adjacent certified roles and no certified bit yet.
 template <typename M>
 void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
-                            const int64_t *rp, const M *cert, const LccTable &tab,
-                            const uint64_t *edge_bits, int32_t *eu, int32_t *ew,
-                            int64_t *e_idx, int32_t *n_out, int64_t cap);
+                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_rev,
+                            const M *cert, const LccTable &tab, const uint64_t *c_cert,
+                            int32_t *eu, int32_t *ew, int64_t *e_idx, int32_t *n_out,
+                            int64_t cap);
 
 template <typename M>
 void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,

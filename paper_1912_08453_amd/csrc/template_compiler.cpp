@@ -226,9 +226,16 @@ SearchPlan make_plan(const std::vector<Edge> &sub, const std::vector<int32_t> &l
     for (int i = 0; i < P.k; ++i) {
         P.back[i] = 0;
         P.same[i] = 0;
-        for (int j = 0; j < i; ++j) {
-            if ((sadj[P.q[i]] >> P.q[j]) & 1) P.back[i] |= 1ull << j;
-            if (labels[P.q[i]] == labels[P.q[j]]) P.same[i] |= 1ull << j;
+        P.nbr[i] = 0;
+        P.samel[i] = 0;
+        for (int j = 0; j < P.k; ++j) {
+            if (j == i) continue;
+            const bool adj = (sadj[P.q[i]] >> P.q[j]) & 1;
+            const bool same = labels[P.q[i]] == labels[P.q[j]];
+            if (adj) P.nbr[i] |= 1ull << j;
+            if (same) P.samel[i] |= 1ull << j;
+            if (j < i && adj) P.back[i] |= 1ull << j;
+            if (j < i && same) P.same[i] |= 1ull << j;
         }
     }
     P.certify = certify;

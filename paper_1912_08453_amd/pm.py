@@ -56,10 +56,12 @@ class pm_options(ctypes.Structure):
 class pm_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("ms_total", "ms_init", "ms_lcc", "ms_compact", "ms_nlcc", "ms_exact",
-                 "ms_first_sweep", "ms_sweep_kernel")] + \
+                 "ms_first_sweep", "ms_sweep_kernel", "wave_ms_vq_pos", "wave_ms_vq_neg",
+                 "wave_ms_eq_pos", "wave_ms_eq_neg")] + \
                [(k, ctypes.c_int64) for k in
                 ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
-                 "candidate_entries", "vertex_queries", "edge_queries", "result_vertices")] + \
+                 "candidate_entries", "vertex_queries", "edge_queries", "result_vertices",
+                 "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg")] + \
                [("reserved", ctypes.c_int64 * 6)]
 
     def as_dict(self):
