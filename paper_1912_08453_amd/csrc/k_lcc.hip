@@ -44,6 +44,45 @@ __device__ __forceinline__ uint64_t evaluate(uint64_t w, uint64_t cover, const i
     return nw;
 }
 
+// Accumulate coverage (OR of the neighbours' role masks) and distinct-count
+// tallies over the entries k = k0, k0 + stride, ... < e.  The column ids of
+// kUnroll entries are loaded (streaming, non-temporal) before their role
+// masks are gathered, so each wavefront keeps several loads in flight.
+constexpr int kUnroll = 8;
+
+template <typename M, bool CNT>
+__device__ __forceinline__ void accumulate(const int32_t *__restrict__ col, const M *omega,
+                                           int64_t k0, int64_t e, int stride,
+                                           const LccTable &tab, uint64_t &cover, int *cnt) {
+    int64_t k = k0;
+    for (; k + (int64_t)(kUnroll - 1) * stride < e; k += (int64_t)kUnroll * stride) {
+        int32_t c[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) c[u] = __builtin_nontemporal_load(col + k + (int64_t)u * stride);
+        uint64_t x[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) x[u] = (uint64_t)omega[c[u]];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            cover |= x[u];
+            if constexpr (CNT) {
+#pragma unroll
+                for (int q = 0; q < kMaxCount; ++q)
+                    if (q < tab.ncount) cnt[q] += (x[u] & tab.cmask[q]) != 0ull;
+            }
+        }
+    }
+    for (; k < e; k += stride) {
+        const uint64_t x = (uint64_t)omega[__builtin_nontemporal_load(col + k)];
+        cover |= x;
+        if constexpr (CNT) {
+#pragma unroll
+            for (int q = 0; q < kMaxCount; ++q)
+                if (q < tab.ncount) cnt[q] += (x & tab.cmask[q]) != 0ull;
+        }
+    }
+}
+
 // ------------------------------------------------------- role initialisation
 // omega0(v) = { q : l(q) = l(v) } (vertex state and initialisation algorithm)
 template <typename M>
@@ -209,15 +248,7 @@ __device__ __forceinline__ void lcc_group_body(int64_t local_block, const int64_
     int cnt[CNT ? kMaxCount : 1];
 #pragma unroll
     for (int c = 0; c < (CNT ? kMaxCount : 1); ++c) cnt[c] = 0;
-    for (int64_t k = s + sl; k < e; k += G) {
-        const uint64_t x = (uint64_t)omega[col[k]];
-        cover |= x;
-        if constexpr (CNT) {
-#pragma unroll
-            for (int c = 0; c < kMaxCount; ++c)
-                if (c < tab.ncount) cnt[c] += (x & tab.cmask[c]) != 0ull;
-        }
-    }
+    accumulate<M, CNT>(col, omega, s + sl, e, G, tab, cover, cnt);
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) {
         cover |= shfl_xor_u64(cover, off, G);
@@ -253,15 +284,7 @@ __device__ __forceinline__ void lcc_hub_body(int64_t local_block, const int64_t 
     int cnt[CNT ? kMaxCount : 1];
 #pragma unroll
     for (int c = 0; c < (CNT ? kMaxCount : 1); ++c) cnt[c] = 0;
-    for (int64_t k = b + lane; k < e; k += kWave) {
-        const uint64_t x = (uint64_t)omega[col[k]];
-        cover |= x;
-        if constexpr (CNT) {
-#pragma unroll
-            for (int c = 0; c < kMaxCount; ++c)
-                if (c < tab.ncount) cnt[c] += (x & tab.cmask[c]) != 0ull;
-        }
-    }
+    accumulate<M, CNT>(col, omega, b + lane, e, kWave, tab, cover, cnt);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         cover |= shfl_xor_u64(cover, off, 64);
@@ -388,7 +411,17 @@ __global__ __launch_bounds__(kBlock) void compact_count_group(const int64_t *__r
         e = rp[v + 1];
     }
     int c = 0;
-    for (int64_t k = s + sl; k < e; k += G) c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+    {
+        int64_t k = s + sl;
+        for (; k + (int64_t)(kUnroll - 1) * G < e; k += (int64_t)kUnroll * G) {
+            int32_t cc[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) cc[u] = col[k + (int64_t)u * G];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) c += ((uint64_t)omega[cc[u]] & reach) != 0ull;
+        }
+        for (; k < e; k += G) c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+    }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, G);
     if (valid && sl == 0) deg_out[v] = c;
@@ -407,9 +440,18 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
     const int32_t v = wl.hub_seg_v[seg];
     const uint64_t reach = reach_of<M>((uint64_t)omega[v], tab);
     int c = 0;
-    if (reach)
-        for (int64_t k = wl.hub_seg_begin[seg] + lane; k < wl.hub_seg_end[seg]; k += kWave)
-            c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+    if (reach) {
+        const int64_t e = wl.hub_seg_end[seg];
+        int64_t k = wl.hub_seg_begin[seg] + lane;
+        for (; k + (int64_t)(kUnroll - 1) * kWave < e; k += (int64_t)kUnroll * kWave) {
+            int32_t cc[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) cc[u] = col[k + (int64_t)u * kWave];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) c += ((uint64_t)omega[cc[u]] & reach) != 0ull;
+        }
+        for (; k < e; k += kWave) c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
     if (lane == 0) {
