@@ -98,9 +98,10 @@ struct pm_ctx {
     std::vector<std::unique_ptr<CompiledTemplate>> templates;
     // scratch
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
-    DevBuf eu, ew, eidx, edge_plan_ids, crev, ccert, expdone;
+    DevBuf eu, ew, eidx, edge_plan_ids, crev, ccert, expdone, rcnt;
     int grid_search = 2048;
     int expand = 1;
+    int use_counts = 1;
     int64_t wall_khz = 0;
 };
 
@@ -303,8 +304,10 @@ struct Pruner {
         a.rp = c->rp;
         a.col = c->col;
         a.plans = T.d_plans;
-        a.plan_edges = T.d_plan_edges;
+        a.tedges = T.d_tedges;
         a.m0 = T.m0;
+        a.rcnt = rcnt_dirty ? nullptr : c->rcnt.as<uint16_t>();
+        a.rcnt_stride = T.n0;
         a.mode = mode;
         a.heads = heads;
         for (int i = 0; i < kMaxK; ++i) a.plan_of_head[i] = plan_of_head[i];
@@ -319,9 +322,18 @@ struct Pruner {
         return a;
     }
 
+    // Role counts of the active vertices (search-order estimates).
+    bool rcnt_dirty = true;
+    void role_counts() {
+        c->rcnt.ensure(sizeof(uint16_t) * (size_t)std::max<int64_t>(c->n, 1) * (size_t)T.n0);
+        launch_role_counts<M>(s, A, nA, c_rp, c_col, om, T.n0, c->rcnt.as<uint16_t>());
+        rcnt_dirty = false;
+    }
+
     // One non-local constraint (snapshot semantics); returns vertices changed.
     int32_t nlcc(const Constraint &k) {
         Timer t(s);
+        if (c->use_counts) role_counts();
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         SearchArgs a = search_args(0, k.heads, k.plan_of_head, nullptr);
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
@@ -346,6 +358,7 @@ struct Pruner {
         int32_t *c_rev = c->crev.as<int32_t>();
         uint64_t *c_cert = c->ccert.as<uint64_t>();
         launch_reverse_index(s, A, nA, c_rp, c_col, c_rev);
+        if (c->use_counts) role_counts();
         launch_fill_u64(s, c_cert, cwords, 0ull);
         launch_fill_u64(s, c->expdone.as<uint64_t>(), n, 0ull);
         PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 8, s));
@@ -477,10 +490,14 @@ void load_template_device(pm_ctx *c, CompiledTemplate &T) {
     PM_HIP(hipMalloc(&T.d_plans, sizeof(SearchPlan) * std::max<size_t>(T.plans.size(), 1)));
     PM_HIP(hipMemcpy(T.d_plans, T.plans.data(), sizeof(SearchPlan) * T.plans.size(),
                      hipMemcpyHostToDevice));
-    PM_HIP(hipMalloc(&T.d_plan_edges, sizeof(PlanEdge) * std::max<size_t>(T.plan_edges.size(), 1)));
-    if (!T.plan_edges.empty())
-        PM_HIP(hipMemcpy(T.d_plan_edges, T.plan_edges.data(), sizeof(PlanEdge) * T.plan_edges.size(),
-                         hipMemcpyHostToDevice));
+    std::vector<int32_t> te;
+    for (auto &e : T.edges) {
+        te.push_back(e.first);
+        te.push_back(e.second);
+    }
+    PM_HIP(hipMalloc(&T.d_tedges, sizeof(int32_t) * std::max<size_t>(te.size(), 2)));
+    if (!te.empty())
+        PM_HIP(hipMemcpy(T.d_tedges, te.data(), sizeof(int32_t) * te.size(), hipMemcpyHostToDevice));
     int maxl = 0;
     for (int q = 0; q < T.n0; ++q) maxl = std::max(maxl, T.labels[q]);
     std::vector<uint64_t> lut((size_t)maxl + 1, 0);
@@ -493,10 +510,10 @@ void load_template_device(pm_ctx *c, CompiledTemplate &T) {
 
 void free_template_device(CompiledTemplate &T) {
     if (T.d_plans) (void)hipFree(T.d_plans);
-    if (T.d_plan_edges) (void)hipFree(T.d_plan_edges);
+    if (T.d_tedges) (void)hipFree(T.d_tedges);
     if (T.d_init_lut) (void)hipFree(T.d_init_lut);
     T.d_plans = nullptr;
-    T.d_plan_edges = nullptr;
+    T.d_tedges = nullptr;
     T.d_init_lut = nullptr;
 }
 
@@ -561,6 +578,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
                 c->wall_khz = khz;
             const char *ex = getenv("PM_EXPAND");
             if (ex) c->expand = atoi(ex);
+            const char *uc = getenv("PM_ROLE_COUNTS");
+            if (uc) c->use_counts = atoi(uc);
         } catch (...) {
             delete c;
             throw;
@@ -577,7 +596,7 @@ int pm_destroy(pm_ctx *c) {
         for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->omega, &c->sat, &c->alist[0],
                           &c->alist[1], &c->bins, &c->counters, &c->hub, &c->cdeg, &c->crp,
                           &c->ccol, &c->coff, &c->segcnt, &c->scan_scratch, &c->eu, &c->ew,
-                          &c->eidx, &c->edge_plan_ids, &c->crev, &c->ccert, &c->expdone})
+                          &c->eidx, &c->edge_plan_ids, &c->crev, &c->ccert, &c->expdone, &c->rcnt})
             b->release();
         delete c;
     });

@@ -31,40 +31,59 @@ namespace pm {
 constexpr int kSearchBlock = 256;
 constexpr int kTaskChunk = 4;
 
-// Depth-first search of plan P with positions 0 (and 1) pinned at v0 (v1).
-// Lane-distributed state: lane i holds the image of position i and the scan
-// state of level i.  Returns true with img_r holding a full embedding.
+// Estimated number of candidates for template vertex p next to the image y
+// of a placed neighbour: neighbours of y holding role p (role counts), or
+// y's candidate degree when no counts are available.
+__device__ __forceinline__ int64_t cand_estimate(const SearchArgs &a, int32_t y, int p) {
+    if (a.rcnt) return (int64_t)a.rcnt[(int64_t)y * a.rcnt_stride + p];
+    return a.c_rp[y + 1] - a.c_rp[y];
+}
+
+// Depth-first search for an embedding of plan P's substructure with the
+// pinned template vertices at v0 (and v1).  Lane-distributed state: lane q
+// holds the image of template vertex q; lane l holds the scan state of
+// search level l (which template vertex it places, the placed neighbour
+// whose candidate row it scans, the row cursor and the ballot of surviving
+// candidates of the current 64-entry chunk).  At each new level the
+// unplaced vertex with the fewest estimated candidates is placed next (the
+// paper's constraint optimisation visits rare labels first; here the
+// estimate is per partial match).  Returns true with img_r holding a full
+// embedding.
 template <typename M>
 __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
                            const M *__restrict__ om, int32_t v0, int32_t v1, int32_t &img_r) {
     const int lane = lane_id();
     const int k = P->k;
     const int npin = P->npin;
-    int64_t cur_r = 0, end_r = 0, base_r = 0;
-    uint64_t pend_r = 0;
-    int32_t par_r = 0;
-    img_r = lane == 0 ? v0 : (lane == 1 ? v1 : -1);
+    const uint64_t vmask = P->vmask;
+    const int p0 = P->pin[0], p1 = P->pin[1];
+    img_r = lane == p0 ? v0 : ((npin == 2 && lane == p1) ? v1 : -1);
+    uint64_t placed = (1ull << p0) | (npin == 2 ? (1ull << p1) : 0ull);
     if (k <= npin) return true;
     const int64_t *__restrict__ crp = a.c_rp;
     const int32_t *__restrict__ ccol = a.c_col;
+    int64_t cur_r = 0, end_r = 0, base_r = 0;
+    uint64_t pend_r = 0;
+    int32_t pv_r = 0, par_r = 0;
 
-    int lvl = npin;
-    auto setup = [&](int l) {
-        const uint64_t back = P->back[l];
-        int best = -1;
-        int64_t bd = INT64_MAX;
-        for (uint64_t m = back; m; m &= m - 1) {
-            const int j = __builtin_ctzll(m);
-            const int32_t y = read_lane32(img_r, j);
-            const int64_t d = crp[y + 1] - crp[y];
-            if (d < bd) {
-                bd = d;
-                best = j;
+    auto select = [&](int l) {
+        int bp = -1, bj = -1;
+        int64_t bs = INT64_MAX;
+        for (uint64_t mp = vmask & ~placed; mp; mp &= mp - 1) {
+            const int p = __builtin_ctzll(mp);
+            for (uint64_t mj = P->adj[p] & placed; mj; mj &= mj - 1) {
+                const int j = __builtin_ctzll(mj);
+                const int64_t sc = cand_estimate(a, read_lane32(img_r, j), p);
+                if (sc < bs) {
+                    bs = sc;
+                    bp = p;
+                    bj = j;
+                }
             }
         }
         int64_t s = 0, e = 0;
-        if (best >= 0) {
-            const int32_t y = read_lane32(img_r, best);
+        if (bj >= 0) {
+            const int32_t y = read_lane32(img_r, bj);
             s = crp[y];
             e = crp[y + 1];
         }
@@ -72,10 +91,12 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
             cur_r = s;
             end_r = e;
             pend_r = 0;
-            par_r = best < 0 ? 0 : best;
+            pv_r = bp < 0 ? 0 : bp;
+            par_r = bj < 0 ? 0 : bj;
         }
     };
-    setup(lvl);
+    int lvl = npin;
+    select(lvl);
     for (;;) {
         uint64_t pend = read_lane_u64(pend_r, lvl);
         if (pend == 0) {
@@ -83,11 +104,13 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
             const int64_t end = read_lane64(end_r, lvl);
             if (cur >= end) {
                 if (--lvl < npin) return false;
+                placed &= ~(1ull << read_lane32(pv_r, lvl));
                 continue;
             }
-            const int q = P->q[lvl];
-            const uint64_t same = P->same[lvl];
-            const uint64_t back = P->back[lvl] & ~(1ull << read_lane32(par_r, lvl));
+            const int q = read_lane32(pv_r, lvl);
+            const int par = read_lane32(par_r, lvl);
+            const uint64_t same = P->samelab[q] & placed;
+            const uint64_t back = P->adj[q] & placed & ~(1ull << par);
             const int64_t kk = cur + lane;
             const bool in_range = kk < end;
             const int32_t x = in_range ? ccol[kk] : -1;
@@ -113,13 +136,13 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
         pend &= pend - 1;
         const int64_t base = read_lane64(base_r, lvl);
         const int32_t x = ccol[base + j];
-        if (lane == lvl) {
-            pend_r = pend;
-            img_r = x;
-        }
+        const int q = read_lane32(pv_r, lvl);
+        if (lane == lvl) pend_r = pend;
+        if (lane == q) img_r = x;
+        placed |= 1ull << q;
         if (lvl == k - 1) return true;
         ++lvl;
-        setup(lvl);
+        select(lvl);
     }
 }
 
@@ -127,10 +150,8 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
 template <typename M>
 __device__ void certify_roles(const SearchPlan *__restrict__ P, int32_t img_r, M *sat) {
     const int lane = lane_id();
-    if (lane < P->k) {
-        const int q = P->q[lane];
-        if ((P->certify >> q) & 1ull) atomic_or_elem<M>(sat, img_r, 1ull << q);
-    }
+    if ((P->vmask >> lane) & 1ull)
+        if ((P->certify >> lane) & 1ull) atomic_or_elem<M>(sat, img_r, 1ull << lane);
 }
 
 __device__ __forceinline__ bool test_bit(const uint64_t *bits, int64_t k) {
@@ -140,19 +161,19 @@ __device__ __forceinline__ bool test_bit(const uint64_t *bits, int64_t k) {
 // Certify a full match: every role, and every template edge as an entry of
 // the compacted subgraph (one direction; the output ORs in the reverse).
 template <typename M>
-__device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict__ P, int plan_idx,
+__device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict__ P,
                               int32_t img_r, M *cert) {
     const int lane = lane_id();
-    if (lane < P->k) atomic_or_elem<M>(cert, img_r, 1ull << P->q[lane]);
+    if ((P->vmask >> lane) & 1ull) atomic_or_elem<M>(cert, img_r, 1ull << lane);
     for (int base = 0; base < a.m0; base += kWave) {
         const int i = base + lane;
-        int pa = 0, pb = 0;
+        int ta = 0, tb = 0;
         if (i < a.m0) {
-            pa = a.plan_edges[(int64_t)plan_idx * a.m0 + i].pa;
-            pb = a.plan_edges[(int64_t)plan_idx * a.m0 + i].pb;
+            ta = a.tedges[2 * i];
+            tb = a.tedges[2 * i + 1];
         }
-        const int32_t u = __shfl(img_r, pa);
-        const int32_t w = __shfl(img_r, pb);
+        const int32_t u = __shfl(img_r, ta);
+        const int32_t w = __shfl(img_r, tb);
         if (i < a.m0) {
             const int64_t k = find_sorted(a.c_col, a.c_rp[u], a.c_rp[u + 1], w);
             if (k >= 0) set_bit(a.c_cert, k);
@@ -160,28 +181,26 @@ __device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict_
     }
 }
 
-// Single-vertex swaps of a found match: for each position i, every x that
-// can replace phi(i) with all other images fixed (role q_i, adjacent to the
-// images of all template neighbours of q_i, distinct from the images of
-// same-label positions) gives another match, whose role (x, q_i) and edges
-// at x are certified.  Purely a saving: anything it misses is queried later.
+// Single-vertex swaps of a found match: for each template vertex q, every x
+// that can replace phi(q) with all other images fixed (role q, adjacent to
+// the images of all template neighbours of q, distinct from the images of
+// same-label vertices) gives another match, whose role (x, q) and edges at
+// x are certified.  Purely a saving: anything it misses is queried later.
 template <typename M>
 __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__ P,
                              int32_t img_r, const M *__restrict__ om, M *cert) {
     const int lane = lane_id();
-    const int k = P->k;
     const int64_t *__restrict__ crp = a.c_rp;
     const int32_t *__restrict__ ccol = a.c_col;
-    for (int i = 0; i < k; ++i) {
-        const uint64_t nb = P->nbr[i];
+    for (uint64_t mq = P->vmask; mq; mq &= mq - 1) {
+        const int q = __builtin_ctzll(mq);
+        const uint64_t nb = P->adj[q];
         if (!nb) continue;
-        const int q = P->q[i];
         int js = -1;
         int64_t bd = INT64_MAX;
         for (uint64_t m = nb; m; m &= m - 1) {
             const int j = __builtin_ctzll(m);
-            const int32_t y = read_lane32(img_r, j);
-            const int64_t d = crp[y + 1] - crp[y];
+            const int64_t d = cand_estimate(a, read_lane32(img_r, j), q);
             if (d < bd) {
                 bd = d;
                 js = j;
@@ -189,7 +208,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
         }
         const int32_t ys = read_lane32(img_r, js);
         if (__popcll(nb) == 1) {
-            // a pendant position depends (up to identity checks) only on its
+            // a pendant vertex depends (up to identity checks) only on its
             // neighbour's image: expand it once per (vertex, role)
             unsigned long long old = 0;
             if (lane == 0) old = atomicOr((unsigned long long *)&a.exp_done[ys], 1ull << q);
@@ -197,14 +216,14 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             if ((old >> q) & 1ull) continue;
         }
         const uint64_t others = nb & ~(1ull << js);
-        const uint64_t samel = P->samel[i];
+        const uint64_t same = P->samelab[q];
         const int64_t s = crp[ys], e = crp[ys + 1];
         for (int64_t base = s; base < e; base += kWave) {
             const int64_t kk = base + lane;
             const bool in = kk < e;
             const int32_t x = in ? ccol[kk] : -1;
             bool ok = in && (((uint64_t)om[x] >> q) & 1ull);
-            for (uint64_t m = samel; m; m &= m - 1) {
+            for (uint64_t m = same; m; m &= m - 1) {
                 const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
                 ok = ok && (x != y);
             }
@@ -224,6 +243,49 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             }
         }
     }
+}
+
+// Role counts of the vertices in tasks (one wavefront per vertex; per-wave
+// counters in LDS).
+template <typename M>
+__global__ __launch_bounds__(kSearchBlock) void role_counts_kernel(
+    const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
+    const M *omega, int n0, uint16_t *rcnt) {
+    __shared__ unsigned int acc[kSearchBlock / kWave][kMaxK];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t t = wave; t < n_tasks; t += nwaves) {
+        const int32_t v = tasks[t];
+        if (lane < kMaxK) acc[wib][lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        const int64_t s = c_rp[v], e = c_rp[v + 1];
+        for (int64_t k = s + lane; k < e; k += kWave) {
+            uint64_t w = (uint64_t)omega[c_col[k]];
+            while (w) {
+                const int q = __builtin_ctzll(w);
+                w &= w - 1;
+                atomicAdd(&acc[wib][q], 1u);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < n0) {
+            const unsigned int c = acc[wib][lane];
+            rcnt[(int64_t)v * n0 + lane] = (uint16_t)(c > 65535u ? 65535u : c);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <typename M>
+void launch_role_counts(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
+                        const int32_t *c_col, const M *omega, int n0, uint16_t *rcnt) {
+    if (n_tasks <= 0) return;
+    int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(role_counts_kernel<M>, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
+                       tasks, n_tasks, c_rp, c_col, omega, n0, rcnt);
 }
 
 template <typename M>
@@ -261,7 +323,7 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                     ++npos;
                     tpos += dt;
                     if (a.mode == 1) {
-                        certify_match<M>(a, P, pidx, img, sat);
+                        certify_match<M>(a, P, img, sat);
                         if (a.expand) expand_match<M>(a, P, img, om, sat);
                     } else {
                         certify_roles<M>(P, img, sat);
@@ -408,7 +470,7 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
                     break;
                 const int pidx = edge_plan[i];
                 const SearchPlan *P = a.plans + pidx;
-                if (!((cu >> P->q[0]) & 1ull) || !((cw >> P->q[1]) & 1ull)) continue;
+                if (!((cu >> P->pin[0]) & 1ull) || !((cw >> P->pin[1]) & 1ull)) continue;
                 int32_t img = 0;
                 ++queries;
                 const uint64_t c0 = wall_clock64();
@@ -417,7 +479,7 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
                 if (found) {
                     ++npos;
                     tpos += dt;
-                    certify_match<M>(a, P, pidx, img, cert);
+                    certify_match<M>(a, P, img, cert);
                     if (a.expand) expand_match<M>(a, P, img, om, cert);
                     break;
                 }
@@ -538,6 +600,8 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
     template void launch_edge_search<M>(hipStream_t, const int32_t *, const int32_t *,            \
                                         const int64_t *, int64_t, const M *, M *,                 \
                                         const int32_t *, int32_t, const SearchArgs &, int);       \
+    template void launch_role_counts<M>(hipStream_t, const int32_t *, int64_t, const int64_t *,   \
+                                        const int32_t *, const M *, int, uint16_t *);             \
     template void launch_active_edges<M>(hipStream_t, const int32_t *, int64_t, const int64_t *,  \
                                          const int32_t *, const int32_t *, const int64_t *,       \
                                          const M *, const LccTable &, uint64_t *);

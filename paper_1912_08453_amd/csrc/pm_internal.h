@@ -32,22 +32,17 @@ struct LccTable {
     int32_t cneed[kMaxCount];       // |cmask| >= 2
 };
 
-// One search plan: an ordered walk over a substructure of G0 whose first
-// npin positions are pinned (the head vertex, or both ends of an edge).
+// One search plan: a substructure of G0 (vertex set and its own edges) with
+// one or two template vertices pinned (the head, or both ends of an edge).
+// The search order is chosen per partial match at run time.
 struct SearchPlan {
     int32_t k;                      // substructure vertices
     int32_t npin;                   // 1 or 2
-    int32_t q[kMaxK];               // template vertex at each position
-    uint64_t back[kMaxK];           // earlier positions adjacent in the substructure
-    uint64_t same[kMaxK];           // earlier positions with the same label
-    uint64_t nbr[kMaxK];            // all positions adjacent in the substructure
-    uint64_t samel[kMaxK];          // all other positions with the same label
+    int32_t pin[2];                 // pinned template vertices
+    uint64_t vmask;                 // substructure vertices
+    uint64_t adj[kMaxK];            // substructure adjacency per template vertex
+    uint64_t samelab[kMaxK];        // other substructure vertices of the same label
     uint64_t certify;               // roles certified by a successful search
-};
-
-// A template-edge pair of plan positions, used to certify witness edges.
-struct PlanEdge {
-    int32_t pa, pb;
 };
 
 // Compiled non-local constraint.
@@ -72,11 +67,10 @@ struct CompiledTemplate {
     std::vector<SearchPlan> plans;            // all plans of this template
     int32_t vertex_plan[kMaxK];               // full template, pinned at q
     std::vector<int32_t> edge_plans;          // 2*m0 plans: (a->b), (b->a)
-    std::vector<PlanEdge> plan_edges;         // per plan: m0 position pairs
     uint64_t label_mask_of[kMaxK];            // roles sharing q's label
     // device copies
     SearchPlan *d_plans = nullptr;
-    PlanEdge *d_plan_edges = nullptr;         // [plans][m0]
+    int32_t *d_tedges = nullptr;              // [2*m0] template edges (a, b)
     uint64_t *d_init_lut = nullptr;           // label -> initial roles
     int64_t init_lut_len = 0;
 };
@@ -162,8 +156,10 @@ struct SearchArgs {
     const int64_t *rp;              // original CSR (edge bit indices)
     const int32_t *col;
     const SearchPlan *plans;
-    const PlanEdge *plan_edges;
+    const int32_t *tedges;          // template edges (a, b) pairs
     int32_t m0;
+    const uint16_t *rcnt;           // [n][rcnt_stride]: neighbours holding each role
+    int32_t rcnt_stride;
     int32_t mode;
     uint64_t heads;
     int32_t plan_of_head[kMaxK];
@@ -179,6 +175,13 @@ struct SearchArgs {
     unsigned long long *qstats;     // [8]: vpos, vneg, vpos_t, vneg_t, epos, eneg, epos_t, eneg_t
     int32_t expand;                 // run the single-vertex swap expansion
 };
+
+// Per-vertex role counts: rcnt[v * stride + q] = number of neighbours of v
+// in the compacted subgraph whose role set holds q (saturating at 65535);
+// used to choose the search order.
+template <typename M>
+void launch_role_counts(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
+                        const int32_t *c_col, const M *omega, int n0, uint16_t *rcnt);
 
 // Reverse entry of every compacted entry (the compacted subgraph is
 // symmetric): rows of the vertices in tasks.

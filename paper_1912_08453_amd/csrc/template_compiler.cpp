@@ -180,63 +180,25 @@ std::vector<Edge> bfs_spanning_tree(const std::set<Edge> &es) {
 }
 
 // Search plan over the substructure `sub` (edge list) pinned at qa (and qb).
-// Positions after the pinned ones: the vertex with the most substructure
-// edges to placed vertices, then the rarest background label, then the
-// lowest index (constraint optimisation: visit rare labels first).
-SearchPlan make_plan(const std::vector<Edge> &sub, const std::vector<int32_t> &labels,
-                     const std::vector<int64_t> &freq, int qa, int qb, uint64_t certify) {
+SearchPlan make_plan(const std::vector<Edge> &sub, const std::vector<int32_t> &labels, int qa,
+                     int qb, uint64_t certify) {
     SearchPlan P{};
-    uint64_t sadj[kMaxK] = {0};
     uint64_t vm = 0;
     for (auto &e : sub) {
-        sadj[e.first] |= 1ull << e.second;
-        sadj[e.second] |= 1ull << e.first;
+        P.adj[e.first] |= 1ull << e.second;
+        P.adj[e.second] |= 1ull << e.first;
         vm |= (1ull << e.first) | (1ull << e.second);
     }
     if (sub.empty()) vm = 1ull << qa;
-    auto lf = [&](int q) -> int64_t {
-        int L = labels[q];
-        return (L < (int)freq.size()) ? freq[L] : 0;
-    };
-    uint64_t placed = 0;
-    P.q[P.k++] = qa;
-    placed |= 1ull << qa;
-    P.npin = 1;
-    if (qb >= 0) {
-        P.q[P.k++] = qb;
-        placed |= 1ull << qb;
-        P.npin = 2;
-    }
-    while (placed != vm) {
-        int best = -1, best_links = -1;
-        for (int y = 0; y < kMaxK; ++y) {
-            if (!((vm >> y) & 1) || ((placed >> y) & 1)) continue;
-            int links = __builtin_popcountll(sadj[y] & placed);
-            if (links == 0) continue;
-            if (best < 0 || links > best_links ||
-                (links == best_links && (lf(y) < lf(best) || (lf(y) == lf(best) && y < best)))) {
-                best = y;
-                best_links = links;
-            }
-        }
-        if (best < 0) break;  // disconnected substructure (rejected earlier)
-        P.q[P.k++] = best;
-        placed |= 1ull << best;
-    }
-    for (int i = 0; i < P.k; ++i) {
-        P.back[i] = 0;
-        P.same[i] = 0;
-        P.nbr[i] = 0;
-        P.samel[i] = 0;
-        for (int j = 0; j < P.k; ++j) {
-            if (j == i) continue;
-            const bool adj = (sadj[P.q[i]] >> P.q[j]) & 1;
-            const bool same = labels[P.q[i]] == labels[P.q[j]];
-            if (adj) P.nbr[i] |= 1ull << j;
-            if (same) P.samel[i] |= 1ull << j;
-            if (j < i && adj) P.back[i] |= 1ull << j;
-            if (j < i && same) P.same[i] |= 1ull << j;
-        }
+    P.vmask = vm;
+    P.k = __builtin_popcountll(vm);
+    P.pin[0] = qa;
+    P.pin[1] = qb;
+    P.npin = qb >= 0 ? 2 : 1;
+    for (int q = 0; q < kMaxK; ++q) {
+        if (!((vm >> q) & 1)) continue;
+        for (int r = 0; r < kMaxK; ++r)
+            if (r != q && ((vm >> r) & 1) && labels[r] == labels[q]) P.samelab[q] |= 1ull << r;
     }
     P.certify = certify;
     return P;
@@ -421,30 +383,19 @@ std::string compile_template(int n0, int m0, const uint16_t *labels, const uint3
         for (int h = 0; h < n0; ++h) {
             if (!((c.heads >> h) & 1)) continue;
             c.plan_of_head[h] = (int)T.plans.size();
-            T.plans.push_back(make_plan(c.edges, T.labels, label_freq, h, -1, c.heads));
+            T.plans.push_back(make_plan(c.edges, T.labels, h, -1, c.heads));
         }
     }
     for (int q = 0; q < kMaxK; ++q) T.vertex_plan[q] = -1;
     for (int q = 0; q < n0; ++q) {
         T.vertex_plan[q] = (int)T.plans.size();
-        T.plans.push_back(make_plan(T.edges, T.labels, label_freq, q, -1, all));
+        T.plans.push_back(make_plan(T.edges, T.labels, q, -1, all));
     }
     for (auto &e : T.edges) {
         T.edge_plans.push_back((int)T.plans.size());
-        T.plans.push_back(make_plan(T.edges, T.labels, label_freq, e.first, e.second, all));
+        T.plans.push_back(make_plan(T.edges, T.labels, e.first, e.second, all));
         T.edge_plans.push_back((int)T.plans.size());
-        T.plans.push_back(make_plan(T.edges, T.labels, label_freq, e.second, e.first, all));
-    }
-    // witness edges of every plan as position pairs (used by full-template plans)
-    T.plan_edges.assign(T.plans.size() * (size_t)std::max(m0, 1), PlanEdge{0, 0});
-    for (size_t p = 0; p < T.plans.size(); ++p) {
-        int pos_of[kMaxK];
-        for (int i = 0; i < kMaxK; ++i) pos_of[i] = -1;
-        for (int i = 0; i < T.plans[p].k; ++i) pos_of[T.plans[p].q[i]] = i;
-        for (int i = 0; i < m0; ++i) {
-            T.plan_edges[p * m0 + i].pa = pos_of[T.edges[i].first];
-            T.plan_edges[p * m0 + i].pb = pos_of[T.edges[i].second];
-        }
+        T.plans.push_back(make_plan(T.edges, T.labels, e.second, e.first, all));
     }
     return "";
 }
