@@ -35,7 +35,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--graph-seed", type=int, default=22)
-    ap.add_argument("--template-seed", type=int, default=1)
+    ap.add_argument("--template-seed", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     args = ap.parse_args()
@@ -49,6 +51,19 @@ def main():
     import torch
     from paper_1912_08453_amd import inputs as I
     from paper_1912_08453_amd import pm
+
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        x.fill_(1)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                          "launches": 3}))
+        return
 
     t0 = time.time()
     rp, col = I.rmat_csr(args.scale, seed=args.graph_seed)
