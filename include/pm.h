@@ -101,6 +101,8 @@ typedef struct {
     double wave_ms_vq_neg;         /* failed vertex-rooted searches, and of   */
     double wave_ms_eq_pos;         /* successful and failed edge-rooted       */
     double wave_ms_eq_neg;         /* searches (exact step)                   */
+    double wave_ms_certify;        /* wavefront time certifying found matches
+                                      and their single-vertex swaps           */
     int64_t lcc_sweeps;            /* LCC sweeps run                          */
     int64_t constraints;           /* non-local constraints checked           */
     int64_t first_sweep_vertices;  /* active vertices in the first sweep      */

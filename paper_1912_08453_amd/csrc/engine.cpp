@@ -98,10 +98,9 @@ struct pm_ctx {
     std::vector<std::unique_ptr<CompiledTemplate>> templates;
     // scratch
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
-    DevBuf eu, ew, eidx, edge_plan_ids, crev, ccert, expdone, rcnt;
+    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expdone, rlcnt, rloff, rlpos, rlcol, rlscan;
     int grid_search = 2048;
     int expand = 1;
-    int use_counts = 1;
     int64_t wall_khz = 0;
 };
 
@@ -125,7 +124,7 @@ enum : int {
     C_NOUT = 8,
     C_QUERIES_U64 = 16,   // byte offset 64: unsigned long long
     C_ENTRIES_U64 = 18,   // byte offset 72: unsigned long long
-    C_TOTAL_BYTES = 256,      // bytes 128..191: query statistics [8]
+    C_TOTAL_BYTES = 256,      // bytes 128..207: query statistics [10]
 };
 
 struct Graph {
@@ -306,15 +305,16 @@ struct Pruner {
         a.plans = T.d_plans;
         a.tedges = T.d_tedges;
         a.m0 = T.m0;
-        a.rcnt = rcnt_dirty ? nullptr : c->rcnt.as<uint16_t>();
-        a.rcnt_stride = T.n0;
+        a.rl_off = c->rloff.as<int64_t>();
+        a.rl_col = c->rlcol.as<int32_t>();
+        a.rl_pos = c->rlpos.as<int32_t>();
+        a.n0 = T.n0;
         a.mode = mode;
         a.heads = heads;
         for (int i = 0; i < kMaxK; ++i) a.plan_of_head[i] = plan_of_head[i];
         a.edge_bits = edge_bits;
         a.task_counter = ctr + C_TASK;
         a.n_queries = queries;
-        a.c_rev = nullptr;
         a.c_cert = nullptr;
         a.exp_done = nullptr;
         a.qstats = nullptr;
@@ -323,17 +323,31 @@ struct Pruner {
     }
 
     // Role counts of the active vertices (search-order estimates).
-    bool rcnt_dirty = true;
-    void role_counts() {
-        c->rcnt.ensure(sizeof(uint16_t) * (size_t)std::max<int64_t>(c->n, 1) * (size_t)T.n0);
-        launch_role_counts<M>(s, A, nA, c_rp, c_col, om, T.n0, c->rcnt.as<uint16_t>());
-        rcnt_dirty = false;
+    // Role lists of the active vertices over the compacted subgraph, built
+    // from the current role sets (the snapshot a constraint reads).
+    int64_t rl_total = 0;
+    void role_lists() {
+        const int64_t nn = std::max<int64_t>(nA, 1) * T.n0;
+        c->rlcnt.ensure(sizeof(int64_t) * (size_t)(nn + 1));
+        c->rloff.ensure(sizeof(int64_t) * (size_t)(nn + 1));
+        c->rlpos.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c->n, 1));
+        const int64_t sl = scan_scratch_len(nn);
+        c->rlscan.ensure(sizeof(int64_t) * (size_t)sl);
+        launch_role_count<M>(s, A, nA, c_rp, c_col, om, T.n0, c->rlcnt.as<int64_t>(),
+                             c->rlpos.as<int32_t>());
+        launch_exclusive_scan(s, c->rlcnt.as<int64_t>(), c->rloff.as<int64_t>(), nA * T.n0,
+                              c->rlscan.as<int64_t>(), sl);
+        rl_total = 0;
+        d2h(s, &rl_total, c->rloff.as<int64_t>() + nA * T.n0, 1);
+        c->rlcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
+        launch_role_fill<M>(s, A, nA, c_rp, c_col, om, T.n0, c->rloff.as<int64_t>(),
+                            c->rlcol.as<int32_t>());
     }
 
     // One non-local constraint (snapshot semantics); returns vertices changed.
     int32_t nlcc(const Constraint &k) {
         Timer t(s);
-        if (c->use_counts) role_counts();
+        role_lists();
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         SearchArgs a = search_args(0, k.heads, k.plan_of_head, nullptr);
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
@@ -351,21 +365,17 @@ struct Pruner {
         // certified roles live in sat (cleared by every apply and at start)
         const uint64_t all = T.n0 == 64 ? ~0ull : ((1ull << T.n0) - 1ull);
         unsigned long long q0 = 0, q1 = 0;
-        c->crev.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
         const int64_t cwords = (c_m + 63) / 64;
         c->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
         c->expdone.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(n, 1));
-        int32_t *c_rev = c->crev.as<int32_t>();
         uint64_t *c_cert = c->ccert.as<uint64_t>();
-        launch_reverse_index(s, A, nA, c_rp, c_col, c_rev);
-        if (c->use_counts) role_counts();
+        role_lists();
         launch_fill_u64(s, c_cert, cwords, 0ull);
         launch_fill_u64(s, c->expdone.as<uint64_t>(), n, 0ull);
-        PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 8, s));
+        PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 10, s));
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
         SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
-        a.c_rev = c_rev;
         a.c_cert = c_cert;
         a.exp_done = c->expdone.as<uint64_t>();
         a.qstats = qstats;
@@ -381,7 +391,7 @@ struct Pruner {
         c->ew.ensure(sizeof(int32_t) * (size_t)cap);
         c->eidx.ensure(sizeof(int64_t) * (size_t)cap);
         PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
-        launch_edge_candidates<M>(s, A, nA, c_rp, c_col, c_rev, sat, T.lcc, c_cert,
+        launch_edge_candidates<M>(s, A, nA, c_rp, c_col, sat, T.lcc, c_cert,
                                   c->eu.as<int32_t>(), c->ew.as<int32_t>(),
                                   c->eidx.as<int64_t>(), ctr + C_NOUT, cap);
         int64_t ne = read_ctr(C_NOUT);
@@ -399,10 +409,10 @@ struct Pruner {
                                   a, c->grid_search);
             d2h(s, &q1, queries, 1);
         }
-        launch_edges_from_cert(s, A, nA, c_rp, c_off, c_rev, c->rp, c_cert, edge_out);
+        launch_edges_from_cert(s, A, nA, c_rp, c_off, c->rp, c_cert, edge_out);
         launch_widen<M>(s, n, sat, role_out);
-        unsigned long long qs[8];
-        d2h(s, qs, qstats, 8);
+        unsigned long long qs[10];
+        d2h(s, qs, qstats, 10);
         const double tick_ms = c->wall_khz > 0 ? 1.0 / (double)c->wall_khz : 0.0;
         st.vertex_queries += (int64_t)q0;
         st.edge_queries += (int64_t)q1;
@@ -414,6 +424,7 @@ struct Pruner {
         st.eq_neg += (int64_t)qs[5];
         st.wave_ms_eq_pos += (double)qs[6] * tick_ms;
         st.wave_ms_eq_neg += (double)qs[7] * tick_ms;
+        st.wave_ms_certify += (double)(qs[8] + qs[9]) * tick_ms;
         st.ms_exact += t.stop();
     }
 
@@ -578,8 +589,6 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
                 c->wall_khz = khz;
             const char *ex = getenv("PM_EXPAND");
             if (ex) c->expand = atoi(ex);
-            const char *uc = getenv("PM_ROLE_COUNTS");
-            if (uc) c->use_counts = atoi(uc);
         } catch (...) {
             delete c;
             throw;
@@ -596,7 +605,8 @@ int pm_destroy(pm_ctx *c) {
         for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->omega, &c->sat, &c->alist[0],
                           &c->alist[1], &c->bins, &c->counters, &c->hub, &c->cdeg, &c->crp,
                           &c->ccol, &c->coff, &c->segcnt, &c->scan_scratch, &c->eu, &c->ew,
-                          &c->eidx, &c->edge_plan_ids, &c->crev, &c->ccert, &c->expdone, &c->rcnt})
+                          &c->eidx, &c->edge_plan_ids, &c->ccert, &c->expdone, &c->rlcnt, &c->rloff, &c->rlpos, &c->rlcol,
+                          &c->rlscan})
             b->release();
         delete c;
     });
@@ -782,6 +792,7 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.wave_ms_vq_neg += st.wave_ms_vq_neg;
             total.wave_ms_eq_pos += st.wave_ms_eq_pos;
             total.wave_ms_eq_neg += st.wave_ms_eq_neg;
+            total.wave_ms_certify += st.wave_ms_certify;
         }
         PM_HIP(hipStreamSynchronize(c->stream));
         if (stats) *stats = total;

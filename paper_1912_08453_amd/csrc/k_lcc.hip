@@ -701,11 +701,26 @@ void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v) {
 
 __global__ void label_hist_kernel(int64_t n, const void *labels, int label_bytes,
                                   unsigned long long *hist, int64_t hist_len) {
+    // 8-bit labels: per-block histogram in LDS, one global atomic per bin
+    __shared__ unsigned int local[256];
+    const bool small = label_bytes == 1 && hist_len <= 256;
+    if (small) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) local[i] = 0;
+        __syncthreads();
+    }
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         int64_t L = label_bytes == 1 ? (int64_t)((const uint8_t *)labels)[v]
                                      : (int64_t)((const uint16_t *)labels)[v];
-        if (L < hist_len) atomicAdd(&hist[L], 1ull);
+        if (L < hist_len) {
+            if (small) atomicAdd(&local[L], 1u);
+            else atomicAdd(&hist[L], 1ull);
+        }
+    }
+    if (small) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 256; i += blockDim.x)
+            if (local[i]) atomicAdd(&hist[i], (unsigned long long)local[i]);
     }
 }
 

@@ -158,8 +158,10 @@ struct SearchArgs {
     const SearchPlan *plans;
     const int32_t *tedges;          // template edges (a, b) pairs
     int32_t m0;
-    const uint16_t *rcnt;           // [n][rcnt_stride]: neighbours holding each role
-    int32_t rcnt_stride;
+    const int64_t *rl_off;          // role lists: [tasks * n0 + 1] offsets into rl_col
+    const int32_t *rl_col;
+    const int32_t *rl_pos;          // list position (task index) of each listed vertex
+    int32_t n0;
     int32_t mode;
     uint64_t heads;
     int32_t plan_of_head[kMaxK];
@@ -167,32 +169,33 @@ struct SearchArgs {
     int32_t *task_counter;
     unsigned long long *n_queries;
     // exact step: certified entries of the compacted subgraph (bit k = entry
-    // k), reverse entry index, per-vertex expansion flags (bit t = oriented
-    // template edge t expanded from this vertex), query statistics
-    const int32_t *c_rev;
+    // k; both entries of an edge are set together), per-vertex expansion
+    // flags (bit q = pendant role q expanded from this vertex), query
+    // statistics
     uint64_t *c_cert;
     uint64_t *exp_done;
-    unsigned long long *qstats;     // [8]: vpos, vneg, vpos_t, vneg_t, epos, eneg, epos_t, eneg_t
+    unsigned long long *qstats;     // [10]: vpos, vneg, vpos_t, vneg_t, epos, eneg, epos_t,
+                                    // eneg_t, vcert_t, ecert_t (wall-clock ticks)
     int32_t expand;                 // run the single-vertex swap expansion
 };
 
-// Per-vertex role counts: rcnt[v * stride + q] = number of neighbours of v
-// in the compacted subgraph whose role set holds q (saturating at 65535);
-// used to choose the search order.
+// Role lists of the vertices in tasks over the compacted subgraph: pass 1
+// writes cnt[t * n0 + q] = neighbours of tasks[t] whose role set holds q and
+// pos_of[tasks[t]] = t; an exclusive scan of cnt gives rl_off; pass 2 writes
+// the sorted lists into rl_col.
 template <typename M>
-void launch_role_counts(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
-                        const int32_t *c_col, const M *omega, int n0, uint16_t *rcnt);
+void launch_role_count(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
+                       const int32_t *c_col, const M *omega, int n0, int64_t *cnt,
+                       int32_t *pos_of);
+template <typename M>
+void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
+                      const int32_t *c_col, const M *omega, int n0, const int64_t *rl_off,
+                      int32_t *rl_col);
 
-// Reverse entry of every compacted entry (the compacted subgraph is
-// symmetric): rows of the vertices in tasks.
-void launch_reverse_index(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                          const int64_t *c_rp, const int32_t *c_col, int32_t *c_rev);
-
-// Output edge bits from certified compacted entries: entry k of row a is
-// in the complete set iff k or its reverse is certified.
+// Output edge bits from certified compacted entries.
 void launch_edges_from_cert(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_off, const int32_t *c_rev,
-                            const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits);
+                            const int64_t *c_rp, const int32_t *c_off, const int64_t *rp,
+                            const uint64_t *c_cert, uint64_t *edge_bits);
 
 template <typename M>
 void launch_vertex_search(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,
@@ -207,10 +210,9 @@ void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega
 // with adjacent certified roles and no certified bit yet.
 template <typename M>
 void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_rev,
-                            const M *cert, const LccTable &tab, const uint64_t *c_cert,
-                            int32_t *eu, int32_t *ew, int64_t *e_idx, int32_t *n_out,
-                            int64_t cap);
+                            const int64_t *c_rp, const int32_t *c_col, const M *cert,
+                            const LccTable &tab, const uint64_t *c_cert, int32_t *eu, int32_t *ew,
+                            int64_t *e_idx, int32_t *n_out, int64_t cap);
 
 template <typename M>
 void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
