@@ -64,6 +64,8 @@ def _load():
     lib.orc_bruteforce.argtypes = [I64, P, P, P, I32, I32, P, P, P, P]
     lib.orc_active_edges.restype = I32
     lib.orc_active_edges.argtypes = [I64, P, P, P, I32, I32, P, P, P]
+    lib.orc_exact_subset.restype = I64
+    lib.orc_exact_subset.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64]
     lib.orc_num_threads.restype = I32
     lib.orc_set_threads.restype = None
     lib.orc_set_threads.argtypes = [I32]
@@ -144,6 +146,16 @@ def exact(g: _G, t: _T, omega: np.ndarray):
     if rc:
         raise ValueError("bad template")
     return role[:g.n], edge[:nwords(g.m)]
+
+
+def exact_subset(g: _G, t: _T, omega: np.ndarray, verts: np.ndarray) -> int:
+    """The exact step's searches for the given vertices only (timing samples)."""
+    vs = np.ascontiguousarray(verts, dtype=np.int32)
+    r = _load().orc_exact_subset(g.n, _p(g.row_ptr), _p(g.col), _p(omega), t.n0, t.m0,
+                                 _p(t.labels), _p(t.edges), _p(vs), vs.shape[0])
+    if r < 0:
+        raise ValueError("bad template")
+    return int(r)
 
 
 def active_edges(g: _G, t: _T, omega: np.ndarray) -> np.ndarray:

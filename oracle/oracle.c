@@ -455,3 +455,53 @@ int orc_active_edges(int64_t n, const int64_t *row_ptr, const int32_t *col,
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
 void orc_set_threads(int t) { if (t > 0) omp_set_num_threads(t); }
+
+/* ---- exact step on a vertex subset (timing samples only) ---------------- */
+/* Runs, for the given vertices only, the same searches orc_exact runs for
+   them: one full-template search per candidate role, and one per candidate
+   entry u->w and oriented template edge (w's candidate roles stand in for
+   its exact roles).  Returns the number of searches run. */
+int64_t orc_exact_subset(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                         const uint64_t *omega, int n0, int m0, const int32_t *tl,
+                         const int32_t *te, const int32_t *verts, int64_t nverts) {
+    tmpl_t T;
+    if (load_tmpl(&T, n0, m0, tl, te)) return -1;
+    graph_t G = {n, row_ptr, col, NULL};
+    if (n0 == 1) return 0;
+    uint64_t vmask = (n0 == 64) ? ~0ull : ((1ull << n0) - 1ull);
+    plan_t vplan[64];
+    for (int q = 0; q < n0; ++q) make_plan(&vplan[q], vmask, T.adj, q, -1);
+    plan_t *eplan = (plan_t *)malloc(sizeof(plan_t) * (size_t)(2 * m0 > 0 ? 2 * m0 : 1));
+    for (int i = 0; i < m0; ++i) {
+        make_plan(&eplan[2 * i], vmask, T.adj, T.ea[i], T.eb[i]);
+        make_plan(&eplan[2 * i + 1], vmask, T.adj, T.eb[i], T.ea[i]);
+    }
+    int64_t searches = 0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(+:searches)
+    for (int64_t i = 0; i < nverts; ++i) {
+        const int32_t v = verts[i];
+        uint64_t r = 0;
+        for (int q = 0; q < n0; ++q) {
+            if (!((omega[v] >> q) & 1)) continue;
+            int32_t img[64];
+            img[0] = v;
+            ++searches;
+            if (extend(&G, omega, &vplan[q], 1, img)) r |= 1ull << q;
+        }
+        if (!r) continue;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const int32_t w = col[e];
+            if (!omega[w]) continue;
+            for (int k = 0; k < 2 * m0; ++k) {
+                const plan_t *P = &eplan[k];
+                if (!((r >> P->q[0]) & 1) || !((omega[w] >> P->q[1]) & 1)) continue;
+                int32_t img[64];
+                img[0] = v; img[1] = w;
+                ++searches;
+                if (extend(&G, omega, P, 2, img)) break;
+            }
+        }
+    }
+    free(eplan);
+    return searches;
+}

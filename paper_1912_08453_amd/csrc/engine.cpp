@@ -98,7 +98,8 @@ struct pm_ctx {
     std::vector<std::unique_ptr<CompiledTemplate>> templates;
     // scratch
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
-    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expdone, rlcnt, rloff, rlpos, rlcol, rlscan;
+    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expdone, rlcnt, rloff, rlpos, rlcol, rlscan,
+        actbits;
     int grid_search = 2048;
     int expand = 1;
     int64_t wall_khz = 0;
@@ -435,7 +436,10 @@ struct Pruner {
         launch_fill_u64(s, edge_out, (m + 63) / 64, 0ull);
         {
             Timer t(s);
-            launch_init_roles<M>(s, n, c->labels, c->label_bytes, T.d_init_lut, T.init_lut_len, om);
+            c->actbits.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>((n + 63) / 64, 1));
+            wl.act_bits = c->actbits.as<uint64_t>();
+            launch_init_roles<M>(s, n, c->labels, c->label_bytes, T.d_init_lut, T.init_lut_len, om,
+                                 c->actbits.as<uint64_t>());
             PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
             collect(true);
             st.ms_init += t.stop();
@@ -606,7 +610,7 @@ int pm_destroy(pm_ctx *c) {
                           &c->alist[1], &c->bins, &c->counters, &c->hub, &c->cdeg, &c->crp,
                           &c->ccol, &c->coff, &c->segcnt, &c->scan_scratch, &c->eu, &c->ew,
                           &c->eidx, &c->edge_plan_ids, &c->ccert, &c->expdone, &c->rlcnt, &c->rloff, &c->rlpos, &c->rlcol,
-                          &c->rlscan})
+                          &c->rlscan, &c->actbits})
             b->release();
         delete c;
     });

@@ -50,10 +50,24 @@ __device__ __forceinline__ uint64_t evaluate(uint64_t w, uint64_t cover, const i
 // masks are gathered, so each wavefront keeps several loads in flight.
 constexpr int kUnroll = 8;
 
-template <typename M, bool CNT>
+// With FILT, a bitmap of the vertices whose initial role set is not empty
+// (512 KB at 2^22 vertices, resident in L2) is tested first and only those
+// role masks are gathered: in the first sweep most neighbours are inactive.
+template <bool FILT, typename M>
+__device__ __forceinline__ uint64_t gather_roles(const M *omega, const uint64_t *bits, int32_t c) {
+    if constexpr (FILT) {
+        const uint64_t w = bits[c >> 6];
+        return ((w >> (c & 63)) & 1ull) ? (uint64_t)omega[c] : 0ull;
+    } else {
+        return (uint64_t)omega[c];
+    }
+}
+
+template <typename M, bool CNT, bool FILT = false>
 __device__ __forceinline__ void accumulate(const int32_t *__restrict__ col, const M *omega,
                                            int64_t k0, int64_t e, int stride,
-                                           const LccTable &tab, uint64_t &cover, int *cnt) {
+                                           const LccTable &tab, uint64_t &cover, int *cnt,
+                                           const uint64_t *bits = nullptr) {
     int64_t k = k0;
     for (; k + (int64_t)(kUnroll - 1) * stride < e; k += (int64_t)kUnroll * stride) {
         int32_t c[kUnroll];
@@ -61,7 +75,7 @@ __device__ __forceinline__ void accumulate(const int32_t *__restrict__ col, cons
         for (int u = 0; u < kUnroll; ++u) c[u] = __builtin_nontemporal_load(col + k + (int64_t)u * stride);
         uint64_t x[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) x[u] = (uint64_t)omega[c[u]];
+        for (int u = 0; u < kUnroll; ++u) x[u] = gather_roles<FILT>(omega, bits, c[u]);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             cover |= x[u];
@@ -73,7 +87,7 @@ __device__ __forceinline__ void accumulate(const int32_t *__restrict__ col, cons
         }
     }
     for (; k < e; k += stride) {
-        const uint64_t x = (uint64_t)omega[__builtin_nontemporal_load(col + k)];
+        const uint64_t x = gather_roles<FILT>(omega, bits, __builtin_nontemporal_load(col + k));
         cover |= x;
         if constexpr (CNT) {
 #pragma unroll
@@ -88,21 +102,28 @@ __device__ __forceinline__ void accumulate(const int32_t *__restrict__ col, cons
 template <typename M>
 __global__ __launch_bounds__(kBlock) void init_roles_kernel(int64_t n, const void *labels,
                                                             int label_bytes, const uint64_t *lut,
-                                                            int64_t lut_len, M *omega) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int64_t L = label_bytes == 1 ? (int64_t)((const uint8_t *)labels)[v]
-                                 : (int64_t)((const uint16_t *)labels)[v];
-    omega[v] = (M)(L < lut_len ? lut[L] : 0ull);
+                                                            int64_t lut_len, M *omega,
+                                                            uint64_t *bits) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t w = 0;
+    if (v < n) {
+        const int64_t L = label_bytes == 1 ? (int64_t)((const uint8_t *)labels)[v]
+                                           : (int64_t)((const uint16_t *)labels)[v];
+        w = L < lut_len ? lut[L] : 0ull;
+        omega[v] = (M)w;
+    }
+    // a wavefront covers 64 consecutive vertices: one bitmap word
+    const uint64_t m = ballot64(w != 0ull);
+    if (bits && lane_id() == 0 && v < n) bits[v >> 6] = m;
 }
 
 template <typename M>
 void launch_init_roles(hipStream_t s, int64_t n, const void *labels, int label_bytes,
-                       const uint64_t *lut, int64_t lut_len, M *omega) {
+                       const uint64_t *lut, int64_t lut_len, M *omega, uint64_t *bits) {
     if (n <= 0) return;
     int64_t grid = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(init_roles_kernel<M>, dim3((unsigned)grid), dim3(kBlock), 0, s, n, labels,
-                       label_bytes, lut, lut_len, omega);
+                       label_bytes, lut, lut_len, omega, bits);
 }
 
 // ---------------------------------------------------------------- binning
@@ -228,11 +249,12 @@ void launch_hub_segments(hipStream_t s, const int64_t *rp, Worklists &wl, int64_
 // wavefront per segment of kHubSegment entries for the hub bin, whose
 // partial coverage and counts are combined with atomics; the last segment
 // of a vertex (ticket) applies the rule.
-template <typename M, int G, bool CNT>
+template <typename M, int G, bool CNT, bool FILT>
 __device__ __forceinline__ void lcc_group_body(int64_t local_block, const int64_t *__restrict__ rp,
                                                const int32_t *__restrict__ col, M *omega,
                                                const int32_t *__restrict__ list, int64_t count,
-                                               const LccTable &tab, int32_t *changed) {
+                                               const LccTable &tab, int32_t *changed,
+                                               const uint64_t *bits) {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
     const int64_t idx = (local_block * blockDim.x + threadIdx.x) / G;
@@ -248,7 +270,7 @@ __device__ __forceinline__ void lcc_group_body(int64_t local_block, const int64_
     int cnt[CNT ? kMaxCount : 1];
 #pragma unroll
     for (int c = 0; c < (CNT ? kMaxCount : 1); ++c) cnt[c] = 0;
-    accumulate<M, CNT>(col, omega, s + sl, e, G, tab, cover, cnt);
+    accumulate<M, CNT, FILT>(col, omega, s + sl, e, G, tab, cover, cnt, bits);
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) {
         cover |= shfl_xor_u64(cover, off, G);
@@ -269,11 +291,12 @@ __device__ __forceinline__ void lcc_group_body(int64_t local_block, const int64_
     if (ballot64(ch) && lane == 0) atomicAdd(changed, 1);
 }
 
-template <typename M, bool CNT>
+template <typename M, bool CNT, bool FILT>
 __device__ __forceinline__ void lcc_hub_body(int64_t local_block, const int64_t *__restrict__ rp,
                                              const int32_t *__restrict__ col, M *omega,
                                              const Worklists &wl, int64_t n_seg,
-                                             const LccTable &tab, int32_t *changed) {
+                                             const LccTable &tab, int32_t *changed,
+                                             const uint64_t *bits) {
     const int lane = lane_id();
     const int64_t seg = (local_block * blockDim.x + threadIdx.x) / kWave;
     if (seg >= n_seg) return;
@@ -284,7 +307,7 @@ __device__ __forceinline__ void lcc_hub_body(int64_t local_block, const int64_t 
     int cnt[CNT ? kMaxCount : 1];
 #pragma unroll
     for (int c = 0; c < (CNT ? kMaxCount : 1); ++c) cnt[c] = 0;
-    accumulate<M, CNT>(col, omega, b + lane, e, kWave, tab, cover, cnt);
+    accumulate<M, CNT, FILT>(col, omega, b + lane, e, kWave, tab, cover, cnt, bits);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         cover |= shfl_xor_u64(cover, off, 64);
@@ -350,18 +373,21 @@ template <typename M, bool CNT, bool FULL>
 __global__ __launch_bounds__(kBlock) void lcc_sweep_kernel(const int64_t *__restrict__ rp,
                                                            const int32_t *__restrict__ col,
                                                            M *omega, Worklists wl, SweepGrid sg,
-                                                           LccTable tab, int32_t *changed) {
+                                                           LccTable tab, int32_t *changed,
+                                                           const uint64_t *bits) {
     const int64_t b = blockIdx.x;
     if (b < sg.start[1])
-        lcc_group_body<M, 4, CNT>(b, rp, col, omega, wl.list[0], sg.count[0], tab, changed);
+        lcc_group_body<M, 4, CNT, FULL>(b, rp, col, omega, wl.list[0], sg.count[0], tab, changed,
+                                        bits);
     else if (b < sg.start[2])
-        lcc_group_body<M, 16, CNT>(b - sg.start[1], rp, col, omega, wl.list[1], sg.count[1], tab,
-                                   changed);
+        lcc_group_body<M, 16, CNT, FULL>(b - sg.start[1], rp, col, omega, wl.list[1], sg.count[1],
+                                         tab, changed, bits);
     else if (b < sg.start[3])
-        lcc_group_body<M, 64, CNT>(b - sg.start[2], rp, col, omega, wl.list[2], sg.count[2], tab,
-                                   changed);
+        lcc_group_body<M, 64, CNT, FULL>(b - sg.start[2], rp, col, omega, wl.list[2], sg.count[2],
+                                         tab, changed, bits);
     else
-        lcc_hub_body<M, CNT>(b - sg.start[3], rp, col, omega, wl, sg.n_seg, tab, changed);
+        lcc_hub_body<M, CNT, FULL>(b - sg.start[3], rp, col, omega, wl, sg.n_seg, tab, changed,
+                                   bits);
 }
 
 template <typename M, bool CNT>
@@ -372,10 +398,10 @@ static void sweep_impl(hipStream_t s, const int64_t *rp, const int32_t *col, M *
     if (sg.start[4] == 0) return;
     if (full)
         hipLaunchKernelGGL((lcc_sweep_kernel<M, CNT, true>), dim3((unsigned)sg.start[4]),
-                           dim3(kBlock), 0, s, rp, col, omega, wl, sg, tab, changed);
+                           dim3(kBlock), 0, s, rp, col, omega, wl, sg, tab, changed, wl.act_bits);
     else
         hipLaunchKernelGGL((lcc_sweep_kernel<M, CNT, false>), dim3((unsigned)sg.start[4]),
-                           dim3(kBlock), 0, s, rp, col, omega, wl, sg, tab, changed);
+                           dim3(kBlock), 0, s, rp, col, omega, wl, sg, tab, changed, nullptr);
 }
 
 template <typename M>
@@ -750,7 +776,7 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
 
 #define PM_INSTANTIATE_LCC(M)                                                                     \
     template void launch_init_roles<M>(hipStream_t, int64_t, const void *, int, const uint64_t *, \
-                                       int64_t, M *);                                             \
+                                       int64_t, M *, uint64_t *);                                 \
     template void launch_bin<M>(hipStream_t, const int32_t *, int64_t, const int64_t *,            \
                                 const M *, Worklists &);                                          \
     template void launch_lcc_sweep<M>(hipStream_t, const int64_t *, const int32_t *, M *,          \

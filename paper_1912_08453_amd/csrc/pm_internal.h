@@ -97,14 +97,17 @@ struct Worklists {
     int32_t *hub_ticket;            // [n_hubs]
     int32_t *n_seg;                 // device scalar
     unsigned long long *entries;    // device scalar: CSR entries of binned vertices
+    const uint64_t *act_bits;       // bit v: initial role set of v not empty
     int64_t capacity;               // per list
     int64_t hub_capacity;           // hub slots
     int64_t seg_capacity;
 };
 
+// omega0(v) from the label LUT; bits (ceil(n/64) words, may be null)
+// receives the bitmap of vertices with a non-empty initial role set.
 template <typename M>
 void launch_init_roles(hipStream_t s, int64_t n, const void *labels, int label_bytes,
-                       const uint64_t *lut, int64_t lut_len, M *omega);
+                       const uint64_t *lut, int64_t lut_len, M *omega, uint64_t *bits);
 
 // Active list: vertices of `in` (or 0..n_in-1 when in == nullptr) whose role
 // set is not empty, appended to out via *counter (zeroed by the caller).
