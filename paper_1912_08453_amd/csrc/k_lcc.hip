@@ -53,29 +53,44 @@ constexpr int kUnroll = 8;
 // With FILT, a bitmap of the vertices whose initial role set is not empty
 // (512 KB at 2^22 vertices, resident in L2) is tested first and only those
 // role masks are gathered: in the first sweep most neighbours are inactive.
-template <bool FILT, typename M>
-__device__ __forceinline__ uint64_t gather_roles(const M *omega, const uint64_t *bits, int32_t c) {
-    if constexpr (FILT) {
-        const uint64_t w = bits[c >> 6];
-        return ((w >> (c & 63)) & 1ull) ? (uint64_t)omega[c] : 0ull;
-    } else {
-        return (uint64_t)omega[c];
-    }
-}
-
 template <typename M, bool CNT, bool FILT = false>
 __device__ __forceinline__ void accumulate(const int32_t *__restrict__ col, const M *omega,
                                            int64_t k0, int64_t e, int stride,
                                            const LccTable &tab, uint64_t &cover, int *cnt,
                                            const uint64_t *bits = nullptr) {
-    int64_t k = k0;
-    for (; k + (int64_t)(kUnroll - 1) * stride < e; k += (int64_t)kUnroll * stride) {
+    // Blocks of kUnroll entries; the last block is predicated (indices
+    // clamped to the last entry, results of out-of-range slots zeroed), so
+    // every load of a block is issued before the first wait.
+    for (int64_t k = k0; k < e; k += (int64_t)kUnroll * stride) {
         int32_t c[kUnroll];
+        bool in[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) c[u] = __builtin_nontemporal_load(col + k + (int64_t)u * stride);
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t kk = k + (int64_t)u * stride;
+            in[u] = kk < e;
+            c[u] = __builtin_nontemporal_load(col + (in[u] ? kk : e - 1));
+        }
         uint64_t x[kUnroll];
+        if constexpr (FILT) {
+            // all bitmap words first, then all role gathers (inactive
+            // neighbours read vertex 0's mask, a shared cached line, and
+            // are zeroed): no load waits on a branch
+            uint64_t wd[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) x[u] = gather_roles<FILT>(omega, bits, c[u]);
+            for (int u = 0; u < kUnroll; ++u) wd[u] = bits[c[u] >> 6];
+            bool act[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) act[u] = in[u] && ((wd[u] >> (c[u] & 63)) & 1ull);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) x[u] = (uint64_t)omega[act[u] ? c[u] : 0];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) x[u] = act[u] ? x[u] : 0ull;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) x[u] = (uint64_t)omega[c[u]];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) x[u] = in[u] ? x[u] : 0ull;
+        }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             cover |= x[u];
@@ -84,15 +99,6 @@ __device__ __forceinline__ void accumulate(const int32_t *__restrict__ col, cons
                 for (int q = 0; q < kMaxCount; ++q)
                     if (q < tab.ncount) cnt[q] += (x[u] & tab.cmask[q]) != 0ull;
             }
-        }
-    }
-    for (; k < e; k += stride) {
-        const uint64_t x = gather_roles<FILT>(omega, bits, __builtin_nontemporal_load(col + k));
-        cover |= x;
-        if constexpr (CNT) {
-#pragma unroll
-            for (int q = 0; q < kMaxCount; ++q)
-                if (q < tab.ncount) cnt[q] += (x & tab.cmask[q]) != 0ull;
         }
     }
 }

@@ -313,13 +313,16 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             }
         }
         const int32_t ys = read_lane32(img_r, js);
-        if (__popcll(nb) == 1) {
+        if (__popcll(nb) == 1 || a.expand == 2) {
             // a pendant vertex depends (up to identity checks) only on its
-            // neighbour's image: expand it once per (vertex, role)
+            // neighbour's image: expand it once per (vertex, role pair).
+            // With expand == 2 every vertex is expanded once per (scanned
+            // vertex, role pair), trading missed swaps for edge queries.
+            const int key = (js * a.n0 + q) & 63;
             unsigned long long old = 0;
-            if (lane == 0) old = atomicOr((unsigned long long *)&a.exp_done[ys], 1ull << q);
+            if (lane == 0) old = atomicOr((unsigned long long *)&a.exp_done[ys], 1ull << key);
             old = __shfl(old, 0);
-            if ((old >> q) & 1ull) continue;
+            if ((old >> key) & 1ull) continue;
         }
         const uint64_t others = nb & ~(1ull << js);
         const uint64_t same = P->samelab[q];
