@@ -153,6 +153,9 @@ def main():
         "counts": counts,
         "search_wave_ms": search,
         "roofline": roofline,
+        "dominant_phase": {"phase": "exact step (edge_search_kernel, vertex_search_kernel)",
+                           "share_of_step": round(avg("ms_exact") / max(avg("ms_total"), 1e-9), 4),
+                           "bound": "search latency / random gathers (no roofline claim)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
