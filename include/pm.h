@@ -83,7 +83,10 @@ typedef struct {
                                       fixpoint); outputs are then omega and
                                       the edge state it implies, without the
                                       final search                            */
-    int32_t reserved[7];
+    int32_t batch_streams;         /* count > 1: prune up to this many
+                                      templates concurrently, each on its own
+                                      stream and scratch (0/1: one at a time)  */
+    int32_t reserved[6];
 } pm_options;
 
 /* Per-call statistics (valid when pm_prune returns PM_OK). */

@@ -6,12 +6,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pm.h"
@@ -77,6 +79,26 @@ struct Timer {
     }
 };
 
+// Device scratch of one pruning worker (one template at a time) and the
+// stream its kernels run on.
+struct Scratch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
+    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expdone, rlcnt, rloff, rlpos, rlcol, rlscan,
+        actbits;
+    void release() {
+        for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
+                          &ccol, &coff, &segcnt, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
+                          &ccert, &expdone, &rlcnt, &rloff, &rlpos, &rlcol, &rlscan, &actbits})
+            b->release();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+        own_stream = false;
+    }
+    ~Scratch() { release(); }
+};
+
 }  // namespace pm
 
 using namespace pm;
@@ -96,10 +118,8 @@ struct pm_ctx {
     int64_t hub_cap = 0, seg_cap = 0;
     // templates
     std::vector<std::unique_ptr<CompiledTemplate>> templates;
-    // scratch
-    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
-    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expdone, rlcnt, rloff, rlpos, rlcol, rlscan,
-        actbits;
+    // per-worker scratch; worker 0 runs on the context stream
+    std::vector<std::unique_ptr<pm::Scratch>> scratch;
     int grid_search = 2048;
     int expand = 1;
     int64_t wall_khz = 0;
@@ -136,6 +156,7 @@ struct Graph {
 template <typename M>
 struct Pruner {
     pm_ctx *c;
+    Scratch *w;
     const CompiledTemplate &T;
     hipStream_t s;
     M *om;
@@ -156,30 +177,31 @@ struct Pruner {
     int64_t c_m = 0;
     pm_stats st{};
 
-    Pruner(pm_ctx *ctx, const CompiledTemplate &t) : c(ctx), T(t), s(ctx->stream) {
+    Pruner(pm_ctx *ctx, Scratch *scr, const CompiledTemplate &t)
+        : c(ctx), w(scr), T(t), s(scr->stream) {
         const int64_t n = c->n;
-        c->omega.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
-        c->sat.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
-        c->alist[0].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
-        c->alist[1].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
-        c->bins.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1) * kNumBins);
-        c->counters.ensure(C_TOTAL_BYTES);
+        w->omega.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
+        w->sat.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
+        w->alist[0].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+        w->alist[1].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+        w->bins.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1) * kNumBins);
+        w->counters.ensure(C_TOTAL_BYTES);
         const int64_t hubs = std::max<int64_t>(c->hub_cap, 1), segs = std::max<int64_t>(c->seg_cap, 1);
         size_t hub_bytes = (size_t)segs * (4 + 8 + 8 + 4) + (size_t)hubs * (4 + 4 + 8 + 4 * kMaxCount + 4);
-        c->hub.ensure(hub_bytes + 256);
-        c->segcnt.ensure(sizeof(int64_t) * (size_t)segs);
-        om = c->omega.as<M>();
-        sat = c->sat.as<M>();
-        A = c->alist[0].as<int32_t>();
-        Aalt = c->alist[1].as<int32_t>();
-        ctr = c->counters.as<int32_t>();
-        queries = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 64);
-        qstats = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 128);
-        for (int b = 0; b < kNumBins; ++b) wl.list[b] = c->bins.as<int32_t>() + (size_t)b * n;
+        w->hub.ensure(hub_bytes + 256);
+        w->segcnt.ensure(sizeof(int64_t) * (size_t)segs);
+        om = w->omega.as<M>();
+        sat = w->sat.as<M>();
+        A = w->alist[0].as<int32_t>();
+        Aalt = w->alist[1].as<int32_t>();
+        ctr = w->counters.as<int32_t>();
+        queries = reinterpret_cast<unsigned long long *>(w->counters.as<char>() + 64);
+        qstats = reinterpret_cast<unsigned long long *>(w->counters.as<char>() + 128);
+        for (int b = 0; b < kNumBins; ++b) wl.list[b] = w->bins.as<int32_t>() + (size_t)b * n;
         wl.count = ctr + C_BINS;
-        wl.entries = reinterpret_cast<unsigned long long *>(c->counters.as<char>() + 72);
+        wl.entries = reinterpret_cast<unsigned long long *>(w->counters.as<char>() + 72);
         wl.n_seg = ctr + C_NSEG;
-        char *h = c->hub.as<char>();
+        char *h = w->hub.as<char>();
         wl.hub_seg_begin = reinterpret_cast<int64_t *>(h); h += 8 * (size_t)segs;
         wl.hub_seg_end = reinterpret_cast<int64_t *>(h); h += 8 * (size_t)segs;
         wl.hub_cover = reinterpret_cast<uint64_t *>(h); h += 8 * (size_t)hubs;
@@ -274,23 +296,23 @@ struct Pruner {
         const int64_t n = c->n;
         Graph full{c->rp, c->col};
         bin(full);
-        c->cdeg.ensure(sizeof(int64_t) * (size_t)(n + 1));
-        c->crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
-        int64_t *deg = c->cdeg.as<int64_t>();
+        w->cdeg.ensure(sizeof(int64_t) * (size_t)(n + 1));
+        w->crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
+        int64_t *deg = w->cdeg.as<int64_t>();
         PM_HIP(hipMemsetAsync(deg, 0, sizeof(int64_t) * (size_t)(n + 1), s));
         launch_compact_count<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, deg,
-                                c->segcnt.as<int64_t>());
+                                w->segcnt.as<int64_t>());
         int64_t sl = scan_scratch_len(n);
-        c->scan_scratch.ensure(sizeof(int64_t) * (size_t)sl);
-        c_rp = c->crp.as<int64_t>();
-        launch_exclusive_scan(s, deg, c_rp, n, c->scan_scratch.as<int64_t>(), sl);
+        w->scan_scratch.ensure(sizeof(int64_t) * (size_t)sl);
+        c_rp = w->crp.as<int64_t>();
+        launch_exclusive_scan(s, deg, c_rp, n, w->scan_scratch.as<int64_t>(), sl);
         d2h(s, &c_m, c_rp + n, 1);
-        c->ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
-        c->coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
-        c_col = c->ccol.as<int32_t>();
-        c_off = c->coff.as<int32_t>();
+        w->ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
+        w->coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
+        c_col = w->ccol.as<int32_t>();
+        c_off = w->coff.as<int32_t>();
         launch_compact_fill<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, c_rp,
-                               c->segcnt.as<int64_t>(), c_col, c_off);
+                               w->segcnt.as<int64_t>(), c_col, c_off);
         st.candidate_entries = c_m;
         st.ms_compact += t.stop();
     }
@@ -306,9 +328,9 @@ struct Pruner {
         a.plans = T.d_plans;
         a.tedges = T.d_tedges;
         a.m0 = T.m0;
-        a.rl_off = c->rloff.as<int64_t>();
-        a.rl_col = c->rlcol.as<int32_t>();
-        a.rl_pos = c->rlpos.as<int32_t>();
+        a.rl_off = w->rloff.as<int64_t>();
+        a.rl_col = w->rlcol.as<int32_t>();
+        a.rl_pos = w->rlpos.as<int32_t>();
         a.n0 = T.n0;
         a.mode = mode;
         a.heads = heads;
@@ -329,20 +351,20 @@ struct Pruner {
     int64_t rl_total = 0;
     void role_lists() {
         const int64_t nn = std::max<int64_t>(nA, 1) * T.n0;
-        c->rlcnt.ensure(sizeof(int64_t) * (size_t)(nn + 1));
-        c->rloff.ensure(sizeof(int64_t) * (size_t)(nn + 1));
-        c->rlpos.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c->n, 1));
+        w->rlcnt.ensure(sizeof(int64_t) * (size_t)(nn + 1));
+        w->rloff.ensure(sizeof(int64_t) * (size_t)(nn + 1));
+        w->rlpos.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c->n, 1));
         const int64_t sl = scan_scratch_len(nn);
-        c->rlscan.ensure(sizeof(int64_t) * (size_t)sl);
-        launch_role_count<M>(s, A, nA, c_rp, c_col, om, T.n0, c->rlcnt.as<int64_t>(),
-                             c->rlpos.as<int32_t>());
-        launch_exclusive_scan(s, c->rlcnt.as<int64_t>(), c->rloff.as<int64_t>(), nA * T.n0,
-                              c->rlscan.as<int64_t>(), sl);
+        w->rlscan.ensure(sizeof(int64_t) * (size_t)sl);
+        launch_role_count<M>(s, A, nA, c_rp, c_col, om, T.n0, w->rlcnt.as<int64_t>(),
+                             w->rlpos.as<int32_t>());
+        launch_exclusive_scan(s, w->rlcnt.as<int64_t>(), w->rloff.as<int64_t>(), nA * T.n0,
+                              w->rlscan.as<int64_t>(), sl);
         rl_total = 0;
-        d2h(s, &rl_total, c->rloff.as<int64_t>() + nA * T.n0, 1);
-        c->rlcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
-        launch_role_fill<M>(s, A, nA, c_rp, c_col, om, T.n0, c->rloff.as<int64_t>(),
-                            c->rlcol.as<int32_t>());
+        d2h(s, &rl_total, w->rloff.as<int64_t>() + nA * T.n0, 1);
+        w->rlcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
+        launch_role_fill<M>(s, A, nA, c_rp, c_col, om, T.n0, w->rloff.as<int64_t>(),
+                            w->rlcol.as<int32_t>());
     }
 
     // One non-local constraint (snapshot semantics); returns vertices changed.
@@ -367,18 +389,18 @@ struct Pruner {
         const uint64_t all = T.n0 == 64 ? ~0ull : ((1ull << T.n0) - 1ull);
         unsigned long long q0 = 0, q1 = 0;
         const int64_t cwords = (c_m + 63) / 64;
-        c->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
-        c->expdone.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(n, 1));
-        uint64_t *c_cert = c->ccert.as<uint64_t>();
+        w->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
+        w->expdone.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(n, 1));
+        uint64_t *c_cert = w->ccert.as<uint64_t>();
         role_lists();
         launch_fill_u64(s, c_cert, cwords, 0ull);
-        launch_fill_u64(s, c->expdone.as<uint64_t>(), n, 0ull);
+        launch_fill_u64(s, w->expdone.as<uint64_t>(), n, 0ull);
         PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 10, s));
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
         SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
         a.c_cert = c_cert;
-        a.exp_done = c->expdone.as<uint64_t>();
+        a.exp_done = w->expdone.as<uint64_t>();
         a.qstats = qstats;
         a.expand = c->expand;
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
@@ -388,25 +410,25 @@ struct Pruner {
         collect(false);
         std::swap(om, sat);
         const int64_t cap = c_m / 2 + 1;
-        c->eu.ensure(sizeof(int32_t) * (size_t)cap);
-        c->ew.ensure(sizeof(int32_t) * (size_t)cap);
-        c->eidx.ensure(sizeof(int64_t) * (size_t)cap);
+        w->eu.ensure(sizeof(int32_t) * (size_t)cap);
+        w->ew.ensure(sizeof(int32_t) * (size_t)cap);
+        w->eidx.ensure(sizeof(int64_t) * (size_t)cap);
         PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
         launch_edge_candidates<M>(s, A, nA, c_rp, c_col, sat, T.lcc, c_cert,
-                                  c->eu.as<int32_t>(), c->ew.as<int32_t>(),
-                                  c->eidx.as<int64_t>(), ctr + C_NOUT, cap);
+                                  w->eu.as<int32_t>(), w->ew.as<int32_t>(),
+                                  w->eidx.as<int64_t>(), ctr + C_NOUT, cap);
         int64_t ne = read_ctr(C_NOUT);
         if (ne > cap) throw Error(PM_ERR_CAPACITY, "edge candidate capacity exceeded");
         st.edge_candidates = ne;
         if (ne > 0) {
-            c->edge_plan_ids.ensure(sizeof(int32_t) * std::max<size_t>(T.edge_plans.size(), 1));
-            PM_HIP(hipMemcpyAsync(c->edge_plan_ids.p, T.edge_plans.data(),
+            w->edge_plan_ids.ensure(sizeof(int32_t) * std::max<size_t>(T.edge_plans.size(), 1));
+            PM_HIP(hipMemcpyAsync(w->edge_plan_ids.p, T.edge_plans.data(),
                                   sizeof(int32_t) * T.edge_plans.size(), hipMemcpyHostToDevice, s));
             PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
             PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
-            launch_edge_search<M>(s, c->eu.as<int32_t>(), c->ew.as<int32_t>(),
-                                  c->eidx.as<int64_t>(), ne, sat, sat,
-                                  c->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
+            launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
+                                  w->eidx.as<int64_t>(), ne, sat, sat,
+                                  w->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
                                   a, c->grid_search);
             d2h(s, &q1, queries, 1);
         }
@@ -436,10 +458,10 @@ struct Pruner {
         launch_fill_u64(s, edge_out, (m + 63) / 64, 0ull);
         {
             Timer t(s);
-            c->actbits.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>((n + 63) / 64, 1));
-            wl.act_bits = c->actbits.as<uint64_t>();
+            w->actbits.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>((n + 63) / 64, 1));
+            wl.act_bits = w->actbits.as<uint64_t>();
             launch_init_roles<M>(s, n, c->labels, c->label_bytes, T.d_init_lut, T.init_lut_len, om,
-                                 c->actbits.as<uint64_t>());
+                                 w->actbits.as<uint64_t>());
             PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
             collect(true);
             st.ms_init += t.stop();
@@ -606,12 +628,8 @@ int pm_destroy(pm_ctx *c) {
         if (!c) return;
         (void)hipSetDevice(c->device);
         for (auto &t : c->templates) free_template_device(*t);
-        for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->omega, &c->sat, &c->alist[0],
-                          &c->alist[1], &c->bins, &c->counters, &c->hub, &c->cdeg, &c->crp,
-                          &c->ccol, &c->coff, &c->segcnt, &c->scan_scratch, &c->eu, &c->ew,
-                          &c->eidx, &c->edge_plan_ids, &c->ccert, &c->expdone, &c->rlcnt, &c->rloff, &c->rlpos, &c->rlcol,
-                          &c->rlscan, &c->actbits})
-            b->release();
+        for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels}) b->release();
+        c->scratch.clear();
         delete c;
     });
 }
@@ -758,19 +776,71 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             throw Error(PM_ERR_NOT_FOUND, "template id range out of bounds");
         if (!role_mask || !edge_bits) throw Error(PM_ERR_INVALID_ARG, "null output");
         set_device(c);
-        pm_stats total{};
         const int64_t words = (c->m + 63) / 64;
-        for (int32_t i = 0; i < count; ++i) {
+        // workers: each prunes whole templates on its own stream with its own
+        // scratch; worker 0 uses the context stream
+        int nw = 1;
+        if (opt && opt->batch_streams > 1 && count > 1)
+            nw = std::min<int>(std::min<int>(opt->batch_streams, 16), count);
+        while ((int)c->scratch.size() < nw) {
+            auto sc = std::make_unique<Scratch>();
+            if (c->scratch.empty()) {
+                sc->stream = c->stream;
+            } else {
+                PM_HIP(hipStreamCreateWithFlags(&sc->stream, hipStreamNonBlocking));
+                sc->own_stream = true;
+            }
+            c->scratch.push_back(std::move(sc));
+        }
+        if (nw > 1) {
+            // the caller's pending work on its stream precedes the workers
+            PM_HIP(hipStreamSynchronize(c->stream));
+        }
+        std::vector<pm_stats> per((size_t)count);
+        auto run_one = [&](Scratch *w, int32_t i) {
             const CompiledTemplate &T = *c->templates[(size_t)(first_id + i)];
             uint64_t *ro = role_mask + (size_t)i * (size_t)c->n;
             uint64_t *eo = edge_bits + (size_t)i * (size_t)words;
-            pm_stats st{};
             switch (T.mask_bytes) {
-            case 1: { Pruner<uint8_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
-            case 2: { Pruner<uint16_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
-            case 4: { Pruner<uint32_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
-            default: { Pruner<uint64_t> p(c, T); p.run(ro, eo, opt); st = p.st; break; }
+            case 1: { Pruner<uint8_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
+            case 2: { Pruner<uint16_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
+            case 4: { Pruner<uint32_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
+            default: { Pruner<uint64_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
             }
+        };
+        if (nw == 1) {
+            for (int32_t i = 0; i < count; ++i) run_one(c->scratch[0].get(), i);
+        } else {
+            std::atomic<int32_t> next{0};
+            std::vector<std::string> errs((size_t)nw);
+            std::vector<int> codes((size_t)nw, PM_OK);
+            std::vector<std::thread> th;
+            for (int k = 0; k < nw; ++k)
+                th.emplace_back([&, k] {
+                    try {
+                        PM_HIP(hipSetDevice(c->device));
+                        for (;;) {
+                            int32_t i = next.fetch_add(1);
+                            if (i >= count) break;
+                            run_one(c->scratch[(size_t)k].get(), i);
+                        }
+                        PM_HIP(hipStreamSynchronize(c->scratch[(size_t)k]->stream));
+                    } catch (const Error &e) {
+                        errs[(size_t)k] = e.what();
+                        codes[(size_t)k] = e.code;
+                        next.store(count);
+                    } catch (const std::exception &e) {
+                        errs[(size_t)k] = e.what();
+                        codes[(size_t)k] = PM_ERR_HIP;
+                        next.store(count);
+                    }
+                });
+            for (auto &t : th) t.join();
+            for (int k = 0; k < nw; ++k)
+                if (codes[(size_t)k] != PM_OK) throw Error(codes[(size_t)k], errs[(size_t)k]);
+        }
+        pm_stats total{};
+        for (const pm_stats &st : per) {
             total.ms_total += st.ms_total;
             total.ms_init += st.ms_init;
             total.ms_lcc += st.ms_lcc;

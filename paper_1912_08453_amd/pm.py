@@ -50,7 +50,7 @@ class pm_template(ctypes.Structure):
 class pm_options(ctypes.Structure):
     _fields_ = [("order_mode", ctypes.c_int32), ("n_order", ctypes.c_int32),
                 ("order", ctypes.c_int32 * MAX_CONSTRAINTS), ("stop_after", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("batch_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class pm_stats(ctypes.Structure):
@@ -205,7 +205,7 @@ class PM:
 
     # ------------------------------------------------------------- prune
     def prune(self, first_id: int, count: int = 1, order: Optional[Sequence[int]] = None,
-              stop_after: int = -1, role_mask=None, edge_bits=None):
+              stop_after: int = -1, role_mask=None, edge_bits=None, batch_streams: int = 0):
         """Returns (role_mask uint64-as-int64 tensor [count, n], edge_bits
         [count, ceil(m/64)], stats dict)."""
         torch = self.torch
@@ -216,6 +216,7 @@ class PM:
             edge_bits = torch.empty((count, max(words, 1)), dtype=torch.int64, device=self.device)
         opt = pm_options()
         opt.stop_after = stop_after
+        opt.batch_streams = batch_streams
         if order is not None:
             opt.order_mode = PM_ORDER_GIVEN
             opt.n_order = len(order)
