@@ -49,6 +49,7 @@ extern "C" {
 #define PM_ERR_CAPACITY    (-6)   /* an internal bound was exceeded         */
 #define PM_ERR_OOM         (-7)   /* device memory exhausted                */
 #define PM_ERR_NOT_FOUND   (-8)   /* unknown template id                    */
+#define PM_ERR_MODEL       (-9)   /* no ordering model loaded, or bad one   */
 
 /* ---- limits -------------------------------------------------------------- */
 #define PM_MAX_TEMPLATE_VERTICES 64   /* role masks are 64-bit              */
@@ -73,9 +74,49 @@ typedef struct {
 /* Order of the non-local constraints. */
 #define PM_ORDER_FIXED   0   /* generation order (ordering heuristics)      */
 #define PM_ORDER_GIVEN   1   /* options.order[] permutation                  */
+#define PM_ORDER_LEARNED 2   /* greedy by the loaded model's score (below)   */
+
+/* Learned ordering model (the paper leaves constraint selection and ordering
+   by modelling open, conclusion): before each step the library computes
+   PM_MLP_FEATURES features of every remaining constraint from the current
+   state, runs a perceptron PM_MLP_FEATURES -> 64 -> 64 -> 2 (ReLU, fp32)
+   that predicts y0 = log2(1 + role bits removed by the constraint and the
+   LCC fixpoint after it) and y1 = log2(1 + microseconds both take), and
+   checks the remaining constraint of largest score y0 - y1 (ties: lowest
+   index).  Features of constraint k with vertex set Vk, edges Ek, heads
+   Hk, at a state with active role counts c[q] (vertices whose role set
+   holds q), counts c0[q] at the first LCC fixpoint, nA vertices with a
+   non-empty role set, background label frequency F[q] of q's label, d of K
+   constraints checked; lg(x) = log2(1 + x), min/mean/max over q in Vk:
+     f0 |Ek|/8, f1 |Vk|/8, f2 cycle kind, f3 TDS kind, f4 |Hk|/|Vk|,
+     f5 min lg(c)/16, f6 mean lg(c)/16, f7 max lg(c)/16, f8 lg(nA)/16,
+     f9 mean lg(F)/16, f10 mean(lg(c0) - lg(c))/16, f11 d/K.
+   Parameters (PM_MLP_PARAMS fp32, packed): W1[64][12], b1[64], W2[64][64],
+   b2[64], W3[2][64], b3[2].  The final full-template search always runs,
+   so the pruning output does not depend on the order or on the model. */
+#define PM_MLP_FEATURES 12
+#define PM_MLP_HIDDEN   64
+#define PM_MLP_OUTPUTS  2
+#define PM_MLP_PARAMS   5122
+
+/* One step of the constraint loop, recorded when options.trace is set. */
+typedef struct {
+    int32_t constraint;            /* generation index; -1: the learned loop
+                                      stopped before this step (score below
+                                      learned_min_score)                      */
+    int32_t changed;               /* vertices whose role set the NLCC step
+                                      shrank                                  */
+    int64_t roles_before;          /* role bits over all vertices before     */
+    int64_t roles_after;           /* after the step and its LCC fixpoint    */
+    int64_t active_before;         /* vertices with a non-empty role set     */
+    float ms;                      /* device time of the step and its LCC    */
+    float score;                   /* model score (0 when no model loaded)   */
+    float predicted[PM_MLP_OUTPUTS];
+    float features[PM_MLP_FEATURES];
+} pm_trace_entry;
 
 typedef struct {
-    int32_t order_mode;            /* PM_ORDER_FIXED or PM_ORDER_GIVEN        */
+    int32_t order_mode;            /* PM_ORDER_FIXED, _GIVEN or _LEARNED      */
     int32_t n_order;               /* entries in order[] for PM_ORDER_GIVEN   */
     int32_t order[PM_MAX_CONSTRAINTS];
     int32_t stop_after;            /* -1: full prune.  k >= 0: stop after k
@@ -86,7 +127,16 @@ typedef struct {
     int32_t batch_streams;         /* count > 1: prune up to this many
                                       templates concurrently, each on its own
                                       stream and scratch (0/1: one at a time)  */
-    int32_t reserved[6];
+    float learned_min_score;       /* PM_ORDER_LEARNED with learned_stop: end
+                                      the constraint loop when the best
+                                      remaining score is below this (the
+                                      final search still runs)                */
+    int32_t learned_stop;          /* nonzero: apply learned_min_score        */
+    int32_t trace_cap;             /* entries available in trace[]            */
+    pm_trace_entry *trace;         /* host array or NULL; count must be 1.
+                                      stats.trace_entries receives the number
+                                      written (at most trace_cap)            */
+    int32_t reserved[4];
 } pm_options;
 
 /* Per-call statistics (valid when pm_prune returns PM_OK). */
@@ -117,7 +167,8 @@ typedef struct {
     int64_t edge_candidates;       /* edges left for edge-rooted searches     */
     int64_t vq_pos, vq_neg;        /* vertex-rooted searches found / failed   */
     int64_t eq_pos, eq_neg;        /* edge-rooted searches found / failed     */
-    int64_t reserved[6];
+    int64_t trace_entries;         /* pm_trace_entry records written          */
+    int64_t reserved[5];
 } pm_stats;
 
 /* Returns the message for the last error on this thread ("" if none). */
@@ -178,6 +229,33 @@ int pm_inspect_template(const pm_template *t, int32_t *count, int32_t *kinds, in
    > 1 it receives the sums over the templates. */
 int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
              uint64_t *edge_bits, const pm_options *opt, pm_stats *stats);
+
+/* ---- learned ordering model ------------------------------------------------
+   The perceptron and its training run in the library's kernels; the
+   features and model are defined above PM_MLP_PARAMS. */
+
+/* Copy PM_MLP_PARAMS fp32 parameters from host memory `w` (n must equal
+   PM_MLP_PARAMS) into the context; PM_ORDER_LEARNED uses them from then on.
+   PM_ERR_MODEL if a value is not finite. */
+int pm_load_model(pm_ctx *ctx, const float *w, size_t n);
+
+/* Forward pass: y[N][2] = model(x[N][12]) with parameters w (device
+   float[PM_MLP_PARAMS]); all device pointers, row-major.  N >= 0. */
+int pm_mlp_forward(pm_ctx *ctx, const float *w, const float *x, int64_t N, float *y);
+
+/* Loss L = sum over samples and outputs of (y - t)^2 / (2N) and its
+   gradient with respect to the packed parameters (ReLU'(0) = 0).  x[N][12],
+   t[N][2], grad[PM_MLP_PARAMS], loss[1]: device pointers.  N >= 1.  The
+   sums over samples are taken in a fixed order: results are deterministic. */
+int pm_mlp_grad(pm_ctx *ctx, const float *w, const float *x, const float *t, int64_t N,
+                float *grad, float *loss);
+
+/* Full-batch Adam (beta1 0.9, beta2 0.999, eps 1e-8, zero initial moments)
+   for `steps` steps of learning rate lr on the loss above, updating the
+   device parameters w in place.  loss_history: host float[steps] receiving
+   the loss before each step, or NULL. */
+int pm_mlp_train(pm_ctx *ctx, float *w, const float *x, const float *t, int64_t N,
+                 int32_t steps, float lr, float *loss_history);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -86,11 +87,11 @@ struct Scratch {
     bool own_stream = false;
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expdone, rlcnt, rloff, rlpos, rlcol, rlscan,
-        actbits;
+        actbits, ord;
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
                           &ccol, &coff, &segcnt, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
-                          &ccert, &expdone, &rlcnt, &rloff, &rlpos, &rlcol, &rlscan, &actbits})
+                          &ccert, &expdone, &rlcnt, &rloff, &rlpos, &rlcol, &rlscan, &actbits, &ord})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
@@ -123,6 +124,10 @@ struct pm_ctx {
     int grid_search = 2048;
     int expand = 1;
     int64_t wall_khz = 0;
+    // learned-order model and the workspace of its training kernels
+    DevBuf model;
+    bool has_model = false;
+    DevBuf mlp_partial, mlp_ploss, mlp_grad, mlp_m, mlp_v, mlp_loss;
 };
 
 namespace {
@@ -451,6 +456,128 @@ struct Pruner {
         st.ms_exact += t.stop();
     }
 
+    // ---- constraint loop -----------------------------------------------------
+    // Device block of the ordering state: counts [64], counts0 [64], pick.
+    unsigned long long *ord_counts() { return w->ord.as<unsigned long long>(); }
+    unsigned long long *ord_counts0() { return w->ord.as<unsigned long long>() + kMaxK; }
+    OrderPick *ord_pick() {
+        return reinterpret_cast<OrderPick *>(w->ord.as<unsigned long long>() + 2 * kMaxK);
+    }
+
+    void role_totals(unsigned long long *dst) {
+        launch_fill_u64(s, reinterpret_cast<uint64_t *>(dst), kMaxK, 0ull);
+        launch_role_totals<M>(s, A, nA, om, T.n0, dst);
+    }
+
+    // Features (and, with a model, scores) at the current state; forced >= 0
+    // reports that constraint, otherwise the best remaining one is chosen.
+    OrderPick pick(int forced, uint64_t remaining, int done) {
+        role_totals(ord_counts());
+        OrderArgs a{};
+        a.counts = ord_counts();
+        a.counts0 = ord_counts0();
+        a.cons = T.d_cdesc;
+        a.w = c->has_model ? c->model.as<float>() : nullptr;
+        for (int q = 0; q < T.n0; ++q) {
+            const int L = T.labels[(size_t)q];
+            a.role_freq[q] = (size_t)L < c->label_freq.size() ? (uint64_t)c->label_freq[(size_t)L] : 0;
+        }
+        a.remaining = remaining;
+        a.n_active = nA;
+        a.n_cons = (int32_t)T.constraints.size();
+        a.done = done;
+        a.forced = forced;
+        a.n0 = T.n0;
+        launch_order_select(s, a, ord_pick());
+        OrderPick p{};
+        d2h(s, &p, ord_pick(), 1);
+        return p;
+    }
+
+    int64_t roles_now() {
+        role_totals(ord_counts());
+        unsigned long long h[kMaxK];
+        d2h(s, h, ord_counts(), kMaxK);
+        int64_t r = 0;
+        for (int q = 0; q < T.n0; ++q) r += (int64_t)h[q];
+        return r;
+    }
+
+    // Main loop over the non-local constraints: NLCC, then LCC to the
+    // fixpoint when anything changed.  In the learned mode the next
+    // constraint is the remaining one of largest model score.
+    int64_t n_trace = 0;
+    void constraint_loop(const std::vector<int> &order, bool learned, int stop_after,
+                         const pm_options *opt) {
+        const int K = (int)T.constraints.size();
+        pm_trace_entry *trace = opt && opt->trace && opt->trace_cap > 0 ? opt->trace : nullptr;
+        const int64_t cap = trace ? opt->trace_cap : 0;
+        const bool featured = learned || trace;
+        if (featured && K > 0) {
+            w->ord.ensure(sizeof(unsigned long long) * 2 * kMaxK + sizeof(OrderPick) + 64);
+            role_totals(ord_counts0());
+        }
+        uint64_t remaining = K == 64 ? ~0ull : ((1ull << K) - 1ull);
+        int done = 0;
+        int64_t pending_after = -1;   // trace entry waiting for roles_after
+        while (done < K) {
+            if (stop_after >= 0 && done >= stop_after) break;
+            if (nA == 0) break;
+            OrderPick pk{};
+            int k = learned ? -1 : order[(size_t)done];
+            const int64_t active_before = nA;
+            if (featured) {
+                pk = pick(learned ? -1 : k, remaining, done);
+                if (pending_after >= 0) {
+                    trace[pending_after].roles_after = (int64_t)pk.roles;
+                    pending_after = -1;
+                }
+                if (learned) {
+                    k = pk.idx;
+                    if (k < 0) break;
+                    if (opt->learned_stop && !(pk.score >= opt->learned_min_score)) {
+                        if (n_trace < cap) {
+                            pm_trace_entry &e = trace[n_trace++];
+                            e = pm_trace_entry{};
+                            e.constraint = -1;
+                            e.roles_before = e.roles_after = (int64_t)pk.roles;
+                            e.active_before = active_before;
+                            e.score = pk.score;
+                            for (int i = 0; i < kMlpOut; ++i) e.predicted[i] = pk.pred[i];
+                            for (int i = 0; i < kMlpIn; ++i) e.features[i] = pk.feat[i];
+                        }
+                        break;
+                    }
+                }
+            }
+            Timer tt(s);
+            int32_t ch = nlcc(T.constraints[(size_t)k]);
+            if (ch) {
+                collect(false);
+                if (nA > 0) lcc_fixpoint(Graph{c_rp, c_col});
+            }
+            const double ms = tt.stop();
+            remaining &= ~(1ull << k);
+            ++done;
+            if (trace && n_trace < cap) {
+                pm_trace_entry &e = trace[n_trace];
+                e = pm_trace_entry{};
+                e.constraint = k;
+                e.changed = ch;
+                e.roles_before = (int64_t)pk.roles;
+                e.roles_after = -1;
+                e.active_before = active_before;
+                e.ms = (float)ms;
+                e.score = pk.score;
+                for (int i = 0; i < kMlpOut; ++i) e.predicted[i] = pk.pred[i];
+                for (int i = 0; i < kMlpIn; ++i) e.features[i] = pk.feat[i];
+                pending_after = n_trace++;
+            }
+        }
+        if (pending_after >= 0) trace[pending_after].roles_after = nA > 0 ? roles_now() : 0;
+        st.trace_entries = n_trace;
+    }
+
     void run(uint64_t *role_out, uint64_t *edge_out, const pm_options *opt) {
         Timer total(s);
         const int64_t n = c->n, m = c->m;
@@ -483,32 +610,24 @@ struct Pruner {
         Graph cand{c_rp, c_col};
         if (T.n0 > 1 && nA > 0) lcc_fixpoint(cand);
         int stop_after = opt ? opt->stop_after : -1;
+        const int K = (int)T.constraints.size();
+        const bool learned = opt && opt->order_mode == PM_ORDER_LEARNED;
         std::vector<int> order;
         if (opt && opt->order_mode == PM_ORDER_GIVEN) {
-            if (opt->n_order != (int)T.constraints.size())
+            if (opt->n_order != K)
                 throw Error(PM_ERR_INVALID_ARG, "order length differs from the constraint count");
-            std::vector<char> seen(T.constraints.size(), 0);
+            std::vector<char> seen((size_t)K, 0);
             for (int i = 0; i < opt->n_order; ++i) {
                 int k = opt->order[i];
-                if (k < 0 || k >= (int)T.constraints.size() || seen[k])
+                if (k < 0 || k >= K || seen[k])
                     throw Error(PM_ERR_INVALID_ARG, "order is not a permutation");
                 seen[k] = 1;
                 order.push_back(k);
             }
         } else {
-            for (size_t i = 0; i < T.constraints.size(); ++i) order.push_back((int)i);
+            for (int i = 0; i < K; ++i) order.push_back(i);
         }
-        int done = 0;
-        for (int k : order) {
-            if (stop_after >= 0 && done >= stop_after) break;
-            if (nA == 0) break;
-            int32_t ch = nlcc(T.constraints[k]);
-            ++done;
-            if (ch) {
-                collect(false);
-                if (nA > 0) lcc_fixpoint(cand);
-            }
-        }
+        constraint_loop(order, learned, stop_after, opt);
         if (stop_after >= 0 || T.acyclic_unique || T.n0 == 1) {
             // omega and its implied edge state (exact for acyclic unique-label
             // templates: LCC alone suffices)
@@ -542,6 +661,12 @@ void load_template_device(pm_ctx *c, CompiledTemplate &T) {
     T.init_lut_len = (int64_t)lut.size();
     PM_HIP(hipMalloc(&T.d_init_lut, sizeof(uint64_t) * lut.size()));
     PM_HIP(hipMemcpy(T.d_init_lut, lut.data(), sizeof(uint64_t) * lut.size(), hipMemcpyHostToDevice));
+    std::vector<ConstraintDesc> cd;
+    for (const Constraint &k : T.constraints)
+        cd.push_back(ConstraintDesc{k.vmask, k.heads, (int32_t)k.edges.size(), k.kind});
+    PM_HIP(hipMalloc(&T.d_cdesc, sizeof(ConstraintDesc) * std::max<size_t>(cd.size(), 1)));
+    if (!cd.empty())
+        PM_HIP(hipMemcpy(T.d_cdesc, cd.data(), sizeof(ConstraintDesc) * cd.size(), hipMemcpyHostToDevice));
     (void)c;
 }
 
@@ -549,6 +674,8 @@ void free_template_device(CompiledTemplate &T) {
     if (T.d_plans) (void)hipFree(T.d_plans);
     if (T.d_tedges) (void)hipFree(T.d_tedges);
     if (T.d_init_lut) (void)hipFree(T.d_init_lut);
+    if (T.d_cdesc) (void)hipFree(T.d_cdesc);
+    T.d_cdesc = nullptr;
     T.d_plans = nullptr;
     T.d_tedges = nullptr;
     T.d_init_lut = nullptr;
@@ -630,6 +757,9 @@ int pm_destroy(pm_ctx *c) {
         for (auto &t : c->templates) free_template_device(*t);
         for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels}) b->release();
         c->scratch.clear();
+        for (DevBuf *b : {&c->model, &c->mlp_partial, &c->mlp_ploss, &c->mlp_grad, &c->mlp_m,
+                          &c->mlp_v, &c->mlp_loss})
+            b->release();
         delete c;
     });
 }
@@ -775,6 +905,12 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
         if (count <= 0 || first_id < 0 || first_id + count > (int32_t)c->templates.size())
             throw Error(PM_ERR_NOT_FOUND, "template id range out of bounds");
         if (!role_mask || !edge_bits) throw Error(PM_ERR_INVALID_ARG, "null output");
+        if (opt && (opt->order_mode < PM_ORDER_FIXED || opt->order_mode > PM_ORDER_LEARNED))
+            throw Error(PM_ERR_INVALID_ARG, "unknown order mode");
+        if (opt && opt->order_mode == PM_ORDER_LEARNED && !c->has_model)
+            throw Error(PM_ERR_MODEL, "learned order without a loaded model");
+        if (opt && opt->trace && opt->trace_cap > 0 && count != 1)
+            throw Error(PM_ERR_INVALID_ARG, "a trace records one template: count must be 1");
         set_device(c);
         const int64_t words = (c->m + 63) / 64;
         // workers: each prunes whole templates on its own stream with its own
@@ -867,9 +1003,86 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.wave_ms_eq_pos += st.wave_ms_eq_pos;
             total.wave_ms_eq_neg += st.wave_ms_eq_neg;
             total.wave_ms_certify += st.wave_ms_certify;
+            total.trace_entries += st.trace_entries;
         }
         PM_HIP(hipStreamSynchronize(c->stream));
         if (stats) *stats = total;
+    });
+}
+
+int pm_load_model(pm_ctx *c, const float *w, size_t n) {
+    return guarded([&] {
+        if (!c || !w) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        if (n != (size_t)kMlpParams) throw Error(PM_ERR_INVALID_ARG, "model must have PM_MLP_PARAMS values");
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(w[i])) throw Error(PM_ERR_MODEL, "model parameter is not finite");
+        set_device(c);
+        c->model.ensure(sizeof(float) * (size_t)kMlpParams);
+        PM_HIP(hipMemcpyAsync(c->model.p, w, sizeof(float) * (size_t)kMlpParams,
+                              hipMemcpyHostToDevice, c->stream));
+        PM_HIP(hipStreamSynchronize(c->stream));
+        c->has_model = true;
+    });
+}
+
+int pm_mlp_forward(pm_ctx *c, const float *w, const float *x, int64_t n, float *y) {
+    return guarded([&] {
+        if (!c || n < 0 || (n > 0 && (!w || !x || !y))) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        set_device(c);
+        launch_mlp_forward(c->stream, w, x, n, y);
+        PM_HIP(hipGetLastError());
+        PM_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+static void mlp_workspace(pm_ctx *c) {
+    c->mlp_partial.ensure(sizeof(float) * (size_t)kMlpGradGrid * kMlpParams);
+    c->mlp_ploss.ensure(sizeof(float) * kMlpGradGrid);
+}
+
+int pm_mlp_grad(pm_ctx *c, const float *w, const float *x, const float *t, int64_t n, float *grad,
+                float *loss) {
+    return guarded([&] {
+        if (!c || n < 1 || !w || !x || !t || !grad || !loss)
+            throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        set_device(c);
+        mlp_workspace(c);
+        launch_mlp_grad(c->stream, w, x, t, n, c->mlp_partial.as<float>(), c->mlp_ploss.as<float>(),
+                        grad, loss);
+        PM_HIP(hipGetLastError());
+        PM_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int pm_mlp_train(pm_ctx *c, float *w, const float *x, const float *t, int64_t n, int32_t steps,
+                 float lr, float *loss_history) {
+    return guarded([&] {
+        if (!c || n < 1 || steps < 0 || !w || !x || !t || !(lr > 0.0f))
+            throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        set_device(c);
+        mlp_workspace(c);
+        c->mlp_grad.ensure(sizeof(float) * kMlpParams);
+        c->mlp_m.ensure(sizeof(float) * kMlpParams);
+        c->mlp_v.ensure(sizeof(float) * kMlpParams);
+        c->mlp_loss.ensure(sizeof(float) * (size_t)std::max(steps, 1));
+        hipStream_t s = c->stream;
+        launch_fill_i32(s, c->mlp_m.as<int32_t>(), kMlpParams, 0);
+        launch_fill_i32(s, c->mlp_v.as<int32_t>(), kMlpParams, 0);
+        double b1t = 1.0, b2t = 1.0;
+        for (int32_t k = 1; k <= steps; ++k) {
+            b1t *= 0.9;
+            b2t *= 0.999;
+            launch_mlp_grad(s, w, x, t, n, c->mlp_partial.as<float>(), c->mlp_ploss.as<float>(),
+                            c->mlp_grad.as<float>(), c->mlp_loss.as<float>() + (k - 1));
+            launch_adam(s, w, c->mlp_grad.as<float>(), c->mlp_m.as<float>(), c->mlp_v.as<float>(), lr,
+                        (float)(1.0 - b1t), (float)(1.0 - b2t));
+        }
+        PM_HIP(hipGetLastError());
+        if (loss_history && steps > 0) {
+            PM_HIP(hipMemcpyAsync(loss_history, c->mlp_loss.p, sizeof(float) * (size_t)steps,
+                                  hipMemcpyDeviceToHost, s));
+        }
+        PM_HIP(hipStreamSynchronize(s));
     });
 }
 

@@ -431,7 +431,8 @@ __global__ void apply_kernel(const int32_t *tasks, int64_t n_tasks, M *omega, M 
             ch = true;
         }
     }
-    if (ballot64(ch) && lane_id() == 0) atomicAdd(changed, 1);
+    const uint64_t b = ballot64(ch);
+    if (b && lane_id() == 0) atomicAdd(changed, (int32_t)__popcll(b));
 }
 
 template <typename M>

@@ -56,6 +56,49 @@ struct Constraint {
     int32_t plan_of_head[kMaxK];    // -1 if not a head
 };
 
+// Learned constraint order: perceptron sizes and packed parameter offsets.
+constexpr int kMlpIn = 12, kMlpHid = 64, kMlpOut = 2;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpHid * kMlpIn;      // 768
+constexpr int kOffW2 = kOffB1 + kMlpHid;               // 832
+constexpr int kOffB2 = kOffW2 + kMlpHid * kMlpHid;     // 4928
+constexpr int kOffW3 = kOffB2 + kMlpHid;               // 4992
+constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpHid;     // 5120
+constexpr int kMlpParams = kOffB3 + kMlpOut;           // 5122
+constexpr int kMlpGradGrid = 128;                      // blocks of the gradient kernel
+
+// Device descriptor of one constraint (features of the learned order).
+struct ConstraintDesc {
+    uint64_t vmask;
+    uint64_t heads;
+    int32_t n_edges;
+    int32_t kind;
+};
+
+// Inputs of the feature/choice kernel (by value).
+struct OrderArgs {
+    const unsigned long long *counts;   // [64] active role counts now
+    const unsigned long long *counts0;  // [64] at the first LCC fixpoint
+    const ConstraintDesc *cons;         // [n_cons]
+    const float *w;                     // model parameters, or null
+    uint64_t role_freq[kMaxK];          // background vertices of q's label
+    uint64_t remaining;                 // constraints not yet checked
+    int64_t n_active;
+    int32_t n_cons;
+    int32_t done;
+    int32_t forced;                     // >= 0: report this constraint
+    int32_t n0;
+};
+
+// Output of the feature/choice kernel.
+struct OrderPick {
+    int32_t idx;                        // chosen (or forced) constraint, -1 none
+    float score;
+    float pred[kMlpOut];
+    float feat[kMlpIn];
+    unsigned long long roles;           // sum of counts
+};
+
 struct CompiledTemplate {
     int32_t n0 = 0, m0 = 0;
     std::vector<int32_t> labels;
@@ -73,6 +116,7 @@ struct CompiledTemplate {
     int32_t *d_tedges = nullptr;              // [2*m0] template edges (a, b)
     uint64_t *d_init_lut = nullptr;           // label -> initial roles
     int64_t init_lut_len = 0;
+    ConstraintDesc *d_cdesc = nullptr;        // [constraints]
 };
 
 // Template compiler (host).  Returns an empty string on success, otherwise
@@ -204,7 +248,8 @@ template <typename M>
 void launch_vertex_search(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,
                           M *sat, const SearchArgs &a, int grid);
 
-// NLCC application: omega &= ~heads | sat; sat cleared; changed counter.
+// NLCC application: omega &= ~heads | sat; sat cleared; *changed += vertices
+// whose role set shrank.
 template <typename M>
 void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega, M *sat,
                   uint64_t heads, int32_t *changed);
@@ -233,6 +278,22 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
 
 template <typename M>
 void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst);
+
+// ---- learned order ----------------------------------------------------------
+// counts[q] += number of vertices of tasks whose role set holds q (counts
+// zeroed by the caller).
+template <typename M>
+void launch_role_totals(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,
+                        int n0, unsigned long long *counts);
+// Features of the remaining constraints, model scores, greedy choice.
+void launch_order_select(hipStream_t s, const OrderArgs &a, OrderPick *out);
+void launch_mlp_forward(hipStream_t s, const float *w, const float *x, int64_t n, float *y);
+// Per-block partial gradients [kMlpGradGrid][kMlpParams] and partial losses
+// [kMlpGradGrid], then their fixed-order sums into grad and loss[0].
+void launch_mlp_grad(hipStream_t s, const float *w, const float *x, const float *t, int64_t n,
+                     float *partial, float *partial_loss, float *grad, float *loss);
+void launch_adam(hipStream_t s, float *w, const float *grad, float *m, float *v, float lr,
+                 float bc1, float bc2);
 
 void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t n, uint64_t v);
 void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);

@@ -524,3 +524,20 @@ def templates_multicycle(graph: "Graph", seed: int, count: int = 64) -> List[Tem
 
 def label_histogram(labels: np.ndarray) -> np.ndarray:
     return np.bincount(labels.astype(np.int64), minlength=int(labels.max()) + 1 if labels.size else 1)
+
+
+def model_params(seed: int, n_params: int = 5122, fan_ins=((768, 12), (64, 0), (4096, 64),
+                                                            (64, 0), (128, 64), (2, 0))):
+    """Seeded initial parameters of the ordering model, packed block by block
+    (weights uniform in +-sqrt(6 / fan_in), biases 0.01), float32."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    parts = []
+    for size, fan_in in fan_ins:
+        if fan_in:
+            b = float(np.sqrt(6.0 / fan_in))
+            parts.append(rng.uniform(-b, b, size))
+        else:
+            parts.append(np.full(size, 0.01))
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.shape[0] == n_params
+    return w

@@ -22,17 +22,23 @@ PM_HOST_PTRS = 1
 PM_VALIDATE = 2
 PM_ORDER_FIXED = 0
 PM_ORDER_GIVEN = 1
+PM_ORDER_LEARNED = 2
 MAX_CONSTRAINTS = 64
+MLP_FEATURES = 12
+MLP_OUTPUTS = 2
+MLP_PARAMS = 5122
 
 ERRORS = {
     -1: "PM_ERR_INVALID_ARG", -2: "PM_ERR_HIP", -3: "PM_ERR_GRAPH", -4: "PM_ERR_TEMPLATE",
     -5: "PM_ERR_NO_GRAPH", -6: "PM_ERR_CAPACITY", -7: "PM_ERR_OOM", -8: "PM_ERR_NOT_FOUND",
+    -9: "PM_ERR_MODEL",
 }
 
 # exported symbols declared in include/pm.h
 SYMBOLS = ["pm_last_error", "pm_version", "pm_create", "pm_destroy", "pm_load_graph",
            "pm_unload_graph", "pm_load_templates", "pm_template_constraints",
-           "pm_inspect_template", "pm_prune"]
+           "pm_inspect_template", "pm_prune", "pm_load_model", "pm_mlp_forward", "pm_mlp_grad",
+           "pm_mlp_train"]
 
 
 class PMError(RuntimeError):
@@ -47,10 +53,26 @@ class pm_template(ctypes.Structure):
                 ("edges", ctypes.POINTER(ctypes.c_uint32))]
 
 
+class pm_trace_entry(ctypes.Structure):
+    _fields_ = [("constraint", ctypes.c_int32), ("changed", ctypes.c_int32),
+                ("roles_before", ctypes.c_int64), ("roles_after", ctypes.c_int64),
+                ("active_before", ctypes.c_int64), ("ms", ctypes.c_float),
+                ("score", ctypes.c_float), ("predicted", ctypes.c_float * MLP_OUTPUTS),
+                ("features", ctypes.c_float * MLP_FEATURES)]
+
+    def as_dict(self):
+        return {"constraint": self.constraint, "changed": self.changed,
+                "roles_before": self.roles_before, "roles_after": self.roles_after,
+                "active_before": self.active_before, "ms": self.ms, "score": self.score,
+                "predicted": list(self.predicted), "features": list(self.features)}
+
+
 class pm_options(ctypes.Structure):
     _fields_ = [("order_mode", ctypes.c_int32), ("n_order", ctypes.c_int32),
                 ("order", ctypes.c_int32 * MAX_CONSTRAINTS), ("stop_after", ctypes.c_int32),
-                ("batch_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("batch_streams", ctypes.c_int32), ("learned_min_score", ctypes.c_float),
+                ("learned_stop", ctypes.c_int32), ("trace_cap", ctypes.c_int32),
+                ("trace", ctypes.POINTER(pm_trace_entry)), ("reserved", ctypes.c_int32 * 4)]
 
 
 class pm_stats(ctypes.Structure):
@@ -61,8 +83,8 @@ class pm_stats(ctypes.Structure):
                [(k, ctypes.c_int64) for k in
                 ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
                  "candidate_entries", "vertex_queries", "edge_queries", "result_vertices",
-                 "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg")] + \
-               [("reserved", ctypes.c_int64 * 6)]
+                 "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries")] + \
+               [("reserved", ctypes.c_int64 * 5)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -96,6 +118,10 @@ def load_library(path: str = LIB_PATH):
                                         P, P]
     lib.pm_prune.argtypes = [P, I32, I32, P, P, ctypes.POINTER(pm_options),
                              ctypes.POINTER(pm_stats)]
+    lib.pm_load_model.argtypes = [P, P, ctypes.c_size_t]
+    lib.pm_mlp_forward.argtypes = [P, P, P, I64, P]
+    lib.pm_mlp_grad.argtypes = [P, P, P, P, I64, P, P]
+    lib.pm_mlp_train.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, P]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -204,10 +230,13 @@ class PM:
         return _unpack_constraints(cnt.value, kinds, ne, heads, edges)
 
     # ------------------------------------------------------------- prune
-    def prune(self, first_id: int, count: int = 1, order: Optional[Sequence[int]] = None,
-              stop_after: int = -1, role_mask=None, edge_bits=None, batch_streams: int = 0):
+    def prune(self, first_id: int, count: int = 1, order=None,
+              stop_after: int = -1, role_mask=None, edge_bits=None, batch_streams: int = 0,
+              learned_min_score: Optional[float] = None, trace: bool = False):
         """Returns (role_mask uint64-as-int64 tensor [count, n], edge_bits
-        [count, ceil(m/64)], stats dict)."""
+        [count, ceil(m/64)], stats dict); with trace=True the stats dict also
+        holds "trace", the list of per-step records.  order: None (fixed),
+        "learned" (greedy by the loaded model), or a permutation."""
         torch = self.torch
         words = (self.m + 63) // 64
         if role_mask is None:
@@ -217,17 +246,81 @@ class PM:
         opt = pm_options()
         opt.stop_after = stop_after
         opt.batch_streams = batch_streams
-        if order is not None:
+        if isinstance(order, str):
+            if order != "learned":
+                raise ValueError("order must be None, 'learned' or a permutation")
+            opt.order_mode = PM_ORDER_LEARNED
+        elif order is not None:
             opt.order_mode = PM_ORDER_GIVEN
             opt.n_order = len(order)
             for i, k in enumerate(order):
                 opt.order[i] = int(k)
+        if learned_min_score is not None:
+            opt.learned_stop = 1
+            opt.learned_min_score = float(learned_min_score)
+        tr = None
+        if trace:
+            tr = (pm_trace_entry * (MAX_CONSTRAINTS + 1))()
+            opt.trace_cap = MAX_CONSTRAINTS + 1
+            opt.trace = ctypes.cast(tr, ctypes.POINTER(pm_trace_entry))
         st = pm_stats()
         _check(self.lib, self.lib.pm_prune(self.h, first_id, count,
                                            ctypes.c_void_p(role_mask.data_ptr()),
                                            ctypes.c_void_p(edge_bits.data_ptr()),
                                            ctypes.byref(opt), ctypes.byref(st)))
-        return role_mask[:, :self.n], edge_bits[:, :words], st.as_dict()
+        out = st.as_dict()
+        if tr is not None:
+            out["trace"] = [tr[i].as_dict() for i in range(int(st.trace_entries))]
+        return role_mask[:, :self.n], edge_bits[:, :words], out
+
+    # ----------------------------------------------------- ordering model
+    def load_model(self, w) -> None:
+        """Load the ordering model (MLP_PARAMS float32 values, host)."""
+        a = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+        _check(self.lib, self.lib.pm_load_model(self.h, a.ctypes.data_as(ctypes.c_void_p),
+                                                a.shape[0]))
+
+    def _f32(self, a, shape):
+        t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device)
+        return t.reshape(shape).contiguous()
+
+    def mlp_forward(self, w, x):
+        """Model outputs [N][2] for inputs [N][12] (device kernel)."""
+        wd = self._f32(w, (MLP_PARAMS,))
+        xd = self._f32(x, (-1, MLP_FEATURES))
+        y = self.torch.empty((xd.shape[0], MLP_OUTPUTS), dtype=self.torch.float32,
+                             device=self.device)
+        _check(self.lib, self.lib.pm_mlp_forward(self.h, ctypes.c_void_p(wd.data_ptr()),
+                                                 ctypes.c_void_p(xd.data_ptr()), xd.shape[0],
+                                                 ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def mlp_grad(self, w, x, t):
+        """(loss, gradient [MLP_PARAMS]) of the halved mean squared error."""
+        wd = self._f32(w, (MLP_PARAMS,))
+        xd = self._f32(x, (-1, MLP_FEATURES))
+        td = self._f32(t, (-1, MLP_OUTPUTS))
+        g = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.device)
+        loss = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
+        _check(self.lib, self.lib.pm_mlp_grad(self.h, ctypes.c_void_p(wd.data_ptr()),
+                                              ctypes.c_void_p(xd.data_ptr()),
+                                              ctypes.c_void_p(td.data_ptr()), xd.shape[0],
+                                              ctypes.c_void_p(g.data_ptr()),
+                                              ctypes.c_void_p(loss.data_ptr())))
+        return float(loss.item()), g
+
+    def mlp_train(self, w, x, t, steps: int, lr: float):
+        """Full-batch Adam on the device; returns (parameters, loss history)."""
+        wd = self._f32(w, (MLP_PARAMS,)).clone()
+        xd = self._f32(x, (-1, MLP_FEATURES))
+        td = self._f32(t, (-1, MLP_OUTPUTS))
+        hist = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(self.lib, self.lib.pm_mlp_train(self.h, ctypes.c_void_p(wd.data_ptr()),
+                                               ctypes.c_void_p(xd.data_ptr()),
+                                               ctypes.c_void_p(td.data_ptr()), xd.shape[0],
+                                               int(steps), float(lr),
+                                               hist.ctypes.data_as(ctypes.c_void_p)))
+        return wd, hist[:steps]
 
 
 def _unpack_constraints(cnt, kinds, ne, heads, edges):

@@ -108,3 +108,44 @@ def test_cycle_rich_template_bounded(lib):
     got = pm.inspect_template(t)
     assert got == oracle_list(t)
     assert sum(1 for c in got if c[0] == C.CC) == 32
+
+
+def _c_layout(tmp_path):
+    """sizeof/offsetof of the ABI structs as the C compiler lays them out."""
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "pm.h"
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+    printf("pm_options %zu\n", sizeof(pm_options));
+    printf("pm_trace_entry %zu\n", sizeof(pm_trace_entry));
+    printf("pm_stats %zu\n", sizeof(pm_stats));
+    printf("pm_template %zu\n", sizeof(pm_template));
+    F(pm_options, stop_after); F(pm_options, batch_streams); F(pm_options, learned_min_score);
+    F(pm_options, learned_stop); F(pm_options, trace_cap); F(pm_options, trace);
+    F(pm_options, reserved);
+    F(pm_trace_entry, roles_before); F(pm_trace_entry, ms); F(pm_trace_entry, score);
+    F(pm_trace_entry, predicted); F(pm_trace_entry, features);
+    F(pm_stats, lcc_sweeps); F(pm_stats, trace_entries); F(pm_stats, reserved);
+    return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    return dict(line.rsplit(" ", 1) for line in out if line)
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    c = {k: int(v) for k, v in _c_layout(tmp_path).items()}
+    assert c["pm_options"] == ctypes.sizeof(pm.pm_options)
+    assert c["pm_trace_entry"] == ctypes.sizeof(pm.pm_trace_entry)
+    assert c["pm_stats"] == ctypes.sizeof(pm.pm_stats)
+    assert c["pm_template"] == ctypes.sizeof(pm.pm_template)
+    for key, v in c.items():
+        if "." in key:
+            struct, field = key.split(".")
+            assert getattr(getattr(pm, struct), field).offset == v, key
