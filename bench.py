@@ -40,6 +40,11 @@ def main():
                     help="run only a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
+    ap.add_argument("--legs", default="batched,learned",
+                    help="extra legs on the same resident graph: batched (64 mixed templates, "
+                         "one call per template vs concurrent streams), learned (64 multi-cycle "
+                         "templates, fixed vs learned constraint order); '' for none")
+    ap.add_argument("--batch-streams", type=int, default=4)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -126,6 +131,15 @@ def main():
     counts["result_vertices"] = int((r != 0).sum())
     counts["result_entries"] = int(np.unpackbits(pm.to_u64(edge[0]).view(np.uint8)).sum())
 
+    legs = [x for x in args.legs.split(",") if x]
+    batched = learned = None
+    if "batched" in legs:
+        batched = batched_leg(ctx, g, args.batch_streams)
+        log(f"batched: {json.dumps(batched)}")
+    if "learned" in legs:
+        learned = learned_leg(ctx, g)
+        log(f"learned: {json.dumps(learned)}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, tmpl, args.cpu_sample_s)
@@ -157,9 +171,92 @@ def main():
                            "share_of_step": round(avg("ms_exact") / max(avg("ms_total"), 1e-9), 4),
                            "bound": "search latency / random gathers (no roofline claim)"},
         "cpu_baseline": cpu,
+        "batched": batched,
+        "learned_order": learned,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def batched_leg(ctx, g, streams, seed=3, count=64):
+    """64 mixed templates (paths/trees, one- and two-cycle, K4; some with a
+    repeated label) against the resident graph: one pm_prune call per
+    template in the fixed order, then one call for all of them on `streams`
+    concurrent streams.  Outputs must be identical."""
+    import torch
+    from paper_1912_08453_amd import inputs as I
+    ts = I.templates_batch(g, seed, count=count)
+    first = ctx.load_templates(ts)
+    n, words = g.n, (g.m + 63) // 64
+    dev = torch.device("cuda", 0)
+    r1 = torch.empty((count, n), dtype=torch.int64, device=dev)
+    e1 = torch.empty((count, words), dtype=torch.int64, device=dev)
+    r2 = torch.empty_like(r1)
+    e2 = torch.empty_like(e1)
+    ctx.prune(first, count=count, role_mask=r2, edge_bits=e2, batch_streams=streams)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phase = {"ms_exact": 0.0, "ms_nlcc": 0.0, "ms_lcc": 0.0}
+    for i in range(count):
+        _, _, st = ctx.prune(first + i, role_mask=r1[i:i + 1], edge_bits=e1[i:i + 1])
+        for k in phase:
+            phase[k] += st[k]
+    torch.cuda.synchronize()
+    seq_ms = 1e3 * (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    ctx.prune(first, count=count, role_mask=r2, edge_bits=e2, batch_streams=streams)
+    torch.cuda.synchronize()
+    bat_ms = 1e3 * (time.perf_counter() - t0)
+    same = bool(torch.equal(r1, r2) and torch.equal(e1, e2))
+    del r1, e1, r2, e2
+    return {"workload": f"{count} templates (3-8 vertices; trees, one/two cycles, K4; "
+                        f"seed {seed}) on the same graph",
+            "one_template_per_call_ms": round(seq_ms, 2),
+            "batched_ms": round(bat_ms, 2), "batch_streams": streams,
+            "speedup": round(seq_ms / bat_ms, 4), "outputs_identical": same,
+            "one_per_call_phase_ms": {k: round(v, 2) for k, v in phase.items()}}
+
+
+def learned_leg(ctx, g, seed=4, count=64):
+    """64 seeded 7-8 vertex templates with cyclomatic number >= 2 (seeds
+    disjoint from the model's training templates): whole prune with the
+    fixed order and with the learned order (model and stopping threshold
+    shipped with the package).  Outputs must be identical."""
+    import torch
+    from paper_1912_08453_amd import inputs as I
+    from paper_1912_08453_amd import order_training as OT
+    ts = I.templates_multicycle(g, seed, count=count)
+    first = ctx.load_templates(ts)
+    ctx.load_model(OT.load_model())
+    thr = OT.load_threshold()
+    n, words = g.n, (g.m + 63) // 64
+    dev = torch.device("cuda", 0)
+    ra = torch.empty((1, n), dtype=torch.int64, device=dev)
+    ea = torch.empty((1, words), dtype=torch.int64, device=dev)
+    rb = torch.empty_like(ra)
+    eb = torch.empty_like(ea)
+    keys = ("ms_total", "ms_nlcc", "ms_lcc", "ms_exact", "constraints")
+    tot = {"fixed": dict.fromkeys(keys, 0.0), "learned": dict.fromkeys(keys, 0.0)}
+    same = True
+    ctx.prune(first, role_mask=ra, edge_bits=ea)   # warm-up
+    for i in range(count):
+        _, _, sf = ctx.prune(first + i, role_mask=ra, edge_bits=ea)
+        _, _, sl = ctx.prune(first + i, order="learned", learned_min_score=thr,
+                             role_mask=rb, edge_bits=eb)
+        same = same and bool(torch.equal(ra, rb) and torch.equal(ea, eb))
+        for k in keys:
+            tot["fixed"][k] += sf[k]
+            tot["learned"][k] += sl[k]
+    out = {"workload": f"{count} multi-cycle templates (7-8 vertices, cyclomatic >= 2, "
+                       f"seed {seed}) on the same graph",
+           "min_score": thr, "outputs_identical": same}
+    for mode in ("fixed", "learned"):
+        out[mode] = {k: round(v, 2) for k, v in tot[mode].items()}
+    out["speedup_total"] = round(tot["fixed"]["ms_total"] / tot["learned"]["ms_total"], 4)
+    cl_f = tot["fixed"]["ms_nlcc"] + tot["fixed"]["ms_lcc"]
+    cl_l = tot["learned"]["ms_nlcc"] + tot["learned"]["ms_lcc"]
+    out["speedup_nlcc_plus_lcc"] = round(cl_f / cl_l, 4) if cl_l > 0 else None
+    return out
 
 
 def cpu_baseline(g, tmpl, budget_s):
