@@ -156,6 +156,7 @@ typedef struct {
     double wave_ms_eq_neg;         /* searches (exact step)                   */
     double wave_ms_certify;        /* wavefront time certifying found matches
                                       and their single-vertex swaps           */
+    double wave_ms_expand;         /* the single-vertex swaps alone           */
     int64_t lcc_sweeps;            /* LCC sweeps run                          */
     int64_t constraints;           /* non-local constraints checked           */
     int64_t first_sweep_vertices;  /* active vertices in the first sweep      */
@@ -168,7 +169,10 @@ typedef struct {
     int64_t vq_pos, vq_neg;        /* vertex-rooted searches found / failed   */
     int64_t eq_pos, eq_neg;        /* edge-rooted searches found / failed     */
     int64_t trace_entries;         /* pm_trace_entry records written          */
-    int64_t reserved[5];
+    int64_t expand_scans;          /* swap scans (found match, template vertex) */
+    int64_t expand_candidates;     /* role-list entries those scans read      */
+    int64_t expand_valid;          /* swaps that gave another match           */
+    int64_t reserved[2];
 } pm_stats;
 
 /* Returns the message for the last error on this thread ("" if none). */

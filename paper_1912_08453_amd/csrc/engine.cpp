@@ -86,12 +86,12 @@ struct Scratch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
-    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expdone, rlcnt, rloff, rlpos, rlcol, rlscan,
+    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
         actbits, ord;
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
                           &ccol, &coff, &segcnt, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
-                          &ccert, &expdone, &rlcnt, &rloff, &rlpos, &rlcol, &rlscan, &actbits, &ord})
+                          &ccert, &expseen, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
@@ -312,6 +312,8 @@ struct Pruner {
         c_rp = w->crp.as<int64_t>();
         launch_exclusive_scan(s, deg, c_rp, n, w->scan_scratch.as<int64_t>(), sl);
         d2h(s, &c_m, c_rp + n, 1);
+        if (c_m > (int64_t)INT32_MAX)
+            throw Error(PM_ERR_CAPACITY, "candidate subgraph has more than 2^31 - 1 entries");
         w->ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
         w->coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
         c_col = w->ccol.as<int32_t>();
@@ -335,6 +337,7 @@ struct Pruner {
         a.m0 = T.m0;
         a.rl_off = w->rloff.as<int64_t>();
         a.rl_col = w->rlcol.as<int32_t>();
+        a.rl_ent = w->rlent.as<int32_t>();
         a.rl_pos = w->rlpos.as<int32_t>();
         a.n0 = T.n0;
         a.mode = mode;
@@ -344,7 +347,8 @@ struct Pruner {
         a.task_counter = ctr + C_TASK;
         a.n_queries = queries;
         a.c_cert = nullptr;
-        a.exp_done = nullptr;
+        a.exp_seen = nullptr;
+        a.exp_log2 = 0;
         a.qstats = nullptr;
         a.expand = 0;
         return a;
@@ -368,8 +372,9 @@ struct Pruner {
         rl_total = 0;
         d2h(s, &rl_total, w->rloff.as<int64_t>() + nA * T.n0, 1);
         w->rlcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
+        w->rlent.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
         launch_role_fill<M>(s, A, nA, c_rp, c_col, om, T.n0, w->rloff.as<int64_t>(),
-                            w->rlcol.as<int32_t>());
+                            w->rlcol.as<int32_t>(), w->rlent.as<int32_t>());
     }
 
     // One non-local constraint (snapshot semantics); returns vertices changed.
@@ -395,17 +400,18 @@ struct Pruner {
         unsigned long long q0 = 0, q1 = 0;
         const int64_t cwords = (c_m + 63) / 64;
         w->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
-        w->expdone.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(n, 1));
+        w->expseen.ensure(sizeof(uint64_t) << kExpSeenLog2);
         uint64_t *c_cert = w->ccert.as<uint64_t>();
         role_lists();
         launch_fill_u64(s, c_cert, cwords, 0ull);
-        launch_fill_u64(s, w->expdone.as<uint64_t>(), n, 0ull);
-        PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 10, s));
+        launch_fill_u64(s, w->expseen.as<uint64_t>(), 1ll << kExpSeenLog2, 0ull);
+        PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 16, s));
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
         SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
         a.c_cert = c_cert;
-        a.exp_done = w->expdone.as<uint64_t>();
+        a.exp_seen = w->expseen.as<unsigned long long>();
+        a.exp_log2 = kExpSeenLog2;
         a.qstats = qstats;
         a.expand = c->expand;
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
@@ -437,10 +443,10 @@ struct Pruner {
                                   a, c->grid_search);
             d2h(s, &q1, queries, 1);
         }
-        launch_edges_from_cert(s, A, nA, c_rp, c_off, c->rp, c_cert, edge_out);
+        launch_edges_from_cert(s, A, nA, c_rp, c_col, c_off, c->rp, c_cert, edge_out);
         launch_widen<M>(s, n, sat, role_out);
-        unsigned long long qs[10];
-        d2h(s, qs, qstats, 10);
+        unsigned long long qs[16];
+        d2h(s, qs, qstats, 16);
         const double tick_ms = c->wall_khz > 0 ? 1.0 / (double)c->wall_khz : 0.0;
         st.vertex_queries += (int64_t)q0;
         st.edge_queries += (int64_t)q1;
@@ -453,6 +459,10 @@ struct Pruner {
         st.wave_ms_eq_pos += (double)qs[6] * tick_ms;
         st.wave_ms_eq_neg += (double)qs[7] * tick_ms;
         st.wave_ms_certify += (double)(qs[8] + qs[9]) * tick_ms;
+        st.wave_ms_expand += (double)qs[10] * tick_ms;
+        st.expand_scans += (int64_t)qs[11];
+        st.expand_candidates += (int64_t)qs[12];
+        st.expand_valid += (int64_t)qs[13];
         st.ms_exact += t.stop();
     }
 
@@ -1003,6 +1013,10 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.wave_ms_eq_pos += st.wave_ms_eq_pos;
             total.wave_ms_eq_neg += st.wave_ms_eq_neg;
             total.wave_ms_certify += st.wave_ms_certify;
+            total.wave_ms_expand += st.wave_ms_expand;
+            total.expand_scans += st.expand_scans;
+            total.expand_candidates += st.expand_candidates;
+            total.expand_valid += st.expand_valid;
             total.trace_entries += st.trace_entries;
         }
         PM_HIP(hipStreamSynchronize(c->stream));

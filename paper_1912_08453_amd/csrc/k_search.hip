@@ -88,10 +88,11 @@ __global__ __launch_bounds__(kSearchBlock) void role_count_kernel(
 
 // Pass 2: fill the lists in row order (so each list is sorted), one ballot
 // per role and 64-entry chunk; lane q keeps the write cursor of role q.
+// rl_ent receives the compacted entry index of every list entry.
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void role_fill_kernel(
     const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
-    const M *omega, int n0, const int64_t *rl_off, int32_t *rl_col) {
+    const M *omega, int n0, const int64_t *rl_off, int32_t *rl_col, int32_t *rl_ent) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -108,7 +109,11 @@ __global__ __launch_bounds__(kSearchBlock) void role_fill_kernel(
                 const uint64_t m = ballot64(has);
                 if (!m) continue;
                 const int64_t at = read_lane64(run, q);
-                if (has) rl_col[at + __popcll(m & lanemask_lt())] = w;
+                if (has) {
+                    const int64_t o = at + __popcll(m & lanemask_lt());
+                    rl_col[o] = w;
+                    rl_ent[o] = (int32_t)k;
+                }
                 if (lane == q) run += __popcll(m);
             }
         }
@@ -129,12 +134,12 @@ void launch_role_count(hipStream_t s, const int32_t *tasks, int64_t n_tasks, con
 template <typename M>
 void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
                       const int32_t *c_col, const M *omega, int n0, const int64_t *rl_off,
-                      int32_t *rl_col) {
+                      int32_t *rl_col, int32_t *rl_ent) {
     if (n_tasks <= 0) return;
     int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(role_fill_kernel<M>, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       tasks, n_tasks, c_rp, c_col, omega, n0, rl_off, rl_col);
+                       tasks, n_tasks, c_rp, c_col, omega, n0, rl_off, rl_col, rl_ent);
 }
 
 // ---------------------------------------------------------------- search
@@ -258,12 +263,23 @@ __device__ void certify_roles(const SearchPlan *__restrict__ P, int32_t img_r, M
         atomic_or_elem<M>(sat, img_r, 1ull << lane);
 }
 
-// Mark the compacted entries u->w and w->u as certified.
-__device__ __forceinline__ void certify_edge(const SearchArgs &a, int32_t u, int32_t w) {
-    const int64_t k1 = find_sorted(a.c_col, a.c_rp[u], a.c_rp[u + 1], w);
-    const int64_t k2 = find_sorted(a.c_col, a.c_rp[w], a.c_rp[w + 1], u);
-    if (k1 >= 0) set_bit(a.c_cert, k1);
-    if (k2 >= 0) set_bit(a.c_cert, k2);
+// An edge is certified through one bit: that of its compacted entry from
+// the smaller to the larger vertex id.
+__device__ __forceinline__ void set_entry(const SearchArgs &a, int64_t rl_index) {
+    set_bit(a.c_cert, a.rl_ent[rl_index]);
+}
+
+// Certify edge {u, w} where u holds role qu and w role qw in the match: the
+// entry min -> max is found in the role list of the smaller vertex for the
+// role of the larger.
+__device__ __forceinline__ void certify_pair(const SearchArgs &a, int32_t u, int qu, int32_t w,
+                                             int qw) {
+    if (u > w) {
+        const int32_t t = u; u = w; w = t;
+        const int tq = qu; qu = qw; qw = tq;
+    }
+    const int64_t p = find_sorted(a.rl_col, rl_begin(a, u, qw), rl_end(a, u, qw), w);
+    if (p >= 0) set_entry(a, p);
 }
 
 // Certify a full match: every role and every template edge.
@@ -281,8 +297,14 @@ __device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict_
         }
         const int32_t u = __shfl(img_r, ta);
         const int32_t w = __shfl(img_r, tb);
-        if (i < a.m0) certify_edge(a, u, w);
+        if (i < a.m0) certify_pair(a, u, ta, w, tb);
     }
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
 }
 
 // Single-vertex swaps of a found match: for each template vertex q, every x
@@ -290,9 +312,18 @@ __device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict_
 // the images of all template neighbours of q, distinct from the images of
 // same-label vertices) gives another match, whose role (x, q) and edges at
 // x are certified.  Purely a saving: anything it misses is queried later.
+// The candidates depend (up to the identity checks) only on q and the
+// images of q's template neighbours, so each such key is scanned once: a
+// hash of the key is exchanged into a table, and a scan whose hash is
+// already there is skipped (a collision or an overwritten slot only skips
+// or repeats a scan, neither of which affects the result).
+struct ExpandCount {
+    unsigned long long scans = 0, cands = 0, valid = 0;
+};
+
 template <typename M>
 __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__ P,
-                             int32_t img_r, const M *__restrict__ om, M *cert) {
+                             int32_t img_r, const M *__restrict__ om, M *cert, ExpandCount &ec) {
     const int lane = lane_id();
     const int32_t *__restrict__ rlc = a.rl_col;
     for (uint64_t mq = P->vmask; mq; mq &= mq - 1) {
@@ -313,19 +344,21 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             }
         }
         const int32_t ys = read_lane32(img_r, js);
-        if (__popcll(nb) == 1 || a.expand == 2) {
-            // a pendant vertex depends (up to identity checks) only on its
-            // neighbour's image: expand it once per (vertex, role pair).
-            // With expand == 2 every vertex is expanded once per (scanned
-            // vertex, role pair), trading missed swaps for edge queries.
-            const int key = (js * a.n0 + q) & 63;
+        {
+            uint64_t h = mix64((uint64_t)q + 1ull);
+            for (uint64_t m = nb; m; m &= m - 1)
+                h = mix64(h ^ (uint64_t)(uint32_t)read_lane32(img_r, __builtin_ctzll(m)));
+            h |= 1ull;
             unsigned long long old = 0;
-            if (lane == 0) old = atomicOr((unsigned long long *)&a.exp_done[ys], 1ull << key);
+            if (lane == 0) old = atomicExch(a.exp_seen + (h >> (64 - a.exp_log2)),
+                                            (unsigned long long)h);
             old = __shfl(old, 0);
-            if ((old >> key) & 1ull) continue;
+            if (old == h) continue;
         }
         const uint64_t others = nb & ~(1ull << js);
         const uint64_t same = P->samelab[q];
+        ++ec.scans;
+        ec.cands += (unsigned long long)(e - s);
         for (int64_t base = s; base < e; base += kWave) {
             const int64_t kk = base + lane;
             const bool in = kk < e;
@@ -340,13 +373,22 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
                 const int64_t y0 = rl_begin(a, y, q), y1 = rl_end(a, y, q);
                 if (ok) ok = find_sorted(rlc, y0, y1, x) >= 0;
             }
+            ec.valid += (unsigned long long)__popcll(ballot64(ok));
             if (ok) {
                 atomic_or_elem<M>(cert, x, 1ull << q);
-                certify_edge(a, ys, x);
-            }
-            for (uint64_t m = others; m; m &= m - 1) {
-                const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
-                if (ok) certify_edge(a, y, x);
+                // the scanned entry ys -> x is at kk of ys's list
+                if (ys < x) set_entry(a, kk);
+                else certify_pair(a, x, q, ys, js);
+                for (uint64_t m = others; m; m &= m - 1) {
+                    const int j = __builtin_ctzll(m);
+                    const int32_t y = read_lane32(img_r, j);
+                    if (y < x) {
+                        const int64_t p = find_sorted(rlc, rl_begin(a, y, q), rl_end(a, y, q), x);
+                        if (p >= 0) set_entry(a, p);
+                    } else {
+                        certify_pair(a, x, q, y, j);
+                    }
+                }
             }
         }
     }
@@ -357,7 +399,8 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                                                                      int64_t n_tasks, const M *om,
                                                                      M *sat, SearchArgs a) {
     const int lane = lane_id();
-    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0, tcert = 0;
+    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0, tcert = 0, texp = 0;
+    ExpandCount ec;
     for (;;) {
         int t0 = 0;
         if (lane == 0) t0 = atomicAdd(a.task_counter, kTaskChunk);
@@ -382,7 +425,11 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                     tpos += c1 - c0;
                     if (a.mode == 1) {
                         certify_match<M>(a, P, img, sat);
-                        if (a.expand) expand_match<M>(a, P, img, om, sat);
+                        if (a.expand) {
+                            const uint64_t c2 = wall_clock64();
+                            expand_match<M>(a, P, img, om, sat, ec);
+                            texp += wall_clock64() - c2;
+                        }
                     } else {
                         certify_roles<M>(P, img, sat);
                     }
@@ -401,6 +448,10 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
             atomicAdd(a.qstats + 2, tpos);
             atomicAdd(a.qstats + 3, tneg);
             atomicAdd(a.qstats + 8, tcert);
+            atomicAdd(a.qstats + 10, texp);
+            atomicAdd(a.qstats + 11, ec.scans);
+            atomicAdd(a.qstats + 12, ec.cands);
+            atomicAdd(a.qstats + 13, ec.valid);
         }
     }
 }
@@ -446,7 +497,7 @@ void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega
 // ------------------------------------------------ exact step: edge part
 // Candidate edges: entries a -> b (a < b) of the compacted subgraph whose
 // certified roles are adjacent in G0 and that no found match certified yet
-// (a certified edge has both of its entries set).
+// (a certified edge has the bit of exactly this entry set).
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
     const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
@@ -503,7 +554,8 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
     const int32_t *eu, const int32_t *ew, const int64_t *e_idx, int64_t n_edges, const M *om,
     M *cert, const int32_t *edge_plan, int32_t n_edge_plans, SearchArgs a) {
     const int lane = lane_id();
-    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0, tcert = 0;
+    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0, tcert = 0, texp = 0;
+    ExpandCount ec;
     for (;;) {
         int t0 = 0;
         if (lane == 0) t0 = atomicAdd(a.task_counter, kTaskChunk);
@@ -527,7 +579,11 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
                     ++npos;
                     tpos += c1 - c0;
                     certify_match<M>(a, P, img, cert);
-                    if (a.expand) expand_match<M>(a, P, img, om, cert);
+                    if (a.expand) {
+                        const uint64_t c2 = wall_clock64();
+                        expand_match<M>(a, P, img, om, cert, ec);
+                        texp += wall_clock64() - c2;
+                    }
                     tcert += wall_clock64() - c1;
                     break;
                 }
@@ -543,6 +599,10 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
             atomicAdd(a.qstats + 6, tpos);
             atomicAdd(a.qstats + 7, tneg);
             atomicAdd(a.qstats + 9, tcert);
+            atomicAdd(a.qstats + 10, texp);
+            atomicAdd(a.qstats + 11, ec.scans);
+            atomicAdd(a.qstats + 12, ec.cands);
+            atomicAdd(a.qstats + 13, ec.valid);
         }
     }
 }
@@ -557,29 +617,36 @@ void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
                        e_idx, n_edges, omega, cert, edge_plan_dev, n_edge_plans, a);
 }
 
-// Output edge bits from certified compacted entries.
+// Output edge bits from certified compacted entries (each certified edge
+// holds the bit of its entry u -> w with u < w): both CSR entries of the
+// edge are set; the reverse entry is found in w's compacted row.
 __global__ __launch_bounds__(kSearchBlock) void edges_from_cert_kernel(
-    const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_off,
-    const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
+    const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
+    const int32_t *c_off, const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     for (int64_t t = wave; t < n_tasks; t += nwaves) {
         const int32_t u = tasks[t];
         const int64_t s = c_rp[u], e = c_rp[u + 1], r0 = rp[u];
-        for (int64_t k = s + lane; k < e; k += kWave)
-            if (test_bit(c_cert, k)) set_bit(edge_bits, r0 + c_off[k]);
+        for (int64_t k = s + lane; k < e; k += kWave) {
+            if (!test_bit(c_cert, k)) continue;
+            set_bit(edge_bits, r0 + c_off[k]);
+            const int32_t w = c_col[k];
+            const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
+            if (kr >= 0) set_bit(edge_bits, rp[w] + c_off[kr]);
+        }
     }
 }
 
 void launch_edges_from_cert(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_off, const int64_t *rp,
-                            const uint64_t *c_cert, uint64_t *edge_bits) {
+                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
+                            const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
     if (n_tasks <= 0) return;
     int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(edges_from_cert_kernel, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       tasks, n_tasks, c_rp, c_off, rp, c_cert, edge_bits);
+                       tasks, n_tasks, c_rp, c_col, c_off, rp, c_cert, edge_bits);
 }
 
 // Edge state implied by role sets (edge elimination rule): bit of entry
@@ -618,7 +685,7 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                                        const int32_t *, const M *, int, int64_t *, int32_t *);    \
     template void launch_role_fill<M>(hipStream_t, const int32_t *, int64_t, const int64_t *,     \
                                       const int32_t *, const M *, int, const int64_t *,           \
-                                      int32_t *);                                                 \
+                                      int32_t *, int32_t *);                                      \
     template void launch_vertex_search<M>(hipStream_t, const int32_t *, int64_t, const M *, M *,  \
                                           const SearchArgs &, int);                               \
     template void launch_apply<M>(hipStream_t, const int32_t *, int64_t, M *, M *, uint64_t,      \

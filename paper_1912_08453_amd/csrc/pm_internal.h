@@ -19,6 +19,7 @@ constexpr int kBinSmallMaxDeg = 8;   // 4 lanes per vertex
 constexpr int kBinMidMaxDeg = 64;    // 16 lanes per vertex
 constexpr int kBinWaveMaxDeg = 4096; // one wavefront per vertex
 constexpr int kHubSegment = 4096;    // entries per wavefront for larger vertices
+constexpr int kExpSeenLog2 = 22;     // slots of the swap-scan table (32 MiB)
 constexpr int kNumBins = 4;          // small, mid, wave, hub
 
 // Local-rule tables of one template (LCC algorithm; distinct-count rule of
@@ -207,6 +208,7 @@ struct SearchArgs {
     int32_t m0;
     const int64_t *rl_off;          // role lists: [tasks * n0 + 1] offsets into rl_col
     const int32_t *rl_col;
+    const int32_t *rl_ent;          // compacted entry index of each list entry
     const int32_t *rl_pos;          // list position (task index) of each listed vertex
     int32_t n0;
     int32_t mode;
@@ -215,14 +217,16 @@ struct SearchArgs {
     uint64_t *edge_bits;
     int32_t *task_counter;
     unsigned long long *n_queries;
-    // exact step: certified entries of the compacted subgraph (bit k = entry
-    // k; both entries of an edge are set together), per-vertex expansion
-    // flags (bit q = pendant role q expanded from this vertex), query
-    // statistics
+    // exact step: certified edges of the compacted subgraph (bit k = entry k
+    // = u -> w with u < w), the table of swap scans
+    // already done (hashes of (role, images of its template neighbours);
+    // exp_slots entries, a power of two), query statistics
     uint64_t *c_cert;
-    uint64_t *exp_done;
-    unsigned long long *qstats;     // [10]: vpos, vneg, vpos_t, vneg_t, epos, eneg, epos_t,
-                                    // eneg_t, vcert_t, ecert_t (wall-clock ticks)
+    unsigned long long *exp_seen;
+    int32_t exp_log2;
+    unsigned long long *qstats;     // [16]: vpos, vneg, vpos_t, vneg_t, epos, eneg, epos_t,
+                                    // eneg_t, vcert_t, ecert_t, expand_t (wall-clock
+                                    // ticks), expand scans, candidates, valid swaps
     int32_t expand;                 // run the single-vertex swap expansion
 };
 
@@ -237,12 +241,13 @@ void launch_role_count(hipStream_t s, const int32_t *tasks, int64_t n_tasks, con
 template <typename M>
 void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
                       const int32_t *c_col, const M *omega, int n0, const int64_t *rl_off,
-                      int32_t *rl_col);
+                      int32_t *rl_col, int32_t *rl_ent);
 
-// Output edge bits from certified compacted entries.
+// Output edge bits (both entries) from certified compacted entries u -> w,
+// u < w.
 void launch_edges_from_cert(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_off, const int64_t *rp,
-                            const uint64_t *c_cert, uint64_t *edge_bits);
+                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
+                            const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits);
 
 template <typename M>
 void launch_vertex_search(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,

@@ -79,12 +79,13 @@ class pm_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("ms_total", "ms_init", "ms_lcc", "ms_compact", "ms_nlcc", "ms_exact",
                  "ms_first_sweep", "ms_sweep_kernel", "wave_ms_vq_pos", "wave_ms_vq_neg",
-                 "wave_ms_eq_pos", "wave_ms_eq_neg", "wave_ms_certify")] + \
+                 "wave_ms_eq_pos", "wave_ms_eq_neg", "wave_ms_certify", "wave_ms_expand")] + \
                [(k, ctypes.c_int64) for k in
                 ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
                  "candidate_entries", "vertex_queries", "edge_queries", "result_vertices",
-                 "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries")] + \
-               [("reserved", ctypes.c_int64 * 5)]
+                 "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries", "expand_scans",
+                 "expand_candidates", "expand_valid")] + \
+               [("reserved", ctypes.c_int64 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
