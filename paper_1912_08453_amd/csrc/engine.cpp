@@ -123,6 +123,7 @@ struct pm_ctx {
     std::vector<std::unique_ptr<pm::Scratch>> scratch;
     int grid_search = 2048;
     int expand = 1;
+    int64_t expand_max = INT64_MAX;
     int64_t wall_khz = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
@@ -351,6 +352,8 @@ struct Pruner {
         a.exp_log2 = 0;
         a.qstats = nullptr;
         a.expand = 0;
+        a.expand_max = c->expand_max;
+        a.check_om = 0;
         return a;
     }
 
@@ -437,6 +440,9 @@ struct Pruner {
                                   sizeof(int32_t) * T.edge_plans.size(), hipMemcpyHostToDevice, s));
             PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
             PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
+            // the edge searches read the certified role sets, a subset of
+            // those the role lists were built from
+            a.check_om = 1;
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
                                   w->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
@@ -752,6 +758,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
                 c->wall_khz = khz;
             const char *ex = getenv("PM_EXPAND");
             if (ex) c->expand = atoi(ex);
+            const char *em = getenv("PM_EXPAND_MAX");
+            if (em) c->expand_max = atoll(em);
         } catch (...) {
             delete c;
             throw;

@@ -142,6 +142,49 @@ void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, cons
                        tasks, n_tasks, c_rp, c_col, omega, n0, rl_off, rl_col, rl_ent);
 }
 
+// ----------------------------------------------------- sorted-list search
+// Membership of each lane's key x in one sorted list col[lo, hi) shared by
+// the whole wavefront (all lanes call with the same bounds; lanes with
+// !want get -1).  One coalesced load fetches 64 evenly spaced samples of
+// the list (the whole list when it is at most 64 long); each lane finds its
+// segment among them through lane shuffles and finishes with a binary
+// search of that segment only, so a list of length L costs one load plus
+// log2(L / 64) dependent loads instead of log2(L).  Returns the position of
+// x or -1.
+__device__ __forceinline__ int64_t wave_find(const int32_t *__restrict__ col, int64_t lo,
+                                             int64_t hi, int32_t x, bool want) {
+    const int lane = lane_id();
+    const int64_t len = hi - lo;
+    if (len <= 0) return -1;
+    const bool small = len <= kWave;
+    const int64_t sp = small ? lo + lane : lo + ((len * lane) >> 6);
+    const int32_t sv = (!small || lane < len) ? col[sp] : INT32_MAX;
+    // largest sample index i with sample_i <= x (upper bound - 1); samples
+    // are non-decreasing over the lanes
+    int lo_i = 0, cnt = kWave;
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int half = cnt >> 1;
+        const int mid = lo_i + half;
+        const int32_t mv = __shfl(sv, mid);
+        if (mv <= x) {
+            lo_i = mid;
+            cnt -= half;
+        } else {
+            cnt = half;
+        }
+    }
+    // lo_i: the last sample <= x, or 0 with sample_0 > x
+    // every lane takes part in the shuffles before any lane leaves
+    const int32_t v0 = __shfl(sv, lo_i);
+    const int64_t p0 = __shfl(sp, lo_i);
+    const int64_t p1 = __shfl(sp, lo_i + 1 < kWave ? lo_i + 1 : lo_i);
+    if (!want || v0 > x) return -1;
+    if (v0 == x) return p0;
+    if (small) return -1;
+    return find_sorted(col, p0 + 1, lo_i == kWave - 1 ? hi : p1, x);
+}
+
 // ---------------------------------------------------------------- search
 // Every vertex a search reaches holds a role, so it is in the task list the
 // role lists were built from and has a list position.
@@ -223,15 +266,16 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
             const int64_t kk = cur + lane;
             const bool in_range = kk < end;
             const int32_t x = in_range ? rlc[kk] : -1;
-            bool ok = in_range && (((uint64_t)om[x] >> q) & 1ull);
+            bool ok = in_range && (!a.check_om || (((uint64_t)om[x] >> q) & 1ull));
             for (uint64_t m = same; m; m &= m - 1) {
                 const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
                 ok = ok && (y != x);
             }
             for (uint64_t m = back; m; m &= m - 1) {
+                if (!ballot64(ok)) break;
                 const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
                 const int64_t ys = rl_begin(a, y, q), ye = rl_end(a, y, q);
-                if (ok) ok = find_sorted(rlc, ys, ye, x) >= 0;
+                ok = wave_find(rlc, ys, ye, x, ok) >= 0;
             }
             const uint64_t b = ballot64(ok);
             if (lane == lvl) {
@@ -330,19 +374,28 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
         const int q = __builtin_ctzll(mq);
         const uint64_t nb = P->adj[q];
         if (!nb) continue;
+        // lane j (a template neighbour of q) holds the bounds of the q-list
+        // of its image
+        int64_t lb_r = 0, le_r = 0;
+        if ((nb >> lane) & 1ull) {
+            lb_r = rl_begin(a, img_r, q);
+            le_r = rl_end(a, img_r, q);
+        }
+        // scan the shortest list; test the others shortest first (the most
+        // selective), at most kOrd of them in that order, the rest by index
+        constexpr int kOrd = 10;
         int js = -1;
-        int64_t bd = INT64_MAX, s = 0, e = 0;
+        int64_t bd = INT64_MAX;
         for (uint64_t m = nb; m; m &= m - 1) {
             const int j = __builtin_ctzll(m);
-            const int32_t y = read_lane32(img_r, j);
-            const int64_t b0 = rl_begin(a, y, q), e0 = rl_end(a, y, q);
-            if (e0 - b0 < bd) {
-                bd = e0 - b0;
+            const int64_t len = read_lane64(le_r, j) - read_lane64(lb_r, j);
+            if (len < bd) {
+                bd = len;
                 js = j;
-                s = b0;
-                e = e0;
             }
         }
+        const int64_t s = read_lane64(lb_r, js), e = read_lane64(le_r, js);
+        if (e - s > a.expand_max) continue;
         const int32_t ys = read_lane32(img_r, js);
         {
             uint64_t h = mix64((uint64_t)q + 1ull);
@@ -355,7 +408,24 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             old = __shfl(old, 0);
             if (old == h) continue;
         }
-        const uint64_t others = nb & ~(1ull << js);
+        uint64_t rest = nb & ~(1ull << js);
+        uint64_t ordc = 0;
+        int nord = 0;
+        while (rest && nord < kOrd) {
+            int bj = -1;
+            int64_t bl = INT64_MAX;
+            for (uint64_t m = rest; m; m &= m - 1) {
+                const int j = __builtin_ctzll(m);
+                const int64_t len = read_lane64(le_r, j) - read_lane64(lb_r, j);
+                if (len < bl) {
+                    bl = len;
+                    bj = j;
+                }
+            }
+            ordc |= (uint64_t)bj << (6 * nord);
+            ++nord;
+            rest &= ~(1ull << bj);
+        }
         const uint64_t same = P->samelab[q];
         ++ec.scans;
         ec.cands += (unsigned long long)(e - s);
@@ -363,15 +433,29 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             const int64_t kk = base + lane;
             const bool in = kk < e;
             const int32_t x = in ? rlc[kk] : -1;
-            bool ok = in && (((uint64_t)om[x] >> q) & 1ull);
+            bool ok = in && (!a.check_om || (((uint64_t)om[x] >> q) & 1ull));
             for (uint64_t m = same; m; m &= m - 1) {
                 const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
                 ok = ok && (x != y);
             }
-            for (uint64_t m = others; m; m &= m - 1) {
-                const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
-                const int64_t y0 = rl_begin(a, y, q), y1 = rl_end(a, y, q);
-                if (ok) ok = find_sorted(rlc, y0, y1, x) >= 0;
+            // adjacency to the other neighbours' images; positions kept for
+            // the first three (certification of entries y -> x, y < x)
+            int64_t p0 = -1, p1 = -1, p2 = -1;
+            for (int i = 0; i < nord; ++i) {
+                if (!ballot64(ok)) break;
+                const int j = (int)((ordc >> (6 * i)) & 63ull);
+                const int64_t y0 = read_lane64(lb_r, j), y1 = read_lane64(le_r, j);
+                const int64_t p = wave_find(rlc, y0, y1, x, ok);
+                ok = p >= 0;
+                if (i == 0) p0 = p;
+                else if (i == 1) p1 = p;
+                else if (i == 2) p2 = p;
+            }
+            for (uint64_t m = rest; m; m &= m - 1) {
+                if (!ballot64(ok)) break;
+                const int j = __builtin_ctzll(m);
+                const int64_t y0 = read_lane64(lb_r, j), y1 = read_lane64(le_r, j);
+                ok = wave_find(rlc, y0, y1, x, ok) >= 0;
             }
             ec.valid += (unsigned long long)__popcll(ballot64(ok));
             if (ok) {
@@ -379,11 +463,24 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
                 // the scanned entry ys -> x is at kk of ys's list
                 if (ys < x) set_entry(a, kk);
                 else certify_pair(a, x, q, ys, js);
-                for (uint64_t m = others; m; m &= m - 1) {
+                for (int i = 0; i < nord; ++i) {
+                    const int j = (int)((ordc >> (6 * i)) & 63ull);
+                    const int32_t y = read_lane32(img_r, j);
+                    if (y < x) {
+                        int64_t p = i == 0 ? p0 : (i == 1 ? p1 : (i == 2 ? p2 : -1));
+                        if (p < 0)
+                            p = find_sorted(rlc, read_lane64(lb_r, j), read_lane64(le_r, j), x);
+                        if (p >= 0) set_entry(a, p);
+                    } else {
+                        certify_pair(a, x, q, y, j);
+                    }
+                }
+                for (uint64_t m = rest; m; m &= m - 1) {
                     const int j = __builtin_ctzll(m);
                     const int32_t y = read_lane32(img_r, j);
                     if (y < x) {
-                        const int64_t p = find_sorted(rlc, rl_begin(a, y, q), rl_end(a, y, q), x);
+                        const int64_t p =
+                            find_sorted(rlc, read_lane64(lb_r, j), read_lane64(le_r, j), x);
                         if (p >= 0) set_entry(a, p);
                     } else {
                         certify_pair(a, x, q, y, j);

@@ -228,6 +228,9 @@ struct SearchArgs {
                                     // eneg_t, vcert_t, ecert_t, expand_t (wall-clock
                                     // ticks), expand scans, candidates, valid swaps
     int32_t expand;                 // run the single-vertex swap expansion
+    int64_t expand_max;             // longest list a swap scan reads
+    int32_t check_om;               // candidates' role sets may have shrunk since
+                                    // the role lists were built: test them
 };
 
 // Role lists of the vertices in tasks over the compacted subgraph: pass 1
