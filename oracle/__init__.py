@@ -66,6 +66,8 @@ def _load():
     lib.orc_active_edges.argtypes = [I64, P, P, P, I32, I32, P, P, P]
     lib.orc_exact_subset.restype = I64
     lib.orc_exact_subset.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64]
+    lib.orc_exact_sample.restype = I64
+    lib.orc_exact_sample.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64, P, P, P]
     lib.orc_num_threads.restype = I32
     lib.orc_set_threads.restype = None
     lib.orc_set_threads.argtypes = [I32]
@@ -156,6 +158,41 @@ def exact_subset(g: _G, t: _T, omega: np.ndarray, verts: np.ndarray) -> int:
     if r < 0:
         raise ValueError("bad template")
     return int(r)
+
+
+def exact_sample(g: _G, t: _T, omega: np.ndarray, verts: np.ndarray):
+    """Exact-step results for the given vertices: (role masks uint64[len],
+    per-entry membership uint8 over the concatenated rows of the vertices,
+    row offsets int64[len + 1]).  omega: any sound state (superset of the
+    complete set)."""
+    vs = np.ascontiguousarray(verts, dtype=np.int32)
+    deg = (g.row_ptr[vs.astype(np.int64) + 1] - g.row_ptr[vs]) if vs.size else np.zeros(0, np.int64)
+    off = np.zeros(vs.shape[0] + 1, dtype=np.int64)
+    np.cumsum(deg, out=off[1:])
+    role = np.zeros(max(vs.shape[0], 1), dtype=np.uint64)
+    inc = np.zeros(max(int(off[-1]), 1), dtype=np.uint8)
+    om = np.ascontiguousarray(omega, dtype=np.uint64)
+    r = _load().orc_exact_sample(g.n, _p(g.row_ptr), _p(g.col), _p(om), t.n0, t.m0,
+                                 _p(t.labels), _p(t.edges), _p(vs), vs.shape[0], _p(role),
+                                 _p(off), _p(inc))
+    if r < 0:
+        raise ValueError("bad template")
+    return role[:vs.shape[0]], inc[:int(off[-1])], off
+
+
+def state(row_ptr, col, labels, t_labels, t_edges, order=None):
+    """omega after the first LCC fixpoint and every non-local constraint
+    (the constraint loop of `prune` without the exact step)."""
+    g = _G(row_ptr, col, labels)
+    t = _T(t_labels, t_edges)
+    K0 = constraints_for(t.label_list, t.edge_list)
+    seq = list(range(len(K0))) if order is None else list(order)
+    omega = init_roles(g, t)
+    lcc(g, t, omega)
+    for ci in seq:
+        if nlcc(g, omega, K0[ci]):
+            lcc(g, t, omega)
+    return omega
 
 
 def active_edges(g: _G, t: _T, omega: np.ndarray) -> np.ndarray:

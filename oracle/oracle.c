@@ -505,3 +505,63 @@ int64_t orc_exact_subset(int64_t n, const int64_t *row_ptr, const int32_t *col,
     free(eplan);
     return searches;
 }
+
+/* Exact-step results for sampled vertices only (parity checks at sizes the
+ * full exact step cannot be run on the CPU): role_out[i] = the roles q in
+ * omega(verts[i]) for which a full match with phi(q) = verts[i] exists, and
+ * for the j-th CSR entry verts[i] -> w, inc_out[inc_off[i] + j] = 1 iff some
+ * full match maps a template edge onto it (edge-pinned search over both
+ * orientations of every template edge), else 0.  omega must be a sound
+ * superset of the complete set (any state the constraint loop reaches).
+ * Returns the number of searches, or -1 for a bad template. */
+int64_t orc_exact_sample(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                         const uint64_t *omega, int n0, int m0, const int32_t *tl,
+                         const int32_t *te, const int32_t *verts, int64_t nverts,
+                         uint64_t *role_out, const int64_t *inc_off, uint8_t *inc_out) {
+    tmpl_t T;
+    if (load_tmpl(&T, n0, m0, tl, te)) return -1;
+    graph_t G = {n, row_ptr, col, NULL};
+    uint64_t vmask = (n0 == 64) ? ~0ull : ((1ull << n0) - 1ull);
+    plan_t vplan[64];
+    for (int q = 0; q < n0; ++q) make_plan(&vplan[q], vmask, T.adj, q, -1);
+    plan_t *eplan = (plan_t *)malloc(sizeof(plan_t) * (size_t)(2 * m0 > 0 ? 2 * m0 : 1));
+    for (int i = 0; i < m0; ++i) {
+        make_plan(&eplan[2 * i], vmask, T.adj, T.ea[i], T.eb[i]);
+        make_plan(&eplan[2 * i + 1], vmask, T.adj, T.eb[i], T.ea[i]);
+    }
+    int64_t searches = 0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(+:searches)
+    for (int64_t i = 0; i < nverts; ++i) {
+        const int32_t v = verts[i];
+        uint64_t r = 0;
+        if (n0 == 1) {
+            r = omega[v] & 1ull;
+        } else {
+            for (int q = 0; q < n0; ++q) {
+                if (!((omega[v] >> q) & 1)) continue;
+                int32_t img[64];
+                img[0] = v;
+                ++searches;
+                if (extend(&G, omega, &vplan[q], 1, img)) r |= 1ull << q;
+            }
+        }
+        role_out[i] = r;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            uint8_t hit = 0;
+            const int32_t w = col[e];
+            if (r && omega[w]) {
+                for (int k = 0; k < 2 * m0 && !hit; ++k) {
+                    const plan_t *P = &eplan[k];
+                    if (!((r >> P->q[0]) & 1) || !((omega[w] >> P->q[1]) & 1)) continue;
+                    int32_t img[64];
+                    img[0] = v; img[1] = w;
+                    ++searches;
+                    if (extend(&G, omega, P, 2, img)) hit = 1;
+                }
+            }
+            inc_out[inc_off[i] + (e - row_ptr[v])] = hit;
+        }
+    }
+    free(eplan);
+    return searches;
+}

@@ -423,6 +423,7 @@ struct Pruner {
         std::swap(om, sat);   // collect() reads `om`: use the certified sets
         collect(false);
         std::swap(om, sat);
+        st.result_vertices = nA;
         const int64_t cap = c_m / 2 + 1;
         w->eu.ensure(sizeof(int32_t) * (size_t)cap);
         w->ew.ensure(sizeof(int32_t) * (size_t)cap);
@@ -650,6 +651,7 @@ struct Pruner {
             launch_widen<M>(s, n, om, role_out);
             if (T.n0 > 1)
                 launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, T.lcc, edge_out);
+            st.result_vertices = nA;
         } else {
             if (nA > 0) compact();
             exact(role_out, edge_out);

@@ -541,3 +541,79 @@ def model_params(seed: int, n_params: int = 5122, fan_ins=((768, 12), (64, 0), (
     w = np.concatenate(parts).astype(np.float32)
     assert w.shape[0] == n_params
     return w
+
+
+# Large exploratory workload: an 8-vertex theta graph (edge q0-q1, path
+# q1-q2-q3-q4-q0 of length 4, path q1-q5-q6-q0 of length 3; cyclomatic number
+# 2) with a pendant q7 on q6, and one repeated label on q3 and q7, which are
+# 4 hops apart (q7-q6-q0-q4-q3), so the constraint list holds a path
+# constraint of length 4.
+CFG5_EDGES = [(0, 1), (1, 2), (2, 3), (3, 4), (0, 4), (1, 5), (5, 6), (0, 6), (6, 7)]
+CFG5_REPEAT = (3, 7)
+
+
+def template_cfg5(graph: "Graph", seed: int) -> Template:
+    """The 8-vertex two-cycle base template with labels from an occurrence
+    in the graph (so it has at least one match)."""
+    return extract_template(graph, 8, CFG5_EDGES, seed, repeat_pairs=[CFG5_REPEAT],
+                            name=f"theta8+pendant/s{seed}")
+
+
+def _connected(n0: int, edges) -> bool:
+    adj = [[] for _ in range(n0)]
+    for a, b in edges:
+        adj[a].append(b)
+        adj[b].append(a)
+    seen, stack = {0}, [0]
+    while stack:
+        x = stack.pop()
+        for y in adj[x]:
+            if y not in seen:
+                seen.add(y)
+                stack.append(y)
+    return len(seen) == n0
+
+
+def _canonical(labels, edges):
+    """Smallest sorted edge list over the label-preserving relabellings of
+    the vertices (vertices ordered by label, ties permuted)."""
+    import itertools
+    n0 = len(labels)
+    groups = {}
+    for q in range(n0):
+        groups.setdefault(labels[q], []).append(q)
+    keys = sorted(groups)
+    slots = []
+    for L in keys:
+        slots += [L] * len(groups[L])
+    best = None
+    for choice in itertools.product(*[itertools.permutations(groups[L]) for L in keys]):
+        order = [q for grp in choice for q in grp]
+        pos = {q: i for i, q in enumerate(order)}
+        es = tuple(sorted(tuple(sorted((pos[a], pos[b]))) for a, b in edges))
+        if best is None or es < best:
+            best = es
+    return tuple(slots), best
+
+
+def relaxations(t: Template, max_deletions: int = 2) -> List[Template]:
+    """The template and every variant with 1..max_deletions edges deleted
+    that still spans all template vertices connectedly, deduplicated up to
+    label-preserving isomorphism; base first, then by deletion count and
+    deleted-edge indices."""
+    import itertools
+    out = [t]
+    seen = {_canonical(t.labels, t.edges)}
+    m0 = len(t.edges)
+    for d in range(1, max_deletions + 1):
+        for dels in itertools.combinations(range(m0), d):
+            es = [e for i, e in enumerate(t.edges) if i not in dels]
+            if not _connected(len(t.labels), es):
+                continue
+            key = _canonical(t.labels, es)
+            if key in seen:
+                continue
+            seen.add(key)
+            out.append(Template(list(t.labels), es,
+                                f"{t.name}-del{'.'.join(str(i) for i in dels)}"))
+    return out

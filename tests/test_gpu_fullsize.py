@@ -1,0 +1,207 @@
+"""GPU parity at the benchmark's full sizes and launch configurations.
+
+The whole exact step is too slow on the CPU at these sizes, so each case is
+checked in three ways, all against the oracle or against facts that hold at
+any size:
+  * the state after the first LCC fixpoint and every non-local constraint
+    (stop before the final search) bit-exactly against the oracle's state,
+    over all vertices and all edges;
+  * the final complete set on seeded vertex samples -- roles and the
+    membership of every incident edge -- against the oracle's exact step run
+    for those vertices only (sampled from the oracle's own state: vertices it
+    keeps and vertices it prunes);
+  * properties of the whole output: it lies inside the oracle's state, edge
+    bits are symmetric, an edge bit implies roles at both ends, and a vertex
+    has roles iff it has an edge bit.
+The scale-26 exploratory workload (a base template and its relaxations, one
+batch with the learned order) takes about two minutes, most of it building
+the graph on the host: it runs when PM_TEST_SCALE26=1.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import constraints as C
+from paper_1912_08453_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def pmmod():
+    from paper_1912_08453_amd import pm
+    pm.load_library()
+    return pm
+
+
+def _graph(scale, seed):
+    rp, col = I.rmat_csr(scale, seed=seed)
+    return I.Graph(rp, col, I.labels_log2deg(rp))
+
+
+@pytest.fixture(scope="module")
+def g22():
+    return _graph(22, 22)
+
+
+@pytest.fixture(scope="module")
+def ctx22(pmmod, torch_dev, g22):
+    torch, dev = torch_dev
+    ctx = pmmod.PM(0)
+    ctx.load_graph(torch.from_numpy(g22.row_ptr).to(dev), torch.from_numpy(g22.col).to(dev),
+                   torch.from_numpy(g22.labels).to(dev))
+    yield ctx
+    ctx.close()
+
+
+def _bits(words, m):
+    return np.unpackbits(np.ascontiguousarray(words).view(np.uint8), bitorder="little")[:m]
+
+
+def check_intermediate(pmmod, ctx, tid, g, t):
+    """State after all constraints, GPU vs oracle, every vertex and edge."""
+    K = len(C.non_local_constraints(t.labels, t.edges))
+    role, edge, _ = ctx.prune(tid, stop_after=K)
+    om = oracle.state(g.row_ptr, g.col, g.labels, t.labels, t.edges)
+    gg, tt = oracle._G(g.row_ptr, g.col, g.labels), oracle._T(t.labels, t.edges)
+    r = pmmod.to_u64(role[0])
+    assert np.array_equal(r, om), f"{int((r != om).sum())} role masks differ"
+    e = pmmod.to_u64(edge[0])
+    assert np.array_equal(e, oracle.active_edges(gg, tt, om))
+    return om
+
+
+def check_final(pmmod, g, t, om, r, e, n_keep=1200, n_pruned=300, seed=0):
+    """Sampled exact step and whole-output properties."""
+    gg, tt = oracle._G(g.row_ptr, g.col, g.labels), oracle._T(t.labels, t.edges)
+    n, m = g.n, g.m
+    rng = np.random.Generator(np.random.Philox(seed))
+    om0 = oracle.init_roles(gg, tt)
+    kept = np.nonzero(om)[0]
+    pruned = np.nonzero((om0 != 0) & (om == 0))[0]
+    s1 = rng.choice(kept, size=min(n_keep, kept.size), replace=False) if kept.size else kept
+    s2 = rng.choice(pruned, size=min(n_pruned, pruned.size), replace=False) if pruned.size else pruned
+    verts = np.sort(np.concatenate([s1, s2]).astype(np.int32))
+    want_r, want_inc, off = oracle.exact_sample(gg, tt, om, verts)
+    bits = _bits(e, m)
+    assert np.array_equal(r[verts], want_r), \
+        f"{int((r[verts] != want_r).sum())} sampled role masks differ"
+    for i, v in enumerate(verts):
+        got = bits[g.row_ptr[v]:g.row_ptr[v + 1]]
+        assert np.array_equal(got, want_inc[off[i]:off[i + 1]]), f"edges of vertex {v}"
+    # properties over the whole output
+    assert not np.any(r & ~om), "complete set outside the constraint-loop state"
+    on = np.nonzero(bits)[0]
+    u = np.searchsorted(g.row_ptr, on, side="right").astype(np.int64) - 1
+    w = g.col[on].astype(np.int64)
+    assert np.all(r[u] != 0) and np.all(r[w] != 0)
+    fwd = np.sort(u * n + w)
+    assert np.array_equal(fwd, np.sort(w * n + u)), "edge bits not symmetric"
+    has_edge = np.zeros(n, dtype=bool)
+    has_edge[u] = True
+    assert np.array_equal(has_edge, r != 0), "roles without edges or edges without roles"
+    log(f"  sampled {verts.size} vertices ({s1.size} kept, {s2.size} pruned), "
+        f"{int((r != 0).sum())} result vertices, {on.size} result entries")
+
+
+def test_config2_full_size(pmmod, ctx22, g22):
+    """R-MAT scale 22, log2-degree labels, triangle+square+pendant template
+    with a repeated label (template seed 0): the benchmark's workload."""
+    t = I.template_cfg2(g22, 0)
+    tid = ctx22.load_templates([t])
+    log(f"config2 scale22 t={t.labels}")
+    om = check_intermediate(pmmod, ctx22, tid, g22, t)
+    role, edge, _ = ctx22.prune(tid)
+    check_final(pmmod, g22, t, om, pmmod.to_u64(role[0]), pmmod.to_u64(edge[0]))
+
+
+def test_config3_batch_full_size(pmmod, ctx22, g22, torch_dev):
+    """64 mixed templates in one call on 4 concurrent streams (the
+    benchmark's batched leg): every template's output equals its own
+    one-template call, and seeded templates are checked against the oracle."""
+    torch, dev = torch_dev
+    ts = I.templates_batch(g22, 3, count=64)
+    first = ctx22.load_templates(ts)
+    n, words = g22.n, (g22.m + 63) // 64
+    rb = torch.empty((64, n), dtype=torch.int64, device=dev)
+    eb = torch.empty((64, words), dtype=torch.int64, device=dev)
+    ctx22.prune(first, count=64, role_mask=rb, edge_bits=eb, batch_streams=4)
+    rng = np.random.Generator(np.random.Philox(33))
+    pick = sorted(int(x) for x in rng.choice(64, size=4, replace=False))
+    for i in pick:
+        t = ts[i]
+        log(f"config3 template {i} n0={t.n0} labels={t.labels}")
+        role, edge, _ = ctx22.prune(first + i)
+        assert torch.equal(role[0], rb[i]) and torch.equal(edge[0], eb[i])
+        om = check_intermediate(pmmod, ctx22, first + i, g22, t)
+        check_final(pmmod, g22, t, om, pmmod.to_u64(rb[i]), pmmod.to_u64(eb[i]), n_keep=200,
+                    n_pruned=50, seed=i)
+
+
+def test_config4_learned_order_full_size(pmmod, ctx22, g22):
+    """Multi-cycle templates of the learned-order workload with the shipped
+    model and threshold: output identical to the fixed order over all
+    vertices and edges, and checked against the oracle on samples."""
+    from paper_1912_08453_amd import order_training as OT
+    ts = I.templates_multicycle(g22, 4, count=64)
+    ctx22.load_model(OT.load_model())
+    thr = OT.load_threshold()
+    for i in (0, 42):
+        t = ts[i]
+        tid = ctx22.load_templates([t])
+        log(f"config4 template {i} labels={t.labels}")
+        rf, ef, _ = ctx22.prune(tid)
+        rf, ef = rf.clone(), ef.clone()
+        rl, el, st = ctx22.prune(tid, order="learned", learned_min_score=thr)
+        assert bool((rf == rl).all()) and bool((ef == el).all())
+        om = oracle.state(g22.row_ptr, g22.col, g22.labels, t.labels, t.edges)
+        check_final(pmmod, g22, t, om, pmmod.to_u64(rl[0]), pmmod.to_u64(el[0]), n_keep=300,
+                    n_pruned=100, seed=100 + i)
+
+
+@pytest.mark.skipif(os.environ.get("PM_TEST_SCALE26") != "1",
+                    reason="scale-26 workload: set PM_TEST_SCALE26=1 (about two minutes)")
+def test_config5_scale26_relaxation_batch(pmmod, torch_dev):
+    """R-MAT scale 26 (2.1 billion entries), the 8-vertex two-cycle base
+    template with a repeated-label pair 4 hops apart and its connected
+    1- and 2-edge-deletion relaxations, pruned as one batch on concurrent
+    streams with the learned order (the benchmark's configuration): seeded
+    variants checked against the oracle."""
+    from paper_1912_08453_amd import order_training as OT
+    torch, dev = torch_dev
+    g = _graph(26, 26)
+    base = I.template_cfg5(g, 0)
+    ts = I.relaxations(base)
+    log(f"config5 scale26 m={g.m} variants={len(ts)} base={base.labels}")
+    ctx = pmmod.PM(0)
+    ctx.load_graph(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                   torch.from_numpy(g.labels).to(dev))
+    first = ctx.load_templates(ts)
+    ctx.load_model(OT.load_model())
+    n, words = g.n, (g.m + 63) // 64
+    rb = torch.empty((len(ts), n), dtype=torch.int64, device=dev)
+    eb = torch.empty((len(ts), words), dtype=torch.int64, device=dev)
+    ctx.prune(first, count=len(ts), role_mask=rb, edge_bits=eb, batch_streams=4,
+              order="learned", learned_min_score=OT.load_threshold())
+    for i in (0, 1, len(ts) - 1):
+        t = ts[i]
+        log(f"config5 variant {i} edges={len(t.edges)}")
+        om = oracle.state(g.row_ptr, g.col, g.labels, t.labels, t.edges)
+        check_final(pmmod, g, t, om, pmmod.to_u64(rb[i]), pmmod.to_u64(eb[i]), n_keep=300,
+                    n_pruned=100, seed=200 + i)
+    ctx.close()

@@ -473,3 +473,55 @@ def test_distinct_count_rule_star_with_repeated_leaf_labels(k):
         assert int(st.role_mask[v]) == exp
     role, _, _ = run_brute(g, t)
     assert np.array_equal(st.role_mask, role)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_exact_sample_equals_bruteforce_on_sampled_vertices(seed):
+    """The sampled exact step (used for parity at sizes where the whole
+    exact step is too slow on the CPU) gives, for every sampled vertex, the
+    brute-force role mask and membership of each of its entries -- from the
+    label-only state and from the state after the constraint loop."""
+    g, t = random_case(seed)
+    role, ebits, _ = oracle.bruteforce(g.row_ptr, g.col, g.labels, t.labels, t.edges)
+    gg = oracle._G(g.row_ptr, g.col, g.labels)
+    tt = oracle._T(t.labels, t.edges)
+    rng = np.random.Generator(np.random.Philox(seed))
+    verts = np.sort(rng.choice(g.n, size=min(g.n, 12), replace=False))
+    for om in (oracle.init_roles(gg, tt),
+               oracle.state(g.row_ptr, g.col, g.labels, t.labels, t.edges)):
+        r, inc, off = oracle.exact_sample(gg, tt, om, verts)
+        assert np.array_equal(r, role[verts])
+        for i, v in enumerate(verts):
+            for j, e in enumerate(range(g.row_ptr[v], g.row_ptr[v + 1])):
+                want = (int(ebits[e >> 6]) >> (e & 63)) & 1
+                assert inc[off[i] + j] == want, (seed, v, e)
+
+
+def test_relaxations_are_the_connected_deletion_variants_up_to_isomorphism():
+    def nxt(t):
+        H = nx.Graph()
+        for q, lab in enumerate(t.labels):
+            H.add_node(q, label=lab)
+        H.add_edges_from(t.edges)
+        return H
+    nm = iso.categorical_node_match("label", None)
+    for labels in ([1, 2, 3, 4, 5, 6, 7, 4], [1, 1, 1, 1, 1, 1, 1, 1], [1, 2, 1, 2, 1, 2, 1, 2]):
+        base = I.Template(labels, I.CFG5_EDGES, "b")
+        rel = I.relaxations(base)
+        assert rel[0] is base
+        Hs = [nxt(t) for t in rel]
+        for i in range(len(Hs)):
+            assert nx.is_connected(Hs[i]) and Hs[i].number_of_nodes() == 8
+            assert 7 <= Hs[i].number_of_edges() <= 9
+            for j in range(i):
+                assert not nx.is_isomorphic(Hs[i], Hs[j], node_match=nm)
+        # every connected variant with one or two deletions is one of them
+        for d in (1, 2):
+            for dels in itertools.combinations(range(9), d):
+                es = [e for k, e in enumerate(I.CFG5_EDGES) if k not in dels]
+                H = nxt(I.Template(labels, es))
+                if not nx.is_connected(H):
+                    continue
+                assert any(nx.is_isomorphic(H, K, node_match=nm) for K in Hs)
+    # distinct labels but the repeated pair: 1 + 8 + 19 variants
+    assert len(I.relaxations(I.Template([1, 2, 3, 4, 5, 6, 7, 4], I.CFG5_EDGES))) == 28
