@@ -172,7 +172,10 @@ typedef struct {
     int64_t expand_scans;          /* swap scans (found match, template vertex) */
     int64_t expand_candidates;     /* role-list entries those scans read      */
     int64_t expand_valid;          /* swaps that gave another match           */
-    int64_t reserved[2];
+    int64_t first_sweep_bytes;     /* compulsory bytes of the first LCC sweep
+                                      when it runs from the neighbour-label
+                                      count index (else 0)                     */
+    int64_t reserved[1];
 } pm_stats;
 
 /* Returns the message for the last error on this thread ("" if none). */
@@ -196,7 +199,11 @@ int pm_destroy(pm_ctx *ctx);
    pm_unload_graph/pm_destroy -- unless PM_HOST_PTRS is set, in which case
    they are copied to device memory owned by the context.  PM_VALIDATE
    checks symmetry, ordering, loops and id range and returns PM_ERR_GRAPH on
-   a violation. */
+   a violation.  For uint8 labels whose largest value is below 64 the call
+   also builds a per-graph index, n * (largest label + 1) bytes of device
+   memory owned by the context: the number of neighbours of each label at
+   every vertex (saturated at 255), from which every prune evaluates its
+   first LCC sweep without reading the adjacency lists. */
 int pm_load_graph(pm_ctx *ctx, int64_t n, int64_t m, const int64_t *row_ptr,
                   const int32_t *col, const void *labels, int label_bytes, uint32_t flags);
 

@@ -116,6 +116,12 @@ struct pm_ctx {
     int label_bytes = 1;
     DevBuf own_rp, own_col, own_labels;
     std::vector<int64_t> label_freq;
+    // neighbour-label count index (uint8 labels below kCountLabels): count
+    // of neighbours of v with label L at lab_cnt[L * n + v]; nlab = 0: none
+    DevBuf lab_cnt;
+    int nlab = 0;
+    int64_t cnt_stride = 0;
+    double ms_count_index = 0.0;
     int64_t hub_cap = 0, seg_cap = 0;
     // templates
     std::vector<std::unique_ptr<CompiledTemplate>> templates;
@@ -600,7 +606,47 @@ struct Pruner {
         const int64_t n = c->n, m = c->m;
         zero_counters();
         launch_fill_u64(s, edge_out, (m + 63) / 64, 0ull);
-        {
+        const bool counted = c->nlab > 0 && T.n0 > 1;
+        if (counted) {
+            // first LCC sweep from the neighbour-label count index (it also
+            // initialises omega)
+            Timer t(s);
+            hipEvent_t a, b;
+            PM_HIP(hipEventCreate(&a));
+            PM_HIP(hipEventCreate(&b));
+            PM_HIP(hipEventRecord(a, s));
+            const int32_t *nd = T.d_need;
+            launch_first_sweep_counts<M>(s, n, c->cnt_stride, (const uint8_t *)c->labels, T.d_init_lut,
+                                         (int)std::min<int64_t>(T.init_lut_len, 256),
+                                         c->lab_cnt.as<uint8_t>(), c->nlab, nd, nd + T.n0 + 1,
+                                         nd + T.n0 + 1 + T.need_lab.size(), T.n0, om);
+            PM_HIP(hipEventRecord(b, s));
+            PM_HIP(hipEventSynchronize(b));
+            float ms = 0;
+            PM_HIP(hipEventElapsedTime(&ms, a, b));
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            st.ms_sweep_kernel += ms;
+            // compulsory bytes: every label, for each vertex the count bytes
+            // of the labels its initial roles need (a function of its
+            // label), and omega written
+            int64_t reads = 0;
+            for (size_t L = 0; L < c->label_freq.size() && L < 256; ++L) {
+                uint64_t used = 0;
+                for (int q = 0; q < T.n0; ++q)
+                    if (T.labels[(size_t)q] == (int)L) used |= T.need_labmask[(size_t)q];
+                const uint64_t in_index = c->nlab >= 64 ? ~0ull : ((1ull << c->nlab) - 1ull);
+                reads += c->label_freq[L] * (int64_t)__builtin_popcountll(used & in_index);
+            }
+            st.first_sweep_vertices = n;
+            st.first_sweep_entries = 0;
+            st.first_sweep_bytes = n + reads + (int64_t)sizeof(M) * n;
+            PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
+            collect(true);
+            st.ms_first_sweep = t.stop();
+            st.ms_lcc += st.ms_first_sweep;
+            st.lcc_sweeps++;
+        } else {
             Timer t(s);
             w->actbits.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>((n + 63) / 64, 1));
             wl.act_bits = w->actbits.as<uint64_t>();
@@ -611,7 +657,7 @@ struct Pruner {
             st.ms_init += t.stop();
         }
         Graph full{c->rp, c->col};
-        if (T.n0 > 1 && nA > 0) {
+        if (!counted && T.n0 > 1 && nA > 0) {
             // first sweep over the full graph
             Timer t(s);
             bin(full);
@@ -679,6 +725,11 @@ void load_template_device(pm_ctx *c, CompiledTemplate &T) {
     T.init_lut_len = (int64_t)lut.size();
     PM_HIP(hipMalloc(&T.d_init_lut, sizeof(uint64_t) * lut.size()));
     PM_HIP(hipMemcpy(T.d_init_lut, lut.data(), sizeof(uint64_t) * lut.size(), hipMemcpyHostToDevice));
+    std::vector<int32_t> need(T.need_off);
+    need.insert(need.end(), T.need_lab.begin(), T.need_lab.end());
+    need.insert(need.end(), T.need_min.begin(), T.need_min.end());
+    PM_HIP(hipMalloc(&T.d_need, sizeof(int32_t) * std::max<size_t>(need.size(), 1)));
+    PM_HIP(hipMemcpy(T.d_need, need.data(), sizeof(int32_t) * need.size(), hipMemcpyHostToDevice));
     std::vector<ConstraintDesc> cd;
     for (const Constraint &k : T.constraints)
         cd.push_back(ConstraintDesc{k.vmask, k.heads, (int32_t)k.edges.size(), k.kind});
@@ -693,7 +744,9 @@ void free_template_device(CompiledTemplate &T) {
     if (T.d_tedges) (void)hipFree(T.d_tedges);
     if (T.d_init_lut) (void)hipFree(T.d_init_lut);
     if (T.d_cdesc) (void)hipFree(T.d_cdesc);
+    if (T.d_need) (void)hipFree(T.d_need);
     T.d_cdesc = nullptr;
+    T.d_need = nullptr;
     T.d_plans = nullptr;
     T.d_tedges = nullptr;
     T.d_init_lut = nullptr;
@@ -775,7 +828,7 @@ int pm_destroy(pm_ctx *c) {
         if (!c) return;
         (void)hipSetDevice(c->device);
         for (auto &t : c->templates) free_template_device(*t);
-        for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels}) b->release();
+        for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->lab_cnt}) b->release();
         c->scratch.clear();
         for (DevBuf *b : {&c->model, &c->mlp_partial, &c->mlp_ploss, &c->mlp_grad, &c->mlp_m,
                           &c->mlp_v, &c->mlp_loss})
@@ -816,6 +869,8 @@ int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const
         c->own_rp.release();
         c->own_col.release();
         c->own_labels.release();
+        c->lab_cnt.release();
+        c->nlab = 0;
         if (host) {
             c->own_rp.ensure(sizeof(int64_t) * (size_t)(n + 1));
             c->own_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1));
@@ -857,6 +912,33 @@ int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const
         PM_HIP(hipStreamSynchronize(c->stream));
         hist.release();
         c->label_freq.assign(h.begin(), h.end());
+        // neighbour-label count index for the first LCC sweep
+        int maxl = -1;
+        for (int64_t L = 0; L < hl; ++L)
+            if (h[(size_t)L]) maxl = (int)L;
+        const char *noidx = getenv("PM_NO_COUNT_INDEX");
+        if (label_bytes == 1 && maxl >= 0 && maxl < kCountLabels && n > 0 &&
+            !(noidx && atoi(noidx))) {
+            const int nlab = maxl + 1;
+            const int64_t np = (n + 255) / 256 * 256;
+            c->lab_cnt.ensure((size_t)np * (size_t)nlab);
+            c->cnt_stride = np;
+            hipEvent_t a, b;
+            PM_HIP(hipEventCreate(&a));
+            PM_HIP(hipEventCreate(&b));
+            PM_HIP(hipEventRecord(a, c->stream));
+            launch_label_count(c->stream, n, np, c->rp, c->col, (const uint8_t *)c->labels, nlab,
+                               c->lab_cnt.as<uint8_t>());
+            PM_HIP(hipGetLastError());
+            PM_HIP(hipEventRecord(b, c->stream));
+            PM_HIP(hipEventSynchronize(b));
+            float ms = 0;
+            PM_HIP(hipEventElapsedTime(&ms, a, b));
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            c->ms_count_index = ms;
+            c->nlab = nlab;
+        }
         c->has_graph = true;
     });
 }
@@ -869,6 +951,8 @@ int pm_unload_graph(pm_ctx *c) {
         c->own_rp.release();
         c->own_col.release();
         c->own_labels.release();
+        c->lab_cnt.release();
+        c->nlab = 0;
         c->rp = nullptr;
         c->col = nullptr;
         c->labels = nullptr;
@@ -1027,6 +1111,7 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.expand_scans += st.expand_scans;
             total.expand_candidates += st.expand_candidates;
             total.expand_valid += st.expand_valid;
+            total.first_sweep_bytes += st.first_sweep_bytes;
             total.trace_entries += st.trace_entries;
         }
         PM_HIP(hipStreamSynchronize(c->stream));

@@ -133,36 +133,70 @@ void launch_init_roles(hipStream_t s, int64_t n, const void *labels, int label_b
 }
 
 // ---------------------------------------------------------------- binning
+// The sweep's change flag: set once (a read served by the cache first, so
+// that a sweep in which most wavefronts change something does not queue
+// thousands of atomics on one address).
+__device__ __forceinline__ void mark_changed(int32_t *changed) {
+    if (__atomic_load_n(changed, __ATOMIC_RELAXED) == 0) atomicExch(changed, 1);
+}
+
 __device__ __forceinline__ int degree_bin(int64_t d) {
     return d <= kBinSmallMaxDeg ? 0 : d <= kBinMidMaxDeg ? 1 : d <= kBinWaveMaxDeg ? 2 : 3;
 }
 
-// Append v to list b with one atomic per wavefront (ballot + prefix count).
-__device__ __forceinline__ void wave_append(bool pred, int32_t v, int32_t *list, int32_t *counter) {
-    uint64_t m = ballot64(pred);
+// Appends are staged in LDS: a block gathers the selected vertices of a
+// chunk of kStageChunk inputs per list with LDS atomics, then reserves space
+// in each global list with one atomic and copies the chunk out (one global
+// atomic per list per chunk instead of one per wavefront: on graphs with
+// tens of millions of vertices the per-wavefront counter atomics serialise).
+constexpr int kStageChunk = 2048;
+
+__device__ __forceinline__ void stage_append(bool pred, int32_t v, int32_t *buf, int32_t *cnt) {
+    const uint64_t m = ballot64(pred);
     if (!m) return;
-    int leader = __ffsll((unsigned long long)m) - 1;
+    const int leader = __ffsll((unsigned long long)m) - 1;
     int base = 0;
-    if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+    if (lane_id() == leader) base = atomicAdd(cnt, __popcll(m));
     base = __shfl(base, leader);
-    if (pred) list[base + __popcll(m & lanemask_lt())] = v;
+    if (pred) buf[base + __popcll(m & lanemask_lt())] = v;
 }
 
 template <typename M>
 __global__ __launch_bounds__(kBlock) void bin_kernel(const int32_t *in, int64_t n_in,
                                                      const int64_t *rp, const M *omega,
                                                      Worklists wl) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = i < n_in;
-    int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
-    bool act = valid && omega[v] != 0;
-    const int64_t d = act ? rp[v + 1] - rp[v] : 0;
-    int b = act ? degree_bin(d) : -1;
+    __shared__ int32_t buf[kNumBins][kStageChunk];
+    __shared__ int32_t cnt[kNumBins], base[kNumBins];
+    __shared__ unsigned long long ent;
+    for (int64_t c0 = (int64_t)blockIdx.x * kStageChunk; c0 < n_in;
+         c0 += (int64_t)gridDim.x * kStageChunk) {
+        if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) ent = 0;
+        __syncthreads();
+        unsigned long long tot = 0;
+        for (int r = 0; r < kStageChunk; r += kBlock) {
+            const int64_t i = c0 + r + threadIdx.x;
+            const bool valid = i < n_in;
+            const int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
+            const bool act = valid && omega[v] != 0;
+            const int64_t d = act ? rp[v + 1] - rp[v] : 0;
+            const int b = act ? degree_bin(d) : -1;
+            tot += (unsigned long long)d;
 #pragma unroll
-    for (int k = 0; k < kNumBins; ++k) wave_append(b == k, v, wl.list[k], wl.count + k);
-    unsigned long long tot = (unsigned long long)d;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
-    if (lane_id() == 0 && tot) atomicAdd(wl.entries, tot);
+            for (int k = 0; k < kNumBins; ++k) stage_append(b == k, v, buf[k], &cnt[k]);
+        }
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+        if (lane_id() == 0 && tot) atomicAdd(&ent, tot);
+        __syncthreads();
+        if (threadIdx.x < kNumBins)
+            base[threadIdx.x] =
+                cnt[threadIdx.x] ? atomicAdd(wl.count + threadIdx.x, cnt[threadIdx.x]) : 0;
+        if (threadIdx.x == 0 && ent) atomicAdd(wl.entries, ent);
+        __syncthreads();
+        for (int k = 0; k < kNumBins; ++k)
+            for (int j = threadIdx.x; j < cnt[k]; j += kBlock) wl.list[k][base[k] + j] = buf[k][j];
+        __syncthreads();
+    }
 }
 
 // Active list: the vertices of `in` (or 0..n-1) whose role set is not empty.
@@ -170,18 +204,186 @@ template <typename M>
 __global__ __launch_bounds__(kBlock) void collect_kernel(const int32_t *in, int64_t n_in,
                                                          const M *omega, int32_t *out,
                                                          int32_t *counter) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = i < n_in;
-    int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
-    wave_append(valid && omega[v] != 0, v, out, counter);
+    __shared__ int32_t buf[kStageChunk];
+    __shared__ int32_t cnt, base;
+    for (int64_t c0 = (int64_t)blockIdx.x * kStageChunk; c0 < n_in;
+         c0 += (int64_t)gridDim.x * kStageChunk) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        for (int r = 0; r < kStageChunk; r += kBlock) {
+            const int64_t i = c0 + r + threadIdx.x;
+            const bool valid = i < n_in;
+            const int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
+            stage_append(valid && omega[v] != 0, v, buf, &cnt);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) base = cnt ? atomicAdd(counter, cnt) : 0;
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += kBlock) out[base + j] = buf[j];
+        __syncthreads();
+    }
+}
+
+static unsigned stage_grid(int64_t n_in) {
+    int64_t g = (n_in + kStageChunk - 1) / kStageChunk;
+    return (unsigned)(g > 16384 ? 16384 : g);
+}
+
+// ---------------------------------------- first LCC sweep from label counts
+// Neighbour-label counts of the loaded graph (an index built once per
+// graph, for uint8 labels below kCountLabels): cnt[L * np + v] = number of
+// neighbours of v with label L, saturated at 255 (np = n rounded up to a
+// multiple of kBlock; the padding holds zeros).  A block takes tiles of
+// kBlock consecutive vertices; its wavefronts count one vertex at a time
+// with an LDS histogram, the saturated counts gather in an LDS tile, and
+// the block writes each label's counts for the tile as one contiguous run.
+__global__ __launch_bounds__(kBlock) void label_count_kernel(int64_t n, int64_t np,
+                                                             const int64_t *rp,
+                                                             const int32_t *col,
+                                                             const uint8_t *labels, int nlab,
+                                                             uint8_t *cnt) {
+    __shared__ unsigned int acc[kBlock / kWave][kWave];
+    __shared__ uint8_t tile[kCountLabels][kBlock];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < n; t0 += (int64_t)gridDim.x * kBlock) {
+        for (int j = wib; j < kBlock; j += kBlock / kWave) {
+            const int64_t v = t0 + j;
+            acc[wib][lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            if (v < n) {
+                const int64_t e1 = rp[v + 1];
+                for (int64_t e = rp[v] + lane; e < e1; e += kWave) {
+                    const int L = labels[col[e]];
+                    if (L < nlab) atomicAdd(&acc[wib][L], 1u);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nlab) {
+                const unsigned int c = acc[wib][lane];
+                tile[lane][j] = (uint8_t)(c > 255u ? 255u : c);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        for (int L = 0; L < nlab; ++L) cnt[(int64_t)L * np + t0 + threadIdx.x] = tile[L][threadIdx.x];
+        __syncthreads();
+    }
+}
+
+void launch_label_count(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
+                        const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt) {
+    if (n <= 0) return;
+    int64_t grid = (n + kBlock - 1) / kBlock;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL(label_count_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, n, np, rp,
+                       col, labels, nlab, cnt);
+}
+
+// The first LCC sweep evaluated from the initial role sets alone: with
+// omega0(u) = roles of u's label, a neighbour u covers template neighbour
+// q' of q iff label(u) = label(q'), and the distinct-count rule for label L
+// counts exactly the neighbours of label L.  So role q of v survives the
+// first sweep iff, for every label L, v has at least need_q(L) neighbours
+// of label L (need_q(L) = template neighbours of q with label L).  This is
+// the first Jacobi iteration of the LCC rule; later sweeps continue from
+// it to the same greatest fixpoint.  Each thread takes 4 consecutive
+// vertices: one 4-byte label load, one 4-byte load per needed label column
+// (all independent), and writes omega for every vertex (this also
+// initialises it).
+template <typename M>
+__global__ __launch_bounds__(kBlock) void first_sweep_counts_kernel(
+    int64_t n, int64_t np, const uint8_t *labels, const uint64_t *lut, int lut_len,
+    const uint8_t *cnt, int nlab, const int32_t *need_off, const int32_t *need_lab,
+    const int32_t *need_min, int n0, M *omega, bool aligned) {
+    __shared__ uint64_t s_lut[256];
+    __shared__ uint8_t s_need[kMaxK][kCountLabels];   // need_q(L), 0 if none
+    __shared__ uint64_t s_lmask[kMaxK];               // labels q needs
+    __shared__ int32_t s_drop[kMaxK];                 // q needs a label with no column
+    for (int i = threadIdx.x; i < lut_len; i += blockDim.x) s_lut[i] = lut[i];
+    for (int q = threadIdx.x; q < n0; q += blockDim.x) {
+        for (int L = 0; L < kCountLabels; ++L) s_need[q][L] = 0;
+        uint64_t lm = 0;
+        int drop = 0;
+        for (int i = need_off[q]; i < need_off[q + 1]; ++i) {
+            const int L = need_lab[i];
+            if (L < nlab) {
+                s_need[q][L] = (uint8_t)(need_min[i] > 255 ? 255 : need_min[i]);
+                lm |= 1ull << L;
+            } else {
+                drop = 1;
+            }
+        }
+        s_lmask[q] = lm;
+        s_drop[q] = drop;
+    }
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t v4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; v4 < n; v4 += stride) {
+        const bool full = aligned && v4 + 4 <= n;
+        uint32_t lab4;
+        if (full) {
+            lab4 = *reinterpret_cast<const uint32_t *>(labels + v4);
+        } else {
+            lab4 = 0;
+            for (int i = 0; i < 4 && v4 + i < n; ++i) lab4 |= (uint32_t)labels[v4 + i] << (8 * i);
+        }
+        uint64_t w[4];
+        uint64_t need = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int lab = (int)((lab4 >> (8 * i)) & 0xffu);
+            w[i] = (v4 + i < n && lab < lut_len) ? s_lut[lab] : 0ull;
+            for (uint64_t b = w[i]; b; b &= b - 1) {
+                const int q = __builtin_ctzll(b);
+                if (s_drop[q]) w[i] &= ~(1ull << q);
+                need |= s_lmask[q];
+            }
+        }
+        for (uint64_t lb = need; lb; lb &= lb - 1) {
+            const int L = __builtin_ctzll(lb);
+            const uint32_t c4 = *reinterpret_cast<const uint32_t *>(cnt + (int64_t)L * np + v4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t c = (c4 >> (8 * i)) & 0xffu;
+                for (uint64_t b = w[i]; b; b &= b - 1) {
+                    const int q = __builtin_ctzll(b);
+                    if (c < s_need[q][L]) w[i] &= ~(1ull << q);
+                }
+            }
+        }
+        if (full && sizeof(M) == 1) {
+            const uint32_t o = (uint32_t)w[0] | ((uint32_t)w[1] << 8) | ((uint32_t)w[2] << 16) |
+                               ((uint32_t)w[3] << 24);
+            *reinterpret_cast<uint32_t *>(omega + v4) = o;
+        } else {
+            for (int i = 0; i < 4; ++i)
+                if (v4 + i < n) omega[v4 + i] = (M)w[i];
+        }
+    }
+}
+
+template <typename M>
+void launch_first_sweep_counts(hipStream_t s, int64_t n, int64_t np, const uint8_t *labels,
+                               const uint64_t *lut, int lut_len, const uint8_t *cnt, int nlab,
+                               const int32_t *need_off, const int32_t *need_lab,
+                               const int32_t *need_min, int n0, M *omega) {
+    if (n <= 0) return;
+    int64_t grid = ((n + 3) / 4 + kBlock - 1) / kBlock;
+    if (grid > (1 << 20)) grid = 1 << 20;
+    // 4-byte label loads and omega stores need 4-byte aligned arrays (a
+    // borrowed label tensor may start anywhere)
+    const bool aligned = ((uintptr_t)labels % 4 == 0) && ((uintptr_t)omega % 4 == 0);
+    hipLaunchKernelGGL(first_sweep_counts_kernel<M>, dim3((unsigned)grid), dim3(kBlock), 0, s, n,
+                       np, labels, lut, lut_len, cnt, nlab, need_off, need_lab, need_min, n0,
+                       omega, aligned);
 }
 
 template <typename M>
 void launch_collect(hipStream_t s, const int32_t *in, int64_t n_in, const M *omega,
                     int32_t *out, int32_t *counter) {
     if (n_in <= 0) return;
-    int64_t grid = (n_in + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(collect_kernel<M>, dim3((unsigned)grid), dim3(kBlock), 0, s, in, n_in,
+    hipLaunchKernelGGL(collect_kernel<M>, dim3(stage_grid(n_in)), dim3(kBlock), 0, s, in, n_in,
                        omega, out, counter);
 }
 
@@ -189,8 +391,7 @@ template <typename M>
 void launch_bin(hipStream_t s, const int32_t *in, int64_t n_in, const int64_t *rp,
                 const M *omega, Worklists &wl) {
     if (n_in <= 0) return;
-    int64_t grid = (n_in + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(bin_kernel<M>, dim3((unsigned)grid), dim3(kBlock), 0, s, in, n_in, rp,
+    hipLaunchKernelGGL(bin_kernel<M>, dim3(stage_grid(n_in)), dim3(kBlock), 0, s, in, n_in, rp,
                        omega, wl);
 }
 
@@ -294,7 +495,7 @@ __device__ __forceinline__ void lcc_group_body(int64_t local_block, const int64_
             ch = true;
         }
     }
-    if (ballot64(ch) && lane == 0) atomicAdd(changed, 1);
+    if (ballot64(ch) && lane == 0) mark_changed(changed);
 }
 
 template <typename M, bool CNT, bool FILT>
@@ -349,7 +550,7 @@ __device__ __forceinline__ void lcc_hub_body(int64_t local_block, const int64_t 
             }
             if (nw != w) {
                 omega[v] = (M)nw;
-                atomicAdd(changed, 1);
+                mark_changed(changed);
             }
         }
     }
@@ -797,7 +998,10 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
                                          int32_t *, int32_t *);                                   \
     template void launch_widen<M>(hipStream_t, int64_t, const M *, uint64_t *);                  \
     template void launch_collect<M>(hipStream_t, const int32_t *, int64_t, const M *, int32_t *,  \
-                                    int32_t *);
+                                    int32_t *);                                                   \
+    template void launch_first_sweep_counts<M>(                                                   \
+        hipStream_t, int64_t, int64_t, const uint8_t *, const uint64_t *, int, const uint8_t *,   \
+        int, const int32_t *, const int32_t *, const int32_t *, int, M *);
 
 PM_INSTANTIATE_LCC(uint8_t)
 PM_INSTANTIATE_LCC(uint16_t)

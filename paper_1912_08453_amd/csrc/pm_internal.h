@@ -118,6 +118,11 @@ struct CompiledTemplate {
     uint64_t *d_init_lut = nullptr;           // label -> initial roles
     int64_t init_lut_len = 0;
     ConstraintDesc *d_cdesc = nullptr;        // [constraints]
+    // first-sweep needs: for role q, entries need_off[q] .. need_off[q+1] of
+    // (label L, number of template neighbours of q with label L)
+    std::vector<int32_t> need_off, need_lab, need_min;
+    std::vector<uint64_t> need_labmask;       // labels < 64 that q needs
+    int32_t *d_need = nullptr;                // need_off | need_lab | need_min
 };
 
 // Template compiler (host).  Returns an empty string on success, otherwise
@@ -286,6 +291,23 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
 
 template <typename M>
 void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst);
+
+// Neighbour-label count index of a graph with uint8 labels below nlab:
+// cnt[L * np + v] = min(255, neighbours of v with label L), np = n rounded
+// up to a multiple of 256 (labels and omega must allow 4-byte accesses at
+// multiples of 4: device allocations are aligned).
+constexpr int kCountLabels = 64;
+void launch_label_count(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
+                        const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt);
+
+// First LCC sweep from the count index: omega(v) = roles q of label(v) with
+// cnt[L][v] >= need for every (L, need) of q (need_off[q] .. need_off[q+1]
+// in need_lab / need_min).
+template <typename M>
+void launch_first_sweep_counts(hipStream_t s, int64_t n, int64_t np, const uint8_t *labels,
+                               const uint64_t *lut, int lut_len, const uint8_t *cnt, int nlab,
+                               const int32_t *need_off, const int32_t *need_lab,
+                               const int32_t *need_min, int n0, M *omega);
 
 // ---- learned order ----------------------------------------------------------
 // counts[q] += number of vertices of tasks whose role set holds q (counts

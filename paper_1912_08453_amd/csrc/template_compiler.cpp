@@ -257,10 +257,21 @@ std::string compile_template(int n0, int m0, const uint16_t *labels, const uint3
         L.adj[e.first] |= 1ull << e.second;
         L.adj[e.second] |= 1ull << e.first;
     }
+    T.need_off.assign(1, 0);
+    T.need_lab.clear();
+    T.need_min.clear();
+    T.need_labmask.assign((size_t)n0, 0);
     for (int q = 0; q < n0; ++q) {
         std::map<int, uint64_t> by_label;
         for (int r = 0; r < n0; ++r)
             if ((L.adj[q] >> r) & 1) by_label[T.labels[r]] |= 1ull << r;
+        // first-sweep needs of q: every neighbour label with its multiplicity
+        for (auto &kv : by_label) {
+            T.need_lab.push_back(kv.first);
+            T.need_min.push_back(__builtin_popcountll(kv.second));
+            if (kv.first < 64) T.need_labmask[(size_t)q] |= 1ull << kv.first;
+        }
+        T.need_off.push_back((int32_t)T.need_lab.size());
         for (auto &kv : by_label) {
             int need = __builtin_popcountll(kv.second);
             if (need < 2) continue;

@@ -84,8 +84,8 @@ class pm_stats(ctypes.Structure):
                 ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
                  "candidate_entries", "vertex_queries", "edge_queries", "result_vertices",
                  "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries", "expand_scans",
-                 "expand_candidates", "expand_valid")] + \
-               [("reserved", ctypes.c_int64 * 2)]
+                 "expand_candidates", "expand_valid", "first_sweep_bytes")] + \
+               [("reserved", ctypes.c_int64 * 1)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

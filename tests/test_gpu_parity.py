@@ -255,3 +255,29 @@ def test_concurrent_batch_equals_one_at_a_time(pmmod, torch_dev):
         ref = oracle.prune(g.row_ptr, g.col, g.labels, ts[i].labels, ts[i].edges)
         assert np.array_equal(r1[i], ref.role_mask) and np.array_equal(e1[i], ref.edge_bits)
     ctx.close()
+
+
+def test_count_index_unaligned_labels_and_gather_path_agree(pmmod, torch_dev, monkeypatch):
+    """The first sweep from the neighbour-label count index, with a label
+    array that starts at an odd address (scalar loads) and with the index
+    switched off (gather sweep over the CSR), against the oracle at every
+    intermediate state."""
+    torch, dev = torch_dev
+    rp, col = I.rmat_csr(13, seed=77)
+    g = I.Graph(rp, col, I.labels_log2deg(rp))
+    t = I.template_cfg2(g, 3)
+    big = torch.zeros(g.n + 1, dtype=torch.uint8, device=dev)
+    big[1:] = torch.from_numpy(g.labels).to(dev)
+    for mode in ("unaligned", "no_index"):
+        if mode == "no_index":
+            monkeypatch.setenv("PM_NO_COUNT_INDEX", "1")
+        ctx = pmmod.PM(0)
+        lab = big[1:] if mode == "unaligned" else big[1:].clone()
+        if mode == "unaligned":
+            assert lab.data_ptr() % 4 != 0
+        ctx.load_graph(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), lab)
+        tid = ctx.load_templates([t])
+        for k in range(len(C.non_local_constraints(t.labels, t.edges)) + 1):
+            compare(pmmod, ctx, tid, g, t, stop_after=k, what=f"{mode} after {k}")
+        compare(pmmod, ctx, tid, g, t, what=f"{mode} full")
+        ctx.close()
