@@ -175,6 +175,8 @@ typedef struct {
     int64_t first_sweep_bytes;     /* compulsory bytes of the first LCC sweep
                                       when it runs from the neighbour-label
                                       count index (else 0)                     */
+    int64_t witness_edges;         /* candidate edges certified by moving one
+                                      template vertex of a recorded match      */
     int64_t reserved[1];
 } pm_stats;
 

@@ -86,12 +86,12 @@ struct Scratch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
-    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
+    DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
         actbits, ord;
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
                           &ccol, &coff, &segcnt, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
-                          &ccert, &expseen, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord})
+                          &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
@@ -130,6 +130,9 @@ struct pm_ctx {
     int grid_search = 2048;
     int expand = 1;
     int64_t expand_max = INT64_MAX;
+    int witness = 1;
+    int edge_chunk = 16;
+    int relist = 1;
     int64_t wall_khz = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
@@ -352,10 +355,14 @@ struct Pruner {
         for (int i = 0; i < kMaxK; ++i) a.plan_of_head[i] = plan_of_head[i];
         a.edge_bits = edge_bits;
         a.task_counter = ctr + C_TASK;
+        a.task_chunk = 4;
         a.n_queries = queries;
         a.c_cert = nullptr;
         a.exp_seen = nullptr;
         a.exp_log2 = 0;
+        a.wit = nullptr;
+        a.wit_flag = nullptr;
+        a.wit_on = 0;
         a.qstats = nullptr;
         a.expand = 0;
         a.expand_max = c->expand_max;
@@ -421,6 +428,17 @@ struct Pruner {
         a.c_cert = c_cert;
         a.exp_seen = w->expseen.as<unsigned long long>();
         a.exp_log2 = kExpSeenLog2;
+        // witnesses of certified (vertex, role) pairs, for single-swap
+        // certification of candidate edges (small templates only)
+        const int64_t wit_words = nA * (int64_t)T.n0 * T.n0;
+        if (c->witness && T.n0 <= 16 && nA > 0 && wit_words <= (int64_t)1 << 29) {
+            w->wit.ensure(sizeof(int32_t) * (size_t)wit_words);
+            w->witflag.ensure(sizeof(uint32_t) * (size_t)(nA * T.n0));
+            launch_fill_i32(s, w->witflag.as<int32_t>(), nA * T.n0, 0);
+            a.wit = w->wit.as<int32_t>();
+            a.wit_flag = w->witflag.as<uint32_t>();
+            a.wit_on = 1;
+        }
         a.qstats = qstats;
         a.expand = c->expand;
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
@@ -437,7 +455,8 @@ struct Pruner {
         PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
         launch_edge_candidates<M>(s, A, nA, c_rp, c_col, sat, T.lcc, c_cert,
                                   w->eu.as<int32_t>(), w->ew.as<int32_t>(),
-                                  w->eidx.as<int64_t>(), ctr + C_NOUT, cap);
+                                  w->eidx.as<int64_t>(), ctr + C_NOUT, cap, a);
+        a.wit_on = 0;
         int64_t ne = read_ctr(C_NOUT);
         if (ne > cap) throw Error(PM_ERR_CAPACITY, "edge candidate capacity exceeded");
         st.edge_candidates = ne;
@@ -445,11 +464,26 @@ struct Pruner {
             w->edge_plan_ids.ensure(sizeof(int32_t) * std::max<size_t>(T.edge_plans.size(), 1));
             PM_HIP(hipMemcpyAsync(w->edge_plan_ids.p, T.edge_plans.data(),
                                   sizeof(int32_t) * T.edge_plans.size(), hipMemcpyHostToDevice, s));
+            if (c->relist) {
+                // role lists over the certified role sets (the exact roles):
+                // the edge searches then scan only vertices that can take
+                // part in a match
+                std::swap(om, sat);
+                role_lists();
+                std::swap(om, sat);
+                a.rl_off = w->rloff.as<int64_t>();
+                a.rl_col = w->rlcol.as<int32_t>();
+                a.rl_ent = w->rlent.as<int32_t>();
+                a.rl_pos = w->rlpos.as<int32_t>();
+                a.check_om = 0;
+            } else {
+                // the edge searches read the certified role sets, a subset
+                // of those the role lists were built from
+                a.check_om = 1;
+            }
             PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
             PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
-            // the edge searches read the certified role sets, a subset of
-            // those the role lists were built from
-            a.check_om = 1;
+            a.task_chunk = c->edge_chunk;
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
                                   w->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
@@ -476,6 +510,7 @@ struct Pruner {
         st.expand_scans += (int64_t)qs[11];
         st.expand_candidates += (int64_t)qs[12];
         st.expand_valid += (int64_t)qs[13];
+        st.witness_edges += (int64_t)qs[14];
         st.ms_exact += t.stop();
     }
 
@@ -815,6 +850,12 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             if (ex) c->expand = atoi(ex);
             const char *em = getenv("PM_EXPAND_MAX");
             if (em) c->expand_max = atoll(em);
+            const char *wn = getenv("PM_WITNESS");
+            if (wn) c->witness = atoi(wn);
+            const char *rl = getenv("PM_RELIST");
+            if (rl) c->relist = atoi(rl);
+            const char *ec = getenv("PM_EDGE_CHUNK");
+            if (ec) c->edge_chunk = std::max(1, atoi(ec));
         } catch (...) {
             delete c;
             throw;
@@ -1112,6 +1153,7 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.expand_candidates += st.expand_candidates;
             total.expand_valid += st.expand_valid;
             total.first_sweep_bytes += st.first_sweep_bytes;
+            total.witness_edges += st.witness_edges;
             total.trace_entries += st.trace_entries;
         }
         PM_HIP(hipStreamSynchronize(c->stream));

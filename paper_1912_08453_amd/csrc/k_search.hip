@@ -35,7 +35,6 @@
 namespace pm {
 
 constexpr int kSearchBlock = 256;
-constexpr int kTaskChunk = 4;
 
 __device__ __forceinline__ bool test_bit(const uint64_t *bits, int64_t k) {
     return (bits[k >> 6] >> (k & 63)) & 1ull;
@@ -326,12 +325,29 @@ __device__ __forceinline__ void certify_pair(const SearchArgs &a, int32_t u, int
     if (p >= 0) set_entry(a, p);
 }
 
+// Record the match (images img_r, with x in place of template vertex q
+// when q >= 0) as the witness of (lane's vertex, lane's role) for every
+// lane with `claim` whose (vertex, role) has none yet.
+__device__ void record_witness(const SearchArgs &a, uint64_t vmask, int32_t img_r, bool claim,
+                               int32_t v, int role, int q, int32_t x) {
+    if (claim) {
+        const int64_t idx = (int64_t)a.rl_pos[v] * a.n0 + role;
+        claim = atomicCAS(a.wit_flag + idx, 0u, 1u) == 0u;
+    }
+    for (uint64_t m = vmask; m; m &= m - 1) {
+        const int p = __builtin_ctzll(m);
+        const int32_t y = p == q ? x : read_lane32(img_r, p);
+        if (claim) a.wit[((int64_t)a.rl_pos[v] * a.n0 + role) * a.n0 + p] = y;
+    }
+}
+
 // Certify a full match: every role and every template edge.
 template <typename M>
 __device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict__ P,
                               int32_t img_r, M *cert) {
     const int lane = lane_id();
     if ((P->vmask >> lane) & 1ull) atomic_or_elem<M>(cert, img_r, 1ull << lane);
+    if (a.wit_on) record_witness(a, P->vmask, img_r, (P->vmask >> lane) & 1ull, img_r, lane, -1, 0);
     for (int base = 0; base < a.m0; base += kWave) {
         const int i = base + lane;
         int ta = 0, tb = 0;
@@ -458,6 +474,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
                 ok = wave_find(rlc, y0, y1, x, ok) >= 0;
             }
             ec.valid += (unsigned long long)__popcll(ballot64(ok));
+            if (a.wit_on) record_witness(a, P->vmask, img_r, ok, x, q, q, x);
             if (ok) {
                 atomic_or_elem<M>(cert, x, 1ull << q);
                 // the scanned entry ys -> x is at kk of ys's list
@@ -500,10 +517,10 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
     ExpandCount ec;
     for (;;) {
         int t0 = 0;
-        if (lane == 0) t0 = atomicAdd(a.task_counter, kTaskChunk);
+        if (lane == 0) t0 = atomicAdd(a.task_counter, a.task_chunk);
         t0 = __shfl(t0, 0);
         if ((int64_t)t0 >= n_tasks) break;
-        const int64_t t1 = (int64_t)t0 + kTaskChunk < n_tasks ? (int64_t)t0 + kTaskChunk : n_tasks;
+        const int64_t t1 = (int64_t)t0 + a.task_chunk < n_tasks ? (int64_t)t0 + a.task_chunk : n_tasks;
         for (int64_t t = t0; t < t1; ++t) {
             const int32_t v = tasks[t];
             uint64_t cand = (uint64_t)om[v] & a.heads & ~load_fresh(sat + v);
@@ -592,15 +609,52 @@ void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega
 }
 
 // ------------------------------------------------ exact step: edge part
+// Does the witness of (v, qv) stay a match when template vertex qx moves to
+// x?  x holds role qx and is adjacent to v; it must differ from the other
+// images and be adjacent to the images of qx's other template neighbours.
+__device__ bool try_swap(const SearchArgs &a, const LccTable &tab, int32_t v, int qv, int32_t x,
+                         int qx) {
+    const int64_t idx = (int64_t)a.rl_pos[v] * a.n0 + qv;
+    if (!__atomic_load_n(a.wit_flag + idx, __ATOMIC_RELAXED)) return false;
+    const int32_t *W = a.wit + idx * a.n0;
+    if (W[qx] == x) return true;
+    for (int p = 0; p < a.n0; ++p)
+        if (p != qx && W[p] == x) return false;
+    for (uint64_t m = tab.adj[qx] & ~(1ull << qv); m; m &= m - 1) {
+        const int p = __builtin_ctzll(m);
+        const int32_t y = W[p];
+        if (find_sorted(a.rl_col, rl_begin(a, y, qx), rl_end(a, y, qx), x) < 0) return false;
+    }
+    return true;
+}
+
+// Some match uses edge {u, w}: a recorded witness of u or w becomes one by
+// moving a single template vertex onto the other end.
+__device__ bool witness_swap(const SearchArgs &a, const LccTable &tab, uint64_t cu, uint64_t cw,
+                             int32_t u, int32_t w) {
+    for (int i = 0; i < a.m0; ++i) {
+        const int ta = a.tedges[2 * i], tb = a.tedges[2 * i + 1];
+        for (int o = 0; o < 2; ++o) {
+            const int qa = o ? tb : ta, qb = o ? ta : tb;
+            if (!((cu >> qa) & 1ull) || !((cw >> qb) & 1ull)) continue;
+            if (try_swap(a, tab, u, qa, w, qb)) return true;
+            if (try_swap(a, tab, w, qb, u, qa)) return true;
+        }
+    }
+    return false;
+}
+
 // Candidate edges: entries a -> b (a < b) of the compacted subgraph whose
 // certified roles are adjacent in G0 and that no found match certified yet
-// (a certified edge has the bit of exactly this entry set).
+// (a certified edge has the bit of exactly this entry set); those a witness
+// swap certifies are certified here instead.
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
     const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
-    const M *cert, LccTable tab, const uint64_t *c_cert, int32_t *eu, int32_t *ew,
-    int64_t *e_idx, int32_t *n_out, int64_t cap) {
+    const M *cert, LccTable tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
+    int64_t *e_idx, int32_t *n_out, int64_t cap, SearchArgs a) {
     const int lane = lane_id();
+    unsigned long long swapped = 0;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     for (int64_t t = wave; t < n_tasks; t += nwaves) {
@@ -615,7 +669,13 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
             int32_t w = 0;
             if (k < e) {
                 w = c_col[k];
-                p = w > u && ((uint64_t)cert[w] & reach) != 0ull && !test_bit(c_cert, k);
+                const uint64_t cw = (uint64_t)cert[w];
+                p = w > u && (cw & reach) != 0ull && !test_bit(c_cert, k);
+                if (p && a.wit_on && witness_swap(a, tab, cu, cw, u, w)) {
+                    set_bit(c_cert, k);
+                    ++swapped;
+                    p = false;
+                }
             }
             const uint64_t m = ballot64(p);
             if (!m) continue;
@@ -632,18 +692,21 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
             }
         }
     }
+    for (int off = 32; off > 0; off >>= 1) swapped += __shfl_xor(swapped, off, 64);
+    if (lane == 0 && swapped && a.qstats) atomicAdd(a.qstats + 14, swapped);
 }
 
 template <typename M>
 void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                             const int64_t *c_rp, const int32_t *c_col, const M *cert,
-                            const LccTable &tab, const uint64_t *c_cert, int32_t *eu, int32_t *ew,
-                            int64_t *e_idx, int32_t *n_out, int64_t cap) {
+                            const LccTable &tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
+                            int64_t *e_idx, int32_t *n_out, int64_t cap, const SearchArgs &a) {
     if (n_tasks <= 0) return;
     int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(edge_candidates_kernel<M>, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       tasks, n_tasks, c_rp, c_col, cert, tab, c_cert, eu, ew, e_idx, n_out, cap);
+                       tasks, n_tasks, c_rp, c_col, cert, tab, c_cert, eu, ew, e_idx, n_out, cap,
+                       a);
 }
 
 template <typename M>
@@ -655,10 +718,10 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
     ExpandCount ec;
     for (;;) {
         int t0 = 0;
-        if (lane == 0) t0 = atomicAdd(a.task_counter, kTaskChunk);
+        if (lane == 0) t0 = atomicAdd(a.task_counter, a.task_chunk);
         t0 = __shfl(t0, 0);
         if ((int64_t)t0 >= n_edges) break;
-        const int64_t t1 = (int64_t)t0 + kTaskChunk < n_edges ? (int64_t)t0 + kTaskChunk : n_edges;
+        const int64_t t1 = (int64_t)t0 + a.task_chunk < n_edges ? (int64_t)t0 + a.task_chunk : n_edges;
         for (int64_t t = t0; t < t1; ++t) {
             const int32_t u = eu[t], w = ew[t];
             const int64_t k = e_idx[t];
@@ -789,8 +852,8 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                                   int32_t *);                                                     \
     template void launch_edge_candidates<M>(hipStream_t, const int32_t *, int64_t,                \
                                             const int64_t *, const int32_t *, const M *,          \
-                                            const LccTable &, const uint64_t *, int32_t *,        \
-                                            int32_t *, int64_t *, int32_t *, int64_t);            \
+                                            const LccTable &, uint64_t *, int32_t *, int32_t *,   \
+                                            int64_t *, int32_t *, int64_t, const SearchArgs &);   \
     template void launch_edge_search<M>(hipStream_t, const int32_t *, const int32_t *,            \
                                         const int64_t *, int64_t, const M *, M *,                 \
                                         const int32_t *, int32_t, const SearchArgs &, int);       \

@@ -221,6 +221,7 @@ struct SearchArgs {
     int32_t plan_of_head[kMaxK];
     uint64_t *edge_bits;
     int32_t *task_counter;
+    int32_t task_chunk;             // consecutive tasks a wavefront takes per atomic
     unsigned long long *n_queries;
     // exact step: certified edges of the compacted subgraph (bit k = entry k
     // = u -> w with u < w), the table of swap scans
@@ -233,6 +234,12 @@ struct SearchArgs {
                                     // eneg_t, vcert_t, ecert_t, expand_t (wall-clock
                                     // ticks), expand scans, candidates, valid swaps
     int32_t expand;                 // run the single-vertex swap expansion
+    // witnesses (exact step): for each certified (vertex, role) the first
+    // match that certified it, wit[(pos * n0 + q) * n0 + p] = image of p,
+    // valid once wit_flag[pos * n0 + q] is set; recorded while wit_on
+    int32_t *wit;
+    uint32_t *wit_flag;
+    int32_t wit_on;
     int64_t expand_max;             // longest list a swap scan reads
     int32_t check_om;               // candidates' role sets may have shrunk since
                                     // the role lists were built: test them
@@ -269,11 +276,13 @@ void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega
 
 // Exact step, edge part: candidate edges u < w of the compacted subgraph
 // with adjacent certified roles and no certified bit yet.
+// Candidates whose edge a recorded witness certifies by one vertex swap are
+// certified here instead of being listed (a.wit_on).
 template <typename M>
 void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                             const int64_t *c_rp, const int32_t *c_col, const M *cert,
-                            const LccTable &tab, const uint64_t *c_cert, int32_t *eu, int32_t *ew,
-                            int64_t *e_idx, int32_t *n_out, int64_t cap);
+                            const LccTable &tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
+                            int64_t *e_idx, int32_t *n_out, int64_t cap, const SearchArgs &a);
 
 template <typename M>
 void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,

@@ -84,7 +84,7 @@ class pm_stats(ctypes.Structure):
                 ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
                  "candidate_entries", "vertex_queries", "edge_queries", "result_vertices",
                  "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries", "expand_scans",
-                 "expand_candidates", "expand_valid", "first_sweep_bytes")] + \
+                 "expand_candidates", "expand_valid", "first_sweep_bytes", "witness_edges")] + \
                [("reserved", ctypes.c_int64 * 1)]
 
     def as_dict(self):
@@ -94,11 +94,14 @@ class pm_stats(ctypes.Structure):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libpm.so; raises if it is missing (no CPU fallback exists)."""
+def load_library(path: str = None):
+    """Load libpm.so (or the build named by PM_LIBRARY); raises if it is
+    missing (no CPU fallback exists)."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("PM_LIBRARY", LIB_PATH)
     if not os.path.exists(path):
         raise RuntimeError(f"libpm.so not built at {path}; run __graft_entry__.build()")
     # torch ships its own HIP runtime; loading it first makes libpm bind to
