@@ -281,3 +281,22 @@ def test_count_index_unaligned_labels_and_gather_path_agree(pmmod, torch_dev, mo
             compare(pmmod, ctx, tid, g, t, stop_after=k, what=f"{mode} after {k}")
         compare(pmmod, ctx, tid, g, t, what=f"{mode} full")
         ctx.close()
+
+
+@pytest.mark.parametrize("env", [{"PM_RELIST": "0"}, {"PM_WITNESS": "0"}, {"PM_EXPAND": "0"},
+                                 {"PM_EXPAND_MAX": "32"}, {"PM_EDGE_CHUNK": "1"}])
+def test_exact_step_switches_give_the_same_result(pmmod, torch_dev, monkeypatch, env):
+    """The exact step's optional savings (role lists rebuilt from the exact
+    roles, witness swaps, swap scans, their length cap, task chunking) only
+    change how much work is done: the complete set equals the oracle's with
+    each one switched off or changed."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    rp, col = I.rmat_csr(14, seed=91)
+    g = I.Graph(rp, col, I.labels_log2deg(rp))
+    ts = [I.template_cfg2(g, 5)] + I.templates_multicycle(g, 77, count=2)
+    ctx = load(pmmod, torch_dev, g)
+    for t in ts:
+        tid = ctx.load_templates([t])
+        compare(pmmod, ctx, tid, g, t, what=f"{env} {t.labels}")
+    ctx.close()
