@@ -45,8 +45,8 @@ def main():
                          "one call per template vs concurrent streams), learned (64 multi-cycle "
                          "templates, fixed vs learned constraint order); '' for none")
     ap.add_argument("--batch-streams", type=int, default=4)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg5"],
-                    help="cfg2: one template at scale 22 (default); cfg5: scale-26 base template "
+    ap.add_argument("--workload", default="tri-square-s22", choices=["tri-square-s22", "theta8-s26"],
+                    help="tri-square-s22: one template at scale 22 (default); theta8-s26: scale-26 base template "
                          "and its 1-2 edge-deletion relaxations, one call per variant vs one "
                          "batched call with the learned order")
     args = ap.parse_args()
@@ -74,14 +74,14 @@ def main():
                           "launches": 3}))
         return
 
-    if args.workload == "cfg5":
+    if args.workload == "theta8-s26":
         return exploratory(args)
 
     t0 = time.time()
     rp, col = I.rmat_csr(args.scale, seed=args.graph_seed)
     labels = I.labels_log2deg(rp)
     g = I.Graph(rp, col, labels)
-    tmpl = I.template_cfg2(g, args.template_seed)
+    tmpl = I.template_tri_square(g, args.template_seed)
     n, m = g.n, g.m
     log(f"graph scale {args.scale}: n={n} m={m} (directed entries), built in "
         f"{time.time() - t0:.1f}s; template labels {tmpl.labels}")
@@ -137,9 +137,13 @@ def main():
         kname = "lcc_sweep_kernel (first LCC sweep over the CSR)"
     k_ms = avg("ms_sweep_kernel")
     achieved = alg_bytes / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
+    traffic = None
+    if stats[-1]["first_sweep_bytes"] > 0:
+        traffic = recorded_traffic("first_sweep_counts_kernel", args.scale, args.graph_seed,
+                                   args.template_seed)
     roofline = {"bound": "hbm", "kernel": kname,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": int(alg_bytes), "ms_per_launch": round(k_ms, 5)}
 
     phases = {k: round(avg(k), 4) for k in stats[-1] if k.startswith("ms_")}
@@ -198,6 +202,33 @@ def main():
     ctx.close()
 
 
+def recorded_traffic(kernel, scale, graph_seed, template_seed):
+    """HBM bytes per launch of `kernel` from the counter record under
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
+    None when there is no record for this workload or the kernel's source has
+    changed since the counters were taken."""
+    import hashlib
+    if graph_seed != 22:
+        return None
+    path = os.path.join(ROOT, "profiles",
+                        f"first_sweep_counts_tri_square_scale{scale}_seed{template_seed}.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            rec[k] = v
+    if rec.get("kernel") != kernel:
+        return None
+    src = os.path.join(ROOT, rec.get("source", ""))
+    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != rec.get("source_sha1"):
+        return None
+    return int(float(rec["fetch_kib_per_dispatch"]) * 1024 * float(rec["fetch_scale"]) +
+               float(rec["write_kib_per_dispatch"]) * 1024 * float(rec["write_scale"]))
+
+
 def exploratory(args, scale=26, graph_seed=26, template_seed=0):
     """Scale-26 exploratory workload: the 8-vertex two-cycle base template
     (repeated-label pair 4 hops apart) and its connected 1- and 2-edge
@@ -214,7 +245,7 @@ def exploratory(args, scale=26, graph_seed=26, template_seed=0):
     rp, col = I.rmat_csr(scale, seed=graph_seed)
     labels = I.labels_log2deg(rp)
     g = I.Graph(rp, col, labels)
-    base = I.template_cfg5(g, template_seed)
+    base = I.template_theta8(g, template_seed)
     ts = I.relaxations(base)
     log(f"graph scale {scale}: n={g.n} m={g.m} built in {time.time() - t0:.1f}s; "
         f"{len(ts)} variants of {base.labels}")

@@ -189,7 +189,7 @@ class Template:
         return adj
 
 
-def template_cfg1() -> Template:
+def template_square_pendant() -> Template:
     """4-cycle q0(0)-q1(1)-q2(2)-q3(3)-q0 plus a pendant q4(4) on q0."""
     return Template([0, 1, 2, 3, 4], [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4)], "sq+pendant")
 
@@ -238,15 +238,15 @@ def _degrees(n0: int, edges) -> List[int]:
     return d
 
 
-CFG2_EDGES = [(0, 1), (1, 2), (0, 2), (1, 3), (3, 4), (4, 0), (3, 5)]
+TRI_SQUARE_EDGES = [(0, 1), (1, 2), (0, 2), (1, 3), (3, 4), (4, 0), (3, 5)]
 
 
-def template_cfg2(graph: "Graph", seed: int) -> Template:
+def template_tri_square(graph: "Graph", seed: int) -> Template:
     """Triangle (q0,q1,q2) and 4-cycle (q0,q1,q3,q4) sharing edge q0-q1, a
     pendant q5 on q3, and the repeated label l(q5) = l(q2); the labels are
     those of an occurrence of this shape found from a seeded random start
     vertex, so the template has at least one match."""
-    return extract_template(graph, 6, CFG2_EDGES, seed, repeat_pairs=[(2, 5)],
+    return extract_template(graph, 6, TRI_SQUARE_EDGES, seed, repeat_pairs=[(2, 5)],
                             name=f"tri+sq+pendant/s{seed}")
 
 
@@ -548,14 +548,14 @@ def model_params(seed: int, n_params: int = 5122, fan_ins=((768, 12), (64, 0), (
 # 2) with a pendant q7 on q6, and one repeated label on q3 and q7, which are
 # 4 hops apart (q7-q6-q0-q4-q3), so the constraint list holds a path
 # constraint of length 4.
-CFG5_EDGES = [(0, 1), (1, 2), (2, 3), (3, 4), (0, 4), (1, 5), (5, 6), (0, 6), (6, 7)]
-CFG5_REPEAT = (3, 7)
+THETA8_EDGES = [(0, 1), (1, 2), (2, 3), (3, 4), (0, 4), (1, 5), (5, 6), (0, 6), (6, 7)]
+THETA8_REPEAT = (3, 7)
 
 
-def template_cfg5(graph: "Graph", seed: int) -> Template:
+def template_theta8(graph: "Graph", seed: int) -> Template:
     """The 8-vertex two-cycle base template with labels from an occurrence
     in the graph (so it has at least one match)."""
-    return extract_template(graph, 8, CFG5_EDGES, seed, repeat_pairs=[CFG5_REPEAT],
+    return extract_template(graph, 8, THETA8_EDGES, seed, repeat_pairs=[THETA8_REPEAT],
                             name=f"theta8+pendant/s{seed}")
 
 

@@ -31,7 +31,7 @@ META_PATH = os.path.join(HERE, "order_model.json")
 
 # template seeds: training draws never overlap the evaluation workload
 # (multi-cycle templates of seed 4)
-TRAIN_CFG2_SEEDS = tuple(range(1000, 1024))
+TRAIN_TRI_SQUARE_SEEDS = tuple(range(1000, 1024))
 TRAIN_MULTICYCLE_SEED = 9
 TRAIN_MULTICYCLE_COUNT = 24
 THRESHOLDS = (None, -6.0, -4.0, -2.0, 0.0)
@@ -51,14 +51,14 @@ def load_threshold(path: str = META_PATH):
         return json.load(f).get("min_score")
 
 
-def training_templates(graph, cfg2_seeds: Sequence[int] = TRAIN_CFG2_SEEDS,
+def training_templates(graph, tri_square_seeds: Sequence[int] = TRAIN_TRI_SQUARE_SEEDS,
                        mc_seed: int = TRAIN_MULTICYCLE_SEED,
                        mc_count: int = TRAIN_MULTICYCLE_COUNT):
     from . import inputs as I
     ts = []
-    for s in cfg2_seeds:
+    for s in tri_square_seeds:
         try:
-            ts.append(I.template_cfg2(graph, s))
+            ts.append(I.template_tri_square(graph, s))
         except RuntimeError:
             pass
     ts += I.templates_multicycle(graph, mc_seed, count=mc_count)
@@ -156,7 +156,8 @@ def main(argv=None):
     np.save(os.path.join(args.out, "order_model.npy"), w, allow_pickle=False)
     meta = {
         "graph": f"R-MAT scale {args.scale} seed {args.graph_seed}, log2-degree labels",
-        "templates": f"cfg2-shape seeds {TRAIN_CFG2_SEEDS[0]}..{TRAIN_CFG2_SEEDS[-1]} and "
+        "templates": f"triangle+square+pendant seeds {TRAIN_TRI_SQUARE_SEEDS[0]}.."
+                     f"{TRAIN_TRI_SQUARE_SEEDS[-1]} and "
                      f"{TRAIN_MULTICYCLE_COUNT} multi-cycle templates of seed "
                      f"{TRAIN_MULTICYCLE_SEED}",
         "orders_per_template": args.orders, "samples": int(X.shape[0]),

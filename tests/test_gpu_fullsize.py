@@ -121,18 +121,18 @@ def check_final(pmmod, g, t, om, r, e, n_keep=1200, n_pruned=300, seed=0):
         f"{int((r != 0).sum())} result vertices, {on.size} result entries")
 
 
-def test_config2_full_size(pmmod, ctx22, g22):
+def test_tri_square_scale22_full_size(pmmod, ctx22, g22):
     """R-MAT scale 22, log2-degree labels, triangle+square+pendant template
     with a repeated label (template seed 0): the benchmark's workload."""
-    t = I.template_cfg2(g22, 0)
+    t = I.template_tri_square(g22, 0)
     tid = ctx22.load_templates([t])
-    log(f"config2 scale22 t={t.labels}")
+    log(f"triangle+square+pendant scale22 t={t.labels}")
     om = check_intermediate(pmmod, ctx22, tid, g22, t)
     role, edge, _ = ctx22.prune(tid)
     check_final(pmmod, g22, t, om, pmmod.to_u64(role[0]), pmmod.to_u64(edge[0]))
 
 
-def test_config3_batch_full_size(pmmod, ctx22, g22, torch_dev):
+def test_mixed_batch_64_scale22_full_size(pmmod, ctx22, g22, torch_dev):
     """64 mixed templates in one call on 4 concurrent streams (the
     benchmark's batched leg): every template's output equals its own
     one-template call, and seeded templates are checked against the oracle."""
@@ -147,7 +147,7 @@ def test_config3_batch_full_size(pmmod, ctx22, g22, torch_dev):
     pick = sorted(int(x) for x in rng.choice(64, size=4, replace=False))
     for i in pick:
         t = ts[i]
-        log(f"config3 template {i} n0={t.n0} labels={t.labels}")
+        log(f"mixed batch template {i} n0={t.n0} labels={t.labels}")
         role, edge, _ = ctx22.prune(first + i)
         assert torch.equal(role[0], rb[i]) and torch.equal(edge[0], eb[i])
         om = check_intermediate(pmmod, ctx22, first + i, g22, t)
@@ -155,7 +155,7 @@ def test_config3_batch_full_size(pmmod, ctx22, g22, torch_dev):
                     n_pruned=50, seed=i)
 
 
-def test_config4_learned_order_full_size(pmmod, ctx22, g22):
+def test_multicycle_learned_order_scale22_full_size(pmmod, ctx22, g22):
     """Multi-cycle templates of the learned-order workload with the shipped
     model and threshold: output identical to the fixed order over all
     vertices and edges, and checked against the oracle on samples."""
@@ -166,7 +166,7 @@ def test_config4_learned_order_full_size(pmmod, ctx22, g22):
     for i in (0, 42):
         t = ts[i]
         tid = ctx22.load_templates([t])
-        log(f"config4 template {i} labels={t.labels}")
+        log(f"multi-cycle template {i} labels={t.labels}")
         rf, ef, _ = ctx22.prune(tid)
         rf, ef = rf.clone(), ef.clone()
         rl, el, st = ctx22.prune(tid, order="learned", learned_min_score=thr)
@@ -178,7 +178,7 @@ def test_config4_learned_order_full_size(pmmod, ctx22, g22):
 
 @pytest.mark.skipif(os.environ.get("PM_TEST_SCALE26") != "1",
                     reason="scale-26 workload: set PM_TEST_SCALE26=1 (about two minutes)")
-def test_config5_scale26_relaxation_batch(pmmod, torch_dev):
+def test_theta8_relaxations_scale26(pmmod, torch_dev):
     """R-MAT scale 26 (2.1 billion entries), the 8-vertex two-cycle base
     template with a repeated-label pair 4 hops apart and its connected
     1- and 2-edge-deletion relaxations, pruned as one batch on concurrent
@@ -187,9 +187,9 @@ def test_config5_scale26_relaxation_batch(pmmod, torch_dev):
     from paper_1912_08453_amd import order_training as OT
     torch, dev = torch_dev
     g = _graph(26, 26)
-    base = I.template_cfg5(g, 0)
+    base = I.template_theta8(g, 0)
     ts = I.relaxations(base)
-    log(f"config5 scale26 m={g.m} variants={len(ts)} base={base.labels}")
+    log(f"theta8 scale26 m={g.m} variants={len(ts)} base={base.labels}")
     ctx = pmmod.PM(0)
     ctx.load_graph(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
                    torch.from_numpy(g.labels).to(dev))
@@ -204,7 +204,7 @@ def test_config5_scale26_relaxation_batch(pmmod, torch_dev):
     # oracle's constraint loop on the larger ones runs for minutes)
     for i in (0, 3, 20):
         t = ts[i]
-        log(f"config5 variant {i} edges={len(t.edges)}")
+        log(f"theta8 variant {i} edges={len(t.edges)}")
         t0 = time.time()
         om = oracle.state(g.row_ptr, g.col, g.labels, t.labels, t.edges)
         log(f"  oracle state {time.time() - t0:.1f}s, {int((om != 0).sum())} vertices")

@@ -146,7 +146,7 @@ def _load(pmmod, torch_dev, g):
 def test_learned_order_needs_a_model(pmmod, torch_dev):
     g = _graph14(0)
     ctx = _load(pmmod, torch_dev, g)
-    tid = ctx.load_templates([I.template_cfg2(g, 0)])
+    tid = ctx.load_templates([I.template_tri_square(g, 0)])
     with pytest.raises(pmmod.PMError) as e:
         ctx.prune(tid, order="learned")
     assert e.value.code == -9
@@ -154,7 +154,7 @@ def test_learned_order_needs_a_model(pmmod, torch_dev):
 
 
 def _templates(g, seed):
-    ts = [I.template_cfg2(g, seed)]
+    ts = [I.template_tri_square(g, seed)]
     ts += I.templates_multicycle(g, 500 + seed, count=3)
     return ts
 

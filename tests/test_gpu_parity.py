@@ -93,19 +93,19 @@ def test_random_small_full_and_every_intermediate_state(pmmod, torch_dev, seed):
     ctx.close()
 
 
-def test_config1_scale12_uniform_labels(pmmod, torch_dev):
+def test_square_pendant_scale12_uniform_labels(pmmod, torch_dev):
     """R-MAT scale 12, 8 uniform labels, square plus pendant: final masks
     against the oracle and against brute-force enumeration; every
     intermediate state against the oracle."""
     rp, col = I.rmat_csr(12, seed=1)
     g = I.Graph(rp, col, I.labels_uniform(rp.shape[0] - 1, 8, 12))
-    t = I.template_cfg1()
-    log(f"config1 n={g.n} m={g.m}")
+    t = I.template_square_pendant()
+    log(f"square+pendant n={g.n} m={g.m}")
     ctx = load(pmmod, torch_dev, g)
     tid = ctx.load_templates([t])
     for k in range(len(C.non_local_constraints(t.labels, t.edges)) + 1):
-        compare(pmmod, ctx, tid, g, t, stop_after=k, what=f"cfg1 after {k}")
-    st, ref = compare(pmmod, ctx, tid, g, t, what="cfg1 full")
+        compare(pmmod, ctx, tid, g, t, stop_after=k, what=f"square+pendant after {k}")
+    st, ref = compare(pmmod, ctx, tid, g, t, what="square+pendant full")
     role, ebits, cnt = oracle.bruteforce(g.row_ptr, g.col, g.labels, t.labels, t.edges)
     assert np.array_equal(role, ref.role_mask) and np.array_equal(ebits, ref.edge_bits)
     assert cnt > 0 and (role != 0).sum() > 0
@@ -113,13 +113,13 @@ def test_config1_scale12_uniform_labels(pmmod, torch_dev):
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_rmat_scale16_degree_labels_cfg2_shape(pmmod, torch_dev, seed):
+def test_rmat_scale16_degree_labels_tri_square(pmmod, torch_dev, seed):
     """Triangle + square + pendant with a repeated label on an R-MAT scale-16
     graph with log2-degree labels (several tiles, hubs split over
     wavefronts)."""
     rp, col = I.rmat_csr(16, seed=100 + seed)
     g = I.Graph(rp, col, I.labels_log2deg(rp))
-    t = I.template_cfg2(g, seed)
+    t = I.template_tri_square(g, seed)
     log(f"scale16 seed={seed} labels={t.labels} m={g.m}")
     ctx = load(pmmod, torch_dev, g)
     tid = ctx.load_templates([t])
@@ -211,7 +211,7 @@ def test_edge_cases(pmmod, torch_dev):
 def test_repeated_calls_are_identical(pmmod, torch_dev):
     rp, col = I.rmat_csr(14, seed=11)
     g = I.Graph(rp, col, I.labels_log2deg(rp))
-    t = I.template_cfg2(g, 4)
+    t = I.template_tri_square(g, 4)
     ctx = load(pmmod, torch_dev, g)
     tid = ctx.load_templates([t])
     outs = [tuple(pmmod.to_u64(x[0]).tobytes() for x in ctx.prune(tid)[:2]) for _ in range(3)]
@@ -265,7 +265,7 @@ def test_count_index_unaligned_labels_and_gather_path_agree(pmmod, torch_dev, mo
     torch, dev = torch_dev
     rp, col = I.rmat_csr(13, seed=77)
     g = I.Graph(rp, col, I.labels_log2deg(rp))
-    t = I.template_cfg2(g, 3)
+    t = I.template_tri_square(g, 3)
     big = torch.zeros(g.n + 1, dtype=torch.uint8, device=dev)
     big[1:] = torch.from_numpy(g.labels).to(dev)
     for mode in ("unaligned", "no_index"):
@@ -294,7 +294,7 @@ def test_exact_step_switches_give_the_same_result(pmmod, torch_dev, monkeypatch,
         monkeypatch.setenv(k, v)
     rp, col = I.rmat_csr(14, seed=91)
     g = I.Graph(rp, col, I.labels_log2deg(rp))
-    ts = [I.template_cfg2(g, 5)] + I.templates_multicycle(g, 77, count=2)
+    ts = [I.template_tri_square(g, 5)] + I.templates_multicycle(g, 77, count=2)
     ctx = load(pmmod, torch_dev, g)
     for t in ts:
         tid = ctx.load_templates([t])

@@ -72,7 +72,7 @@ def test_constraint_lists_match_oracle(lib, seed):
 
 
 def test_constraint_list_named_shapes(lib):
-    for t in [I.template_cfg1(), I.Template([10, 11, 12, 13, 14, 12], I.CFG2_EDGES),
+    for t in [I.template_square_pendant(), I.Template([10, 11, 12, 13, 14, 12], I.TRI_SQUARE_EDGES),
               I.Template([0] * 4, [(a, b) for a in range(4) for b in range(a + 1, 4)]),
               I.Template([0, 1, 2, 0, 1, 2, 3], [(i, i + 1) for i in range(6)]),
               I.Template([0] * 6, [(i, (i + 1) % 6) for i in range(6)]),

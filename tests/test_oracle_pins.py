@@ -111,11 +111,11 @@ def test_prune_equals_bruteforce(seed):
     assert np.array_equal(r.edge_bits, ebits)
 
 
-def test_prune_equals_bruteforce_config1_shape():
+def test_prune_equals_bruteforce_square_pendant():
     """Square plus pendant on a scale-10 R-MAT graph with 8 uniform labels."""
     rp, col = I.rmat_csr(10, seed=7)
     g = I.Graph(rp, col, I.labels_uniform(rp.shape[0] - 1, 8, 99))
-    t = I.template_cfg1()
+    t = I.template_square_pendant()
     r = run_prune(g, t)
     role, ebits, cnt = run_brute(g, t)
     assert np.array_equal(r.role_mask, role)
@@ -398,7 +398,7 @@ def test_constraints_triangle_square_pendant_by_hand():
     outer 5-cycle), one path constraint q2-q1-q3-q5 between the repeated
     labels (3 hops, not inside one cycle), and one TDS union of the cycles."""
     labels = [10, 11, 12, 13, 14, 12]
-    K0 = C.non_local_constraints(labels, I.CFG2_EDGES)
+    K0 = C.non_local_constraints(labels, I.TRI_SQUARE_EDGES)
     kinds = [(c.kind, len(c.edges)) for c in K0]
     assert kinds == [(C.CC, 3), (C.PC, 3), (C.CC, 4), (C.CC, 5), (C.TDS_CC, 6)]
     assert K0[1].edges == ((1, 2), (1, 3), (3, 5)) and K0[1].heads == (1 << 2) | (1 << 5)
@@ -506,7 +506,7 @@ def test_relaxations_are_the_connected_deletion_variants_up_to_isomorphism():
         return H
     nm = iso.categorical_node_match("label", None)
     for labels in ([1, 2, 3, 4, 5, 6, 7, 4], [1, 1, 1, 1, 1, 1, 1, 1], [1, 2, 1, 2, 1, 2, 1, 2]):
-        base = I.Template(labels, I.CFG5_EDGES, "b")
+        base = I.Template(labels, I.THETA8_EDGES, "b")
         rel = I.relaxations(base)
         assert rel[0] is base
         Hs = [nxt(t) for t in rel]
@@ -518,10 +518,10 @@ def test_relaxations_are_the_connected_deletion_variants_up_to_isomorphism():
         # every connected variant with one or two deletions is one of them
         for d in (1, 2):
             for dels in itertools.combinations(range(9), d):
-                es = [e for k, e in enumerate(I.CFG5_EDGES) if k not in dels]
+                es = [e for k, e in enumerate(I.THETA8_EDGES) if k not in dels]
                 H = nxt(I.Template(labels, es))
                 if not nx.is_connected(H):
                     continue
                 assert any(nx.is_isomorphic(H, K, node_match=nm) for K in Hs)
     # distinct labels but the repeated pair: 1 + 8 + 19 variants
-    assert len(I.relaxations(I.Template([1, 2, 3, 4, 5, 6, 7, 4], I.CFG5_EDGES))) == 28
+    assert len(I.relaxations(I.Template([1, 2, 3, 4, 5, 6, 7, 4], I.THETA8_EDGES))) == 28
