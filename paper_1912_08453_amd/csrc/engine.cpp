@@ -387,6 +387,9 @@ struct Pruner {
                               w->rlscan.as<int64_t>(), sl);
         rl_total = 0;
         d2h(s, &rl_total, w->rloff.as<int64_t>() + nA * T.n0, 1);
+        // the searches keep role-list positions and row bases in 32 bits
+        if (rl_total > (int64_t)INT32_MAX - 64 || nA * (int64_t)T.n0 > (int64_t)INT32_MAX - 64)
+            throw Error(PM_ERR_CAPACITY, "role lists exceed 2^31 entries");
         w->rlcol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
         w->rlent.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
         launch_role_fill<M>(s, A, nA, c_rp, c_col, om, T.n0, w->rloff.as<int64_t>(),

@@ -196,54 +196,67 @@ __device__ __forceinline__ int64_t rl_end(const SearchArgs &a, int32_t y, int q)
 
 // Depth-first search for an embedding of plan P's substructure with the
 // pinned template vertices at v0 (and v1).  Lane-distributed state: lane q
-// holds the image of template vertex q; lane l holds the scan state of
-// search level l (the template vertex it places, the placed neighbour whose
-// role list it scans, the list cursor and the ballot of surviving
-// candidates of the current 64-entry chunk).  At each new level the
-// unplaced vertex with the shortest candidate list is placed next (the
-// paper's constraint optimisation visits rare labels first; here the choice
-// is made per partial match from exact list lengths).  Returns true with
-// img_r holding a full embedding.
+// holds the image of template vertex q and the start of that image's row of
+// role-list offsets (rb_r); lane l holds the scan state of search level l
+// (the template vertex it places, the placed neighbour whose role list it
+// scans, the list cursor and the ballot of surviving candidates of the
+// current 64-entry chunk).  At each new level the unplaced vertex with the
+// shortest candidate list is placed next (the paper's constraint
+// optimisation visits rare labels first; here the choice is made per
+// partial match from exact list lengths): every open template vertex's lane
+// reads its list lengths under the placed neighbours in parallel and a
+// wavefront minimum picks the shortest (ties: lowest vertex, then lowest
+// neighbour).  Returns true with img_r (and rb_r) holding a full embedding.
 template <typename M>
 __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
-                           const M *__restrict__ om, int32_t v0, int32_t v1, int32_t &img_r) {
+                           const M *__restrict__ om, int32_t v0, int32_t v1, int32_t &img_r,
+                           int32_t &rb_r) {
     const int lane = lane_id();
     const int k = P->k;
     const int npin = P->npin;
     const uint64_t vmask = P->vmask;
     const int p0 = P->pin[0], p1 = P->pin[1];
     img_r = lane == p0 ? v0 : ((npin == 2 && lane == p1) ? v1 : -1);
+    rb_r = img_r >= 0 ? a.rl_pos[img_r] * a.n0 : 0;
     uint64_t placed = (1ull << p0) | (npin == 2 ? (1ull << p1) : 0ull);
     if (k <= npin) return true;
     const int32_t *__restrict__ rlc = a.rl_col;
-    int64_t cur_r = 0, end_r = 0, base_r = 0;
+    const int64_t *__restrict__ rlo = a.rl_off;
+    // role-list positions fit in 32 bits (checked when the lists are built)
+    int32_t cur_r = 0, end_r = 0, base_r = 0;
     uint64_t pend_r = 0;
     int32_t pv_r = 0, par_r = 0;
 
     auto select = [&](int l) {
-        int bp = -1, bj = -1;
-        int64_t bs = INT64_MAX, bb = 0, be = 0;
-        for (uint64_t mp = vmask & ~placed; mp; mp &= mp - 1) {
-            const int p = __builtin_ctzll(mp);
-            for (uint64_t mj = P->adj[p] & placed; mj; mj &= mj - 1) {
-                const int j = __builtin_ctzll(mj);
-                const int32_t y = read_lane32(img_r, j);
-                const int64_t b = rl_begin(a, y, p), e = rl_end(a, y, p);
-                if (e - b < bs) {
-                    bs = e - b;
-                    bp = p;
-                    bj = j;
-                    bb = b;
-                    be = e;
-                }
+        const uint64_t nbr = ((vmask & ~placed) >> lane) & 1ull ? (P->adj[lane] & placed) : 0ull;
+        uint64_t key = ~0ull;
+        for (uint64_t mj = placed; mj; mj &= mj - 1) {
+            const int j = __builtin_ctzll(mj);
+            const int32_t rbj = read_lane32(rb_r, j);
+            if ((nbr >> j) & 1ull) {
+                const int64_t len = rlo[rbj + lane + 1] - rlo[rbj + lane];
+                const uint64_t kv = ((uint64_t)len << 12) | ((uint64_t)lane << 6) | (uint64_t)j;
+                if (kv < key) key = kv;
             }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = shfl_xor_u64(key, off, kWave);
+            if (o < key) key = o;
+        }
+        int bp = 0, bj = 0;
+        int32_t bb = 0, be = 0;
+        if (key != ~0ull) {
+            bp = (int)((key >> 6) & 63ull);
+            bj = (int)(key & 63ull);
+            bb = (int32_t)rlo[read_lane32(rb_r, bj) + bp];
+            be = bb + (int32_t)(key >> 12);
         }
         if (lane == l) {
             cur_r = bb;
             end_r = be;
             pend_r = 0;
-            pv_r = bp < 0 ? 0 : bp;
-            par_r = bj < 0 ? 0 : bj;
+            pv_r = bp;
+            par_r = bj;
         }
     };
     int lvl = npin;
@@ -251,8 +264,8 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
     for (;;) {
         uint64_t pend = read_lane_u64(pend_r, lvl);
         if (pend == 0) {
-            const int64_t cur = read_lane64(cur_r, lvl);
-            const int64_t end = read_lane64(end_r, lvl);
+            const int32_t cur = read_lane32(cur_r, lvl);
+            const int32_t end = read_lane32(end_r, lvl);
             if (cur >= end) {
                 if (--lvl < npin) return false;
                 placed &= ~(1ull << read_lane32(pv_r, lvl));
@@ -262,7 +275,7 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
             const int par = read_lane32(par_r, lvl);
             const uint64_t same = P->samelab[q] & placed;
             const uint64_t back = P->adj[q] & placed & ~(1ull << par);
-            const int64_t kk = cur + lane;
+            const int32_t kk = cur + lane;
             const bool in_range = kk < end;
             const int32_t x = in_range ? rlc[kk] : -1;
             bool ok = in_range && (!a.check_om || (((uint64_t)om[x] >> q) & 1ull));
@@ -272,9 +285,8 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
             }
             for (uint64_t m = back; m; m &= m - 1) {
                 if (!ballot64(ok)) break;
-                const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
-                const int64_t ys = rl_begin(a, y, q), ye = rl_end(a, y, q);
-                ok = wave_find(rlc, ys, ye, x, ok) >= 0;
+                const int32_t rbj = read_lane32(rb_r, __builtin_ctzll(m));
+                ok = wave_find(rlc, rlo[rbj + q], rlo[rbj + q + 1], x, ok) >= 0;
             }
             const uint64_t b = ballot64(ok);
             if (lane == lvl) {
@@ -286,11 +298,14 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
         }
         const int j = __builtin_ctzll(pend);
         pend &= pend - 1;
-        const int64_t base = read_lane64(base_r, lvl);
+        const int32_t base = read_lane32(base_r, lvl);
         const int32_t x = rlc[base + j];
         const int q = read_lane32(pv_r, lvl);
         if (lane == lvl) pend_r = pend;
-        if (lane == q) img_r = x;
+        if (lane == q) {
+            img_r = x;
+            rb_r = a.rl_pos[x] * a.n0;
+        }
         placed |= 1ull << q;
         if (lvl == k - 1) return true;
         ++lvl;
@@ -383,7 +398,8 @@ struct ExpandCount {
 
 template <typename M>
 __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__ P,
-                             int32_t img_r, const M *__restrict__ om, M *cert, ExpandCount &ec) {
+                             int32_t img_r, int32_t rb_r, const M *__restrict__ om, M *cert,
+                             ExpandCount &ec) {
     const int lane = lane_id();
     const int32_t *__restrict__ rlc = a.rl_col;
     for (uint64_t mq = P->vmask; mq; mq &= mq - 1) {
@@ -392,10 +408,10 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
         if (!nb) continue;
         // lane j (a template neighbour of q) holds the bounds of the q-list
         // of its image
-        int64_t lb_r = 0, le_r = 0;
+        int32_t lb_r = 0, le_r = 0;
         if ((nb >> lane) & 1ull) {
-            lb_r = rl_begin(a, img_r, q);
-            le_r = rl_end(a, img_r, q);
+            lb_r = (int32_t)a.rl_off[rb_r + q];
+            le_r = (int32_t)a.rl_off[rb_r + q + 1];
         }
         // scan the shortest list; test the others shortest first (the most
         // selective), at most kOrd of them in that order, the rest by index
@@ -404,13 +420,13 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
         int64_t bd = INT64_MAX;
         for (uint64_t m = nb; m; m &= m - 1) {
             const int j = __builtin_ctzll(m);
-            const int64_t len = read_lane64(le_r, j) - read_lane64(lb_r, j);
+            const int64_t len = read_lane32(le_r, j) - read_lane32(lb_r, j);
             if (len < bd) {
                 bd = len;
                 js = j;
             }
         }
-        const int64_t s = read_lane64(lb_r, js), e = read_lane64(le_r, js);
+        const int32_t s = read_lane32(lb_r, js), e = read_lane32(le_r, js);
         if (e - s > a.expand_max) continue;
         const int32_t ys = read_lane32(img_r, js);
         {
@@ -432,7 +448,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             int64_t bl = INT64_MAX;
             for (uint64_t m = rest; m; m &= m - 1) {
                 const int j = __builtin_ctzll(m);
-                const int64_t len = read_lane64(le_r, j) - read_lane64(lb_r, j);
+                const int64_t len = read_lane32(le_r, j) - read_lane32(lb_r, j);
                 if (len < bl) {
                     bl = len;
                     bj = j;
@@ -445,8 +461,8 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
         const uint64_t same = P->samelab[q];
         ++ec.scans;
         ec.cands += (unsigned long long)(e - s);
-        for (int64_t base = s; base < e; base += kWave) {
-            const int64_t kk = base + lane;
+        for (int32_t base = s; base < e; base += kWave) {
+            const int32_t kk = base + lane;
             const bool in = kk < e;
             const int32_t x = in ? rlc[kk] : -1;
             bool ok = in && (!a.check_om || (((uint64_t)om[x] >> q) & 1ull));
@@ -456,12 +472,12 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             }
             // adjacency to the other neighbours' images; positions kept for
             // the first three (certification of entries y -> x, y < x)
-            int64_t p0 = -1, p1 = -1, p2 = -1;
+            int32_t p0 = -1, p1 = -1, p2 = -1;
             for (int i = 0; i < nord; ++i) {
                 if (!ballot64(ok)) break;
                 const int j = (int)((ordc >> (6 * i)) & 63ull);
-                const int64_t y0 = read_lane64(lb_r, j), y1 = read_lane64(le_r, j);
-                const int64_t p = wave_find(rlc, y0, y1, x, ok);
+                const int32_t y0 = read_lane32(lb_r, j), y1 = read_lane32(le_r, j);
+                const int32_t p = (int32_t)wave_find(rlc, y0, y1, x, ok);
                 ok = p >= 0;
                 if (i == 0) p0 = p;
                 else if (i == 1) p1 = p;
@@ -470,7 +486,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             for (uint64_t m = rest; m; m &= m - 1) {
                 if (!ballot64(ok)) break;
                 const int j = __builtin_ctzll(m);
-                const int64_t y0 = read_lane64(lb_r, j), y1 = read_lane64(le_r, j);
+                const int32_t y0 = read_lane32(lb_r, j), y1 = read_lane32(le_r, j);
                 ok = wave_find(rlc, y0, y1, x, ok) >= 0;
             }
             ec.valid += (unsigned long long)__popcll(ballot64(ok));
@@ -486,7 +502,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
                     if (y < x) {
                         int64_t p = i == 0 ? p0 : (i == 1 ? p1 : (i == 2 ? p2 : -1));
                         if (p < 0)
-                            p = find_sorted(rlc, read_lane64(lb_r, j), read_lane64(le_r, j), x);
+                            p = find_sorted(rlc, read_lane32(lb_r, j), read_lane32(le_r, j), x);
                         if (p >= 0) set_entry(a, p);
                     } else {
                         certify_pair(a, x, q, y, j);
@@ -497,7 +513,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
                     const int32_t y = read_lane32(img_r, j);
                     if (y < x) {
                         const int64_t p =
-                            find_sorted(rlc, read_lane64(lb_r, j), read_lane64(le_r, j), x);
+                            find_sorted(rlc, read_lane32(lb_r, j), read_lane32(le_r, j), x);
                         if (p >= 0) set_entry(a, p);
                     } else {
                         certify_pair(a, x, q, y, j);
@@ -530,9 +546,10 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                 if ((load_fresh(sat + v) >> h) & 1ull) continue;
                 const SearchPlan *P = a.plans + a.plan_of_head[h];
                 int32_t img = 0;
+                int32_t rb = 0;
                 ++queries;
                 const uint64_t c0 = wall_clock64();
-                const bool found = dfs_search<M>(a, P, om, v, -1, img);
+                const bool found = dfs_search<M>(a, P, om, v, -1, img, rb);
                 const uint64_t c1 = wall_clock64();
                 if (found) {
                     ++npos;
@@ -541,7 +558,7 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                         certify_match<M>(a, P, img, sat);
                         if (a.expand) {
                             const uint64_t c2 = wall_clock64();
-                            expand_match<M>(a, P, img, om, sat, ec);
+                            expand_match<M>(a, P, img, rb, om, sat, ec);
                             texp += wall_clock64() - c2;
                         }
                     } else {
@@ -731,9 +748,10 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
                 const SearchPlan *P = a.plans + edge_plan[i];
                 if (!((cu >> P->pin[0]) & 1ull) || !((cw >> P->pin[1]) & 1ull)) continue;
                 int32_t img = 0;
+                int32_t rb = 0;
                 ++queries;
                 const uint64_t c0 = wall_clock64();
-                const bool found = dfs_search<M>(a, P, om, u, w, img);
+                const bool found = dfs_search<M>(a, P, om, u, w, img, rb);
                 const uint64_t c1 = wall_clock64();
                 if (found) {
                     ++npos;
@@ -741,7 +759,7 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
                     certify_match<M>(a, P, img, cert);
                     if (a.expand) {
                         const uint64_t c2 = wall_clock64();
-                        expand_match<M>(a, P, img, om, cert, ec);
+                        expand_match<M>(a, P, img, rb, om, cert, ec);
                         texp += wall_clock64() - c2;
                     }
                     tcert += wall_clock64() - c1;
