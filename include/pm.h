@@ -31,8 +31,9 @@
  *  - Environment variables read by pm_create (work-saving switches of the
  *    final search; none changes any result): PM_EXPAND=0 turns off the
  *    single-vertex swap scans of found matches, PM_EXPAND_MAX=k skips scans
- *    of lists longer than k, PM_WITNESS=0 turns off certifying candidate
- *    edges by swaps of recorded witnesses, PM_RELIST=0 keeps the edge
+ *    of lists longer than k, PM_WITNESS=1 turns on certifying candidate
+ *    edges by swaps of recorded witnesses (off by default: measured slower
+ *    once the edge searches use relisted roles), PM_RELIST=0 keeps the edge
  *    searches on the pre-search role lists, PM_EDGE_CHUNK=k sets the edge
  *    tasks a wavefront takes at once (default 16).  Read by pm_load_graph:
  *    PM_NO_COUNT_INDEX=1 skips the neighbour-label count index (the first

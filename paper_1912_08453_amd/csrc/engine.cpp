@@ -130,7 +130,7 @@ struct pm_ctx {
     int grid_search = 2048;
     int expand = 1;
     int64_t expand_max = INT64_MAX;
-    int witness = 1;
+    int witness = 0;
     int edge_chunk = 16;
     int relist = 1;
     int64_t wall_khz = 0;
