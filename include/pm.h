@@ -31,7 +31,7 @@
  *  - Environment variables read by pm_create (work-saving switches of the
  *    final search; none changes any result): PM_EXPAND=0 turns off the
  *    single-vertex swap scans of found matches, PM_EXPAND_MAX=k skips scans
- *    of lists longer than k, PM_WITNESS=1 turns on certifying candidate
+ *    of lists longer than k (default 4096), PM_WITNESS=1 turns on certifying candidate
  *    edges by swaps of recorded witnesses (off by default: measured slower
  *    once the edge searches use relisted roles), PM_RELIST=0 keeps the edge
  *    searches on the pre-search role lists, PM_EDGE_CHUNK=k sets the edge

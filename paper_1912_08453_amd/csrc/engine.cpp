@@ -129,7 +129,7 @@ struct pm_ctx {
     std::vector<std::unique_ptr<pm::Scratch>> scratch;
     int grid_search = 2048;
     int expand = 1;
-    int64_t expand_max = INT64_MAX;
+    int64_t expand_max = 4096;
     int witness = 0;
     int edge_chunk = 16;
     int relist = 1;
