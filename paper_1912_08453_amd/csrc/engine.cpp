@@ -85,12 +85,13 @@ struct Timer {
 struct Scratch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, scan_scratch;
+    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, segscan,
+        segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
         actbits, ord;
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
-                          &ccol, &coff, &segcnt, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
+                          &ccol, &coff, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
                           &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -205,6 +206,8 @@ struct Pruner {
         size_t hub_bytes = (size_t)segs * (4 + 8 + 8 + 4) + (size_t)hubs * (4 + 4 + 8 + 4 * kMaxCount + 4);
         w->hub.ensure(hub_bytes + 256);
         w->segcnt.ensure(sizeof(int64_t) * (size_t)segs);
+        w->segscan.ensure(sizeof(int64_t) * (size_t)(segs + 1));
+        w->segbits.ensure(sizeof(uint64_t) * (size_t)segs * (kHubSegment / kWave));
         om = w->omega.as<M>();
         sat = w->sat.as<M>();
         A = w->alist[0].as<int32_t>();
@@ -316,11 +319,14 @@ struct Pruner {
         int64_t *deg = w->cdeg.as<int64_t>();
         PM_HIP(hipMemsetAsync(deg, 0, sizeof(int64_t) * (size_t)(n + 1), s));
         launch_compact_count<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, deg,
-                                w->segcnt.as<int64_t>());
-        int64_t sl = scan_scratch_len(n);
+                                w->segcnt.as<int64_t>(), w->segbits.as<uint64_t>());
+        int64_t sl = scan_scratch_len(std::max<int64_t>(n, nseg));
         w->scan_scratch.ensure(sizeof(int64_t) * (size_t)sl);
         c_rp = w->crp.as<int64_t>();
         launch_exclusive_scan(s, deg, c_rp, n, w->scan_scratch.as<int64_t>(), sl);
+        if (nseg > 0)
+            launch_exclusive_scan(s, w->segcnt.as<int64_t>(), w->segscan.as<int64_t>(), nseg,
+                                  w->scan_scratch.as<int64_t>(), sl);
         d2h(s, &c_m, c_rp + n, 1);
         if (c_m > (int64_t)INT32_MAX)
             throw Error(PM_ERR_CAPACITY, "candidate subgraph has more than 2^31 - 1 entries");
@@ -329,7 +335,7 @@ struct Pruner {
         c_col = w->ccol.as<int32_t>();
         c_off = w->coff.as<int32_t>();
         launch_compact_fill<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, c_rp,
-                               w->segcnt.as<int64_t>(), c_col, c_off);
+                               w->segscan.as<int64_t>(), w->segbits.as<uint64_t>(), c_col, c_off);
         st.candidate_entries = c_m;
         st.ms_compact += t.stop();
     }

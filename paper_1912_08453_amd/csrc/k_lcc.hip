@@ -660,36 +660,51 @@ __global__ __launch_bounds__(kBlock) void compact_count_group(const int64_t *__r
     if (valid && sl == 0) deg_out[v] = c;
 }
 
+// Hub segments (kHubSegment entries, one wavefront each): the count pass
+// stores the keep ballot of every 64-entry chunk (seg_bits, 64 words per
+// segment), so the fill pass reads the columns of kept entries only and
+// gathers no role sets.
 template <typename M>
 __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col,
                                                             const M *__restrict__ omega,
                                                             Worklists wl, int64_t n_seg,
                                                             LccTable tab, int64_t *deg_out,
-                                                            int64_t *seg_count) {
+                                                            int64_t *seg_count,
+                                                            uint64_t *seg_bits) {
     const int lane = lane_id();
     const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (seg >= n_seg) return;
     const int32_t v = wl.hub_seg_v[seg];
     const uint64_t reach = reach_of<M>((uint64_t)omega[v], tab);
-    int c = 0;
+    int64_t c = 0;
     if (reach) {
-        const int64_t e = wl.hub_seg_end[seg];
-        int64_t k = wl.hub_seg_begin[seg] + lane;
-        for (; k + (int64_t)(kUnroll - 1) * kWave < e; k += (int64_t)kUnroll * kWave) {
+        const int64_t b = wl.hub_seg_begin[seg], e = wl.hub_seg_end[seg];
+        uint64_t *bits = seg_bits + seg * (kHubSegment / kWave);
+        int chunk = 0;
+        int64_t k0 = b;
+        for (; k0 + (int64_t)kUnroll * kWave <= e; k0 += (int64_t)kUnroll * kWave) {
             int32_t cc[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) cc[u] = col[k + (int64_t)u * kWave];
+            for (int u = 0; u < kUnroll; ++u) cc[u] = col[k0 + (int64_t)u * kWave + lane];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) c += ((uint64_t)omega[cc[u]] & reach) != 0ull;
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t m = ballot64(((uint64_t)omega[cc[u]] & reach) != 0ull);
+                if (lane == 0) bits[chunk + u] = m;
+                c += __popcll(m);
+            }
+            chunk += kUnroll;
         }
-        for (; k < e; k += kWave) c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+        for (; k0 < e; k0 += kWave, ++chunk) {
+            const int64_t k = k0 + lane;
+            const uint64_t m = ballot64(k < e && ((uint64_t)omega[col[k]] & reach) != 0ull);
+            if (lane == 0) bits[chunk] = m;
+            c += __popcll(m);
+        }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
     if (lane == 0) {
         seg_count[seg] = c;
-        atomicAdd((unsigned long long *)&deg_out[v], (unsigned long long)c);
+        if (c) atomicAdd((unsigned long long *)&deg_out[v], (unsigned long long)c);
     }
 }
 
@@ -743,7 +758,8 @@ template <typename M>
 __global__ __launch_bounds__(kBlock) void compact_fill_hub(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
     Worklists wl, int64_t n_seg, LccTable tab, const int64_t *__restrict__ c_rp,
-    const int64_t *__restrict__ seg_count, int32_t *c_col, int32_t *c_off) {
+    const int64_t *__restrict__ seg_scan, const uint64_t *__restrict__ seg_bits, int32_t *c_col,
+    int32_t *c_off) {
     const int lane = lane_id();
     const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (seg >= n_seg) return;
@@ -751,22 +767,20 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
     const int32_t slot = wl.hub_seg_slot[seg];
     const uint64_t reach = reach_of<M>((uint64_t)omega[v], tab);
     if (!reach) return;
-    int64_t pos = c_rp[v];
-    for (int64_t j = wl.hub_seg_first[slot]; j < seg; ++j) pos += seg_count[j];
+    // offset of this segment in v's compacted row: kept entries of the
+    // slot's earlier segments (exclusive scan over all segments)
+    int64_t pos = c_rp[v] + seg_scan[seg] - seg_scan[wl.hub_seg_first[slot]];
     const int64_t row0 = rp[v];
     const int64_t b = wl.hub_seg_begin[seg], e = wl.hub_seg_end[seg];
-    for (int64_t base = b; base < e; base += kWave) {
-        const int64_t k = base + lane;
-        bool keep = false;
-        int32_t x = 0;
-        if (k < e) {
-            x = col[k];
-            keep = ((uint64_t)omega[x] & reach) != 0ull;
-        }
-        const uint64_t m = ballot64(keep);
-        if (keep) {
+    const uint64_t *bits = seg_bits + seg * (kHubSegment / kWave);
+    int chunk = 0;
+    for (int64_t base = b; base < e; base += kWave, ++chunk) {
+        const uint64_t m = bits[chunk];
+        if (!m) continue;
+        if ((m >> lane) & 1ull) {
+            const int64_t k = base + lane;
             const int64_t p = pos + __popcll(m & lanemask_lt());
-            c_col[p] = x;
+            c_col[p] = col[k];
             c_off[p] = (int32_t)(k - row0);
         }
         pos += __popcll(m);
@@ -776,7 +790,8 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
 template <typename M>
 void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                           const Worklists &wl, const int64_t *hc, int64_t n_seg,
-                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count) {
+                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count,
+                          uint64_t *seg_bits) {
     if (hc[0] > 0)
         hipLaunchKernelGGL((compact_count_group<M, 4>),
                            dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
@@ -792,14 +807,14 @@ void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, 
     if (n_seg > 0)
         hipLaunchKernelGGL((compact_count_hub<M>),
                            dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl, n_seg, tab, deg_out, seg_count);
+                           s, rp, col, omega, wl, n_seg, tab, deg_out, seg_count, seg_bits);
 }
 
 template <typename M>
 void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                          const Worklists &wl, const int64_t *hc, int64_t n_seg,
-                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_count,
-                         int32_t *c_col, int32_t *c_off) {
+                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
+                         const uint64_t *seg_bits, int32_t *c_col, int32_t *c_off) {
     if (hc[0] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 4>),
                            dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
@@ -815,7 +830,8 @@ void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, c
     if (n_seg > 0)
         hipLaunchKernelGGL((compact_fill_hub<M>),
                            dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl, n_seg, tab, c_rp, seg_count, c_col, c_off);
+                           s, rp, col, omega, wl, n_seg, tab, c_rp, seg_scan, seg_bits, c_col,
+                           c_off);
 }
 
 // --------------------------------------------------------- exclusive scan
@@ -991,11 +1007,11 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
                                       const LccTable &, int32_t *, bool);                         \
     template void launch_compact_count<M>(hipStream_t, const int64_t *, const int32_t *,           \
                                           const M *, const Worklists &, const int64_t *, int64_t, \
-                                          const LccTable &, int64_t *, int64_t *);                \
+                                          const LccTable &, int64_t *, int64_t *, uint64_t *);    \
     template void launch_compact_fill<M>(hipStream_t, const int64_t *, const int32_t *, const M *, \
                                          const Worklists &, const int64_t *, int64_t,             \
                                          const LccTable &, const int64_t *, const int64_t *,      \
-                                         int32_t *, int32_t *);                                   \
+                                         const uint64_t *, int32_t *, int32_t *);                 \
     template void launch_widen<M>(hipStream_t, int64_t, const M *, uint64_t *);                  \
     template void launch_collect<M>(hipStream_t, const int32_t *, int64_t, const M *, int32_t *,  \
                                     int32_t *);                                                   \

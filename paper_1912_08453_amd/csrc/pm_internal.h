@@ -185,20 +185,23 @@ void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *o
 // Candidate-subgraph compaction: keep the entries u->w of active u whose
 // roles are adjacent (edge elimination).  Count pass writes deg_out[v] for
 // binned v (deg_out must be zeroed; hubs accumulate per segment into
-// seg_count), then an exclusive scan gives c_rp (n+1), then the fill pass
-// writes c_col and c_off (offset of the entry within the original row).
+// seg_count and store each segment's keep bits in seg_bits, kHubSegment/64
+// words per segment), then an exclusive scan gives c_rp (n+1) and another
+// one over seg_count gives seg_scan, then the fill pass writes c_col and
+// c_off (offset of the entry within the original row).
 template <typename M>
 void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                           const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
-                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count);
+                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count,
+                          uint64_t *seg_bits);
 void launch_exclusive_scan(hipStream_t s, const int64_t *in, int64_t *out, int64_t n,
                            int64_t *scratch, int64_t scratch_len);
 int64_t scan_scratch_len(int64_t n);
 template <typename M>
 void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                          const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
-                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_count,
-                         int32_t *c_col, int32_t *c_off);
+                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
+                         const uint64_t *seg_bits, int32_t *c_col, int32_t *c_off);
 
 // Vertex-rooted searches.  mode 0: NLCC (certify head roles into sat);
 // mode 1: exact step (certify all roles into sat and edges into edge_bits).
