@@ -85,13 +85,13 @@ struct Timer {
 struct Scratch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, segcnt, segscan,
-        segbits, scan_scratch;
+    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, crp2, ccol2, coff2,
+        segcnt, segscan, segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
         actbits, ord;
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
-                          &ccol, &coff, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
+                          &ccol, &coff, &crp2, &ccol2, &coff2, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
                           &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -308,34 +308,50 @@ struct Pruner {
         st.ms_lcc += t.stop();
     }
 
-    // Compacted candidate subgraph of the current state (edge elimination).
-    void compact() {
+    // Compacted candidate subgraph of the current state (edge elimination),
+    // from the full graph or, once one exists, from the current candidate
+    // subgraph (a superset of the new one; offsets into the original rows
+    // are carried through c_off).  Two buffer sets alternate.
+    int cbuf = 0;
+    void compact(bool from_candidate = false) {
         Timer t(s);
         const int64_t n = c->n;
-        Graph full{c->rp, c->col};
-        bin(full);
+        const int64_t *src_rp = from_candidate ? c_rp : c->rp;
+        const int32_t *src_col = from_candidate ? c_col : c->col;
+        const int32_t *base_off = from_candidate ? c_off : nullptr;
+        Graph src{src_rp, src_col};
+        bin(src);
+        const int nb = from_candidate ? 1 - cbuf : cbuf;
+        DevBuf &crp = nb ? w->crp2 : w->crp;
+        DevBuf &ccol = nb ? w->ccol2 : w->ccol;
+        DevBuf &coff = nb ? w->coff2 : w->coff;
         w->cdeg.ensure(sizeof(int64_t) * (size_t)(n + 1));
-        w->crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
+        crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
         int64_t *deg = w->cdeg.as<int64_t>();
         PM_HIP(hipMemsetAsync(deg, 0, sizeof(int64_t) * (size_t)(n + 1), s));
-        launch_compact_count<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, deg,
+        launch_compact_count<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, deg,
                                 w->segcnt.as<int64_t>(), w->segbits.as<uint64_t>());
         int64_t sl = scan_scratch_len(std::max<int64_t>(n, nseg));
         w->scan_scratch.ensure(sizeof(int64_t) * (size_t)sl);
-        c_rp = w->crp.as<int64_t>();
-        launch_exclusive_scan(s, deg, c_rp, n, w->scan_scratch.as<int64_t>(), sl);
+        int64_t *new_rp = crp.as<int64_t>();
+        launch_exclusive_scan(s, deg, new_rp, n, w->scan_scratch.as<int64_t>(), sl);
         if (nseg > 0)
             launch_exclusive_scan(s, w->segcnt.as<int64_t>(), w->segscan.as<int64_t>(), nseg,
                                   w->scan_scratch.as<int64_t>(), sl);
-        d2h(s, &c_m, c_rp + n, 1);
-        if (c_m > (int64_t)INT32_MAX)
+        int64_t new_m = 0;
+        d2h(s, &new_m, new_rp + n, 1);
+        if (new_m > (int64_t)INT32_MAX)
             throw Error(PM_ERR_CAPACITY, "candidate subgraph has more than 2^31 - 1 entries");
-        w->ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
-        w->coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c_m, 1));
-        c_col = w->ccol.as<int32_t>();
-        c_off = w->coff.as<int32_t>();
-        launch_compact_fill<M>(s, c->rp, c->col, om, wl, hc, nseg, T.lcc, c_rp,
-                               w->segscan.as<int64_t>(), w->segbits.as<uint64_t>(), c_col, c_off);
+        ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
+        coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
+        launch_compact_fill<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, new_rp,
+                               w->segscan.as<int64_t>(), w->segbits.as<uint64_t>(), base_off,
+                               ccol.as<int32_t>(), coff.as<int32_t>());
+        c_rp = new_rp;
+        c_col = ccol.as<int32_t>();
+        c_off = coff.as<int32_t>();
+        c_m = new_m;
+        cbuf = nb;
         st.candidate_entries = c_m;
         st.ms_compact += t.stop();
     }
@@ -743,7 +759,7 @@ struct Pruner {
                 launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, T.lcc, edge_out);
             st.result_vertices = nA;
         } else {
-            if (nA > 0) compact();
+            if (nA > 0) compact(true);
             exact(role_out, edge_out);
         }
         st.ms_total = total.stop();

@@ -712,7 +712,7 @@ template <typename M, int G>
 __global__ __launch_bounds__(kBlock) void compact_fill_group(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
     const int32_t *__restrict__ list, int64_t count, LccTable tab, const int64_t *__restrict__ c_rp,
-    int32_t *c_col, int32_t *c_off) {
+    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off) {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
     const int sub_shift = lane & ~(G - 1);
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_group(
         if (keep) {
             const int64_t p = pos + __popcll(m & lanemask_lt());
             c_col[p] = x;
-            c_off[p] = (int32_t)(k - s);
+            c_off[p] = base_off ? base_off[k] : (int32_t)(k - s);
         }
         pos += __popcll(m);
     }
@@ -758,8 +758,8 @@ template <typename M>
 __global__ __launch_bounds__(kBlock) void compact_fill_hub(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
     Worklists wl, int64_t n_seg, LccTable tab, const int64_t *__restrict__ c_rp,
-    const int64_t *__restrict__ seg_scan, const uint64_t *__restrict__ seg_bits, int32_t *c_col,
-    int32_t *c_off) {
+    const int64_t *__restrict__ seg_scan, const uint64_t *__restrict__ seg_bits,
+    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off) {
     const int lane = lane_id();
     const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (seg >= n_seg) return;
@@ -781,7 +781,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
             const int64_t k = base + lane;
             const int64_t p = pos + __popcll(m & lanemask_lt());
             c_col[p] = col[k];
-            c_off[p] = (int32_t)(k - row0);
+            c_off[p] = base_off ? base_off[k] : (int32_t)(k - row0);
         }
         pos += __popcll(m);
     }
@@ -814,24 +814,25 @@ template <typename M>
 void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                          const Worklists &wl, const int64_t *hc, int64_t n_seg,
                          const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
-                         const uint64_t *seg_bits, int32_t *c_col, int32_t *c_off) {
+                         const uint64_t *seg_bits, const int32_t *base_off, int32_t *c_col,
+                         int32_t *c_off) {
     if (hc[0] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 4>),
                            dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           rp, col, omega, wl.list[0], hc[0], tab, c_rp, c_col, c_off);
+                           rp, col, omega, wl.list[0], hc[0], tab, c_rp, base_off, c_col, c_off);
     if (hc[1] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 16>),
                            dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[1], hc[1], tab, c_rp, c_col, c_off);
+                           s, rp, col, omega, wl.list[1], hc[1], tab, c_rp, base_off, c_col, c_off);
     if (hc[2] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 64>),
                            dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[2], hc[2], tab, c_rp, c_col, c_off);
+                           s, rp, col, omega, wl.list[2], hc[2], tab, c_rp, base_off, c_col, c_off);
     if (n_seg > 0)
         hipLaunchKernelGGL((compact_fill_hub<M>),
                            dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl, n_seg, tab, c_rp, seg_scan, seg_bits, c_col,
-                           c_off);
+                           s, rp, col, omega, wl, n_seg, tab, c_rp, seg_scan, seg_bits, base_off,
+                           c_col, c_off);
 }
 
 // --------------------------------------------------------- exclusive scan
@@ -1011,7 +1012,7 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
     template void launch_compact_fill<M>(hipStream_t, const int64_t *, const int32_t *, const M *, \
                                          const Worklists &, const int64_t *, int64_t,             \
                                          const LccTable &, const int64_t *, const int64_t *,      \
-                                         const uint64_t *, int32_t *, int32_t *);                 \
+                                         const uint64_t *, const int32_t *, int32_t *, int32_t *); \
     template void launch_widen<M>(hipStream_t, int64_t, const M *, uint64_t *);                  \
     template void launch_collect<M>(hipStream_t, const int32_t *, int64_t, const M *, int32_t *,  \
                                     int32_t *);                                                   \

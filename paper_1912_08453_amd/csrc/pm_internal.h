@@ -188,7 +188,9 @@ void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *o
 // seg_count and store each segment's keep bits in seg_bits, kHubSegment/64
 // words per segment), then an exclusive scan gives c_rp (n+1) and another
 // one over seg_count gives seg_scan, then the fill pass writes c_col and
-// c_off (offset of the entry within the original row).
+// c_off (offset of the entry within the original row: k - row start, or
+// base_off[k] when the source is itself a compacted graph whose c_off is
+// base_off).
 template <typename M>
 void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                           const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
@@ -201,7 +203,8 @@ template <typename M>
 void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                          const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
                          const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
-                         const uint64_t *seg_bits, int32_t *c_col, int32_t *c_off);
+                         const uint64_t *seg_bits, const int32_t *base_off, int32_t *c_col,
+                         int32_t *c_off);
 
 // Vertex-rooted searches.  mode 0: NLCC (certify head roles into sat);
 // mode 1: exact step (certify all roles into sat and edges into edge_bits).
