@@ -296,10 +296,24 @@ struct Pruner {
     }
 
     // LCC to the fixpoint on graph g, starting from the current active list.
-    void lcc_fixpoint(const Graph &g) {
+    // LCC to the fixpoint on the candidate subgraph.  When the active set
+    // has shrunk to under half of what it was at the last compaction and
+    // the active rows still hold many entries, the candidate subgraph is
+    // compacted again first (entries to eliminated vertices go), so later
+    // sweeps and the role lists read only live entries.
+    void lcc_fixpoint() {
         Timer t(s);
         for (;;) {
+            Graph g{c_rp, c_col};
             bin(g);
+            if (nA * 2 < nA_compact && binned_entries > kRecompactEntries &&
+                binned_entries > 4 * nA) {
+                const double ms_before = st.ms_compact;
+                compact(true);
+                st.ms_lcc -= st.ms_compact - ms_before;   // counted as compaction
+                g = Graph{c_rp, c_col};
+                bin(g);
+            }
             int32_t ch = sweep(g);
             if (!ch) break;
             collect(false);
@@ -313,6 +327,8 @@ struct Pruner {
     // subgraph (a superset of the new one; offsets into the original rows
     // are carried through c_off).  Two buffer sets alternate.
     int cbuf = 0;
+    int64_t nA_compact = 0;   // active vertices when the subgraph was built
+    static constexpr int64_t kRecompactEntries = 1 << 20;
     void compact(bool from_candidate = false) {
         Timer t(s);
         const int64_t n = c->n;
@@ -352,6 +368,7 @@ struct Pruner {
         c_off = coff.as<int32_t>();
         c_m = new_m;
         cbuf = nb;
+        nA_compact = nA;
         st.candidate_entries = c_m;
         st.ms_compact += t.stop();
     }
@@ -637,7 +654,7 @@ struct Pruner {
             int32_t ch = nlcc(T.constraints[(size_t)k]);
             if (ch) {
                 collect(false);
-                if (nA > 0) lcc_fixpoint(Graph{c_rp, c_col});
+                if (nA > 0) lcc_fixpoint();
             }
             const double ms = tt.stop();
             remaining &= ~(1ull << k);
@@ -730,8 +747,7 @@ struct Pruner {
         }
         // candidate subgraph (edge elimination) and the rest of LCC on it
         compact();
-        Graph cand{c_rp, c_col};
-        if (T.n0 > 1 && nA > 0) lcc_fixpoint(cand);
+        if (T.n0 > 1 && nA > 0) lcc_fixpoint();
         int stop_after = opt ? opt->stop_after : -1;
         const int K = (int)T.constraints.size();
         const bool learned = opt && opt->order_mode == PM_ORDER_LEARNED;
