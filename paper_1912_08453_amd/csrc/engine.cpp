@@ -316,6 +316,7 @@ struct Pruner {
             }
             int32_t ch = sweep(g);
             if (!ch) break;
+            rl_valid = false;
             collect(false);
             if (nA == 0) break;
         }
@@ -369,6 +370,7 @@ struct Pruner {
         c_m = new_m;
         cbuf = nb;
         nA_compact = nA;
+        rl_valid = false;
         st.candidate_entries = c_m;
         st.ms_compact += t.stop();
     }
@@ -409,10 +411,13 @@ struct Pruner {
         return a;
     }
 
-    // Role counts of the active vertices (search-order estimates).
     // Role lists of the active vertices over the compacted subgraph, built
-    // from the current role sets (the snapshot a constraint reads).
+    // from the current role sets (the snapshot a constraint reads).  They
+    // stay valid until the role sets, the active list or the subgraph
+    // change (rl_valid), so a constraint that removed nothing lets the next
+    // one reuse them.
     int64_t rl_total = 0;
+    bool rl_valid = false;
     void role_lists() {
         const int64_t nn = std::max<int64_t>(nA, 1) * T.n0;
         w->rlcnt.ensure(sizeof(int64_t) * (size_t)(nn + 1));
@@ -433,18 +438,20 @@ struct Pruner {
         w->rlent.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
         launch_role_fill<M>(s, A, nA, c_rp, c_col, om, T.n0, w->rloff.as<int64_t>(),
                             w->rlcol.as<int32_t>(), w->rlent.as<int32_t>());
+        rl_valid = true;
     }
 
     // One non-local constraint (snapshot semantics); returns vertices changed.
     int32_t nlcc(const Constraint &k) {
         Timer t(s);
-        role_lists();
+        if (!rl_valid) role_lists();
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         SearchArgs a = search_args(0, k.heads, k.plan_of_head, nullptr);
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
         PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
         launch_apply<M>(s, A, nA, om, sat, k.heads, ctr + C_CHANGED);
         int32_t ch = read_ctr(C_CHANGED);
+        if (ch) rl_valid = false;
         st.constraints++;
         st.ms_nlcc += t.stop();
         return ch;
@@ -513,6 +520,7 @@ struct Pruner {
                 std::swap(om, sat);
                 role_lists();
                 std::swap(om, sat);
+                rl_valid = false;   // lists of the certified sets, not of omega
                 a.rl_off = w->rloff.as<int64_t>();
                 a.rl_col = w->rlcol.as<int32_t>();
                 a.rl_ent = w->rlent.as<int32_t>();
