@@ -35,7 +35,8 @@
  *    edges by swaps of recorded witnesses (off by default: measured slower
  *    once the edge searches use relisted roles), PM_RELIST=0 keeps the edge
  *    searches on the pre-search role lists, PM_EDGE_CHUNK=k sets the edge
- *    tasks a wavefront takes at once (default 16).  Read by pm_load_graph:
+ *    tasks a wavefront takes at once (default 16), PM_EDGE_STRIPES=s the
+ *    number of stripes the edge task list is dealt in (default 64).  Read by pm_load_graph:
  *    PM_NO_COUNT_INDEX=1 skips the neighbour-label count index (the first
  *    LCC sweep then gathers over the CSR).
  */

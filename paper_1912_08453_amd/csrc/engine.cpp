@@ -85,13 +85,14 @@ struct Timer {
 struct Scratch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, crp2, ccol2, coff2,
+    DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, cown, crp2, ccol2,
+        coff2, cown2,
         segcnt, segscan, segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
         actbits, ord;
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
-                          &ccol, &coff, &crp2, &ccol2, &coff2, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
+                          &ccol, &coff, &cown, &crp2, &ccol2, &coff2, &cown2, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
                           &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -134,6 +135,7 @@ struct pm_ctx {
     int witness = 0;
     int edge_chunk = 16;
     int relist = 1;
+    int edge_stripes = 64;
     int64_t wall_khz = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
@@ -190,6 +192,7 @@ struct Pruner {
     int64_t *c_rp = nullptr;
     int32_t *c_col = nullptr;
     int32_t *c_off = nullptr;
+    int32_t *c_own = nullptr;
     int64_t c_m = 0;
     pm_stats st{};
 
@@ -342,6 +345,7 @@ struct Pruner {
         DevBuf &crp = nb ? w->crp2 : w->crp;
         DevBuf &ccol = nb ? w->ccol2 : w->ccol;
         DevBuf &coff = nb ? w->coff2 : w->coff;
+        DevBuf &cown = nb ? w->cown2 : w->cown;
         w->cdeg.ensure(sizeof(int64_t) * (size_t)(n + 1));
         crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
         int64_t *deg = w->cdeg.as<int64_t>();
@@ -361,12 +365,14 @@ struct Pruner {
             throw Error(PM_ERR_CAPACITY, "candidate subgraph has more than 2^31 - 1 entries");
         ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
         coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
+        cown.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
         launch_compact_fill<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, new_rp,
                                w->segscan.as<int64_t>(), w->segbits.as<uint64_t>(), base_off,
-                               ccol.as<int32_t>(), coff.as<int32_t>());
+                               ccol.as<int32_t>(), coff.as<int32_t>(), cown.as<int32_t>());
         c_rp = new_rp;
         c_col = ccol.as<int32_t>();
         c_off = coff.as<int32_t>();
+        c_own = cown.as<int32_t>();
         c_m = new_m;
         cbuf = nb;
         nA_compact = nA;
@@ -397,6 +403,7 @@ struct Pruner {
         a.edge_bits = edge_bits;
         a.task_counter = ctr + C_TASK;
         a.task_chunk = 4;
+        a.stripes = 1;
         a.n_queries = queries;
         a.c_cert = nullptr;
         a.exp_seen = nullptr;
@@ -502,7 +509,7 @@ struct Pruner {
         w->ew.ensure(sizeof(int32_t) * (size_t)cap);
         w->eidx.ensure(sizeof(int64_t) * (size_t)cap);
         PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
-        launch_edge_candidates<M>(s, A, nA, c_rp, c_col, sat, T.lcc, c_cert,
+        launch_edge_candidates<M>(s, c_m, c_own, c_col, sat, T.lcc, c_cert,
                                   w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ctr + C_NOUT, cap, a);
         a.wit_on = 0;
@@ -534,13 +541,14 @@ struct Pruner {
             PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
             PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
             a.task_chunk = c->edge_chunk;
+            a.stripes = c->edge_stripes;
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
                                   w->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
                                   a, c->grid_search);
             d2h(s, &q1, queries, 1);
         }
-        launch_edges_from_cert(s, A, nA, c_rp, c_col, c_off, c->rp, c_cert, edge_out);
+        launch_edges_from_cert(s, c_m, c_rp, c_col, c_own, c_off, c->rp, c_cert, edge_out);
         launch_widen<M>(s, n, sat, role_out);
         unsigned long long qs[16];
         d2h(s, qs, qstats, 16);
@@ -903,6 +911,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             if (wn) c->witness = atoi(wn);
             const char *rl = getenv("PM_RELIST");
             if (rl) c->relist = atoi(rl);
+            const char *es = getenv("PM_EDGE_STRIPES");
+            if (es) c->edge_stripes = std::max(1, atoi(es));
             const char *ec = getenv("PM_EDGE_CHUNK");
             if (ec) c->edge_chunk = std::max(1, atoi(ec));
         } catch (...) {

@@ -712,7 +712,7 @@ template <typename M, int G>
 __global__ __launch_bounds__(kBlock) void compact_fill_group(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
     const int32_t *__restrict__ list, int64_t count, LccTable tab, const int64_t *__restrict__ c_rp,
-    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off) {
+    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off, int32_t *c_own) {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
     const int sub_shift = lane & ~(G - 1);
@@ -749,6 +749,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_group(
             const int64_t p = pos + __popcll(m & lanemask_lt());
             c_col[p] = x;
             c_off[p] = base_off ? base_off[k] : (int32_t)(k - s);
+            c_own[p] = v;
         }
         pos += __popcll(m);
     }
@@ -759,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
     Worklists wl, int64_t n_seg, LccTable tab, const int64_t *__restrict__ c_rp,
     const int64_t *__restrict__ seg_scan, const uint64_t *__restrict__ seg_bits,
-    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off) {
+    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off, int32_t *c_own) {
     const int lane = lane_id();
     const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (seg >= n_seg) return;
@@ -782,6 +783,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
             const int64_t p = pos + __popcll(m & lanemask_lt());
             c_col[p] = col[k];
             c_off[p] = base_off ? base_off[k] : (int32_t)(k - row0);
+            c_own[p] = v;
         }
         pos += __popcll(m);
     }
@@ -815,24 +817,27 @@ void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, c
                          const Worklists &wl, const int64_t *hc, int64_t n_seg,
                          const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
                          const uint64_t *seg_bits, const int32_t *base_off, int32_t *c_col,
-                         int32_t *c_off) {
+                         int32_t *c_off, int32_t *c_own) {
     if (hc[0] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 4>),
                            dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           rp, col, omega, wl.list[0], hc[0], tab, c_rp, base_off, c_col, c_off);
+                           rp, col, omega, wl.list[0], hc[0], tab, c_rp, base_off, c_col, c_off,
+                           c_own);
     if (hc[1] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 16>),
                            dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[1], hc[1], tab, c_rp, base_off, c_col, c_off);
+                           s, rp, col, omega, wl.list[1], hc[1], tab, c_rp, base_off, c_col, c_off,
+                           c_own);
     if (hc[2] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 64>),
                            dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[2], hc[2], tab, c_rp, base_off, c_col, c_off);
+                           s, rp, col, omega, wl.list[2], hc[2], tab, c_rp, base_off, c_col, c_off,
+                           c_own);
     if (n_seg > 0)
         hipLaunchKernelGGL((compact_fill_hub<M>),
                            dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            s, rp, col, omega, wl, n_seg, tab, c_rp, seg_scan, seg_bits, base_off,
-                           c_col, c_off);
+                           c_col, c_off, c_own);
 }
 
 // --------------------------------------------------------- exclusive scan
@@ -1012,7 +1017,8 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
     template void launch_compact_fill<M>(hipStream_t, const int64_t *, const int32_t *, const M *, \
                                          const Worklists &, const int64_t *, int64_t,             \
                                          const LccTable &, const int64_t *, const int64_t *,      \
-                                         const uint64_t *, const int32_t *, int32_t *, int32_t *); \
+                                         const uint64_t *, const int32_t *, int32_t *, int32_t *,  \
+                                         int32_t *);                                              \
     template void launch_widen<M>(hipStream_t, int64_t, const M *, uint64_t *);                  \
     template void launch_collect<M>(hipStream_t, const int32_t *, int64_t, const M *, int32_t *,  \
                                     int32_t *);                                                   \

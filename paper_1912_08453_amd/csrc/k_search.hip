@@ -664,48 +664,47 @@ __device__ bool witness_swap(const SearchArgs &a, const LccTable &tab, uint64_t 
 // Candidate edges: entries a -> b (a < b) of the compacted subgraph whose
 // certified roles are adjacent in G0 and that no found match certified yet
 // (a certified edge has the bit of exactly this entry set); those a witness
-// swap certifies are certified here instead.
+// swap certifies are certified here instead.  One thread per compacted
+// entry (c_own gives its row), so hub rows do not serialise on one
+// wavefront.
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
-    const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
-    const M *cert, LccTable tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
-    int64_t *e_idx, int32_t *n_out, int64_t cap, SearchArgs a) {
+    int64_t c_m, const int32_t *__restrict__ c_own, const int32_t *__restrict__ c_col,
+    const M *cert, LccTable tab, uint64_t *c_cert, int32_t *eu, int32_t *ew, int64_t *e_idx,
+    int32_t *n_out, int64_t cap, SearchArgs a) {
     const int lane = lane_id();
     unsigned long long swapped = 0;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t t = wave; t < n_tasks; t += nwaves) {
-        const int32_t u = tasks[t];
-        const uint64_t cu = (uint64_t)cert[u];
-        if (!cu) continue;
-        const uint64_t reach = reach_mask<M>(cu, tab);
-        const int64_t s = c_rp[u], e = c_rp[u + 1];
-        for (int64_t base = s; base < e; base += kWave) {
-            const int64_t k = base + lane;
-            bool p = false;
-            int32_t w = 0;
-            if (k < e) {
-                w = c_col[k];
-                const uint64_t cw = (uint64_t)cert[w];
-                p = w > u && (cw & reach) != 0ull && !test_bit(c_cert, k);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // the loop bound is uniform over the block, so ballots see every lane
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < c_m; base += stride) {
+        const int64_t k = base + threadIdx.x;
+        bool p = false;
+        int32_t u = 0, w = 0;
+        if (k < c_m) {
+            u = c_own[k];
+            w = c_col[k];
+            if (w > u) {
+                const uint64_t cu = (uint64_t)cert[u];
+                const uint64_t cw = cu ? (uint64_t)cert[w] : 0ull;
+                p = cw != 0ull && (cw & reach_mask<M>(cu, tab)) != 0ull && !test_bit(c_cert, k);
                 if (p && a.wit_on && witness_swap(a, tab, cu, cw, u, w)) {
                     set_bit(c_cert, k);
                     ++swapped;
                     p = false;
                 }
             }
-            const uint64_t m = ballot64(p);
-            if (!m) continue;
-            int pos = 0;
-            if (lane == 0) pos = atomicAdd(n_out, __popcll(m));
-            pos = __shfl(pos, 0);
-            if (p) {
-                const int64_t o = pos + __popcll(m & lanemask_lt());
-                if (o < cap) {
-                    eu[o] = u;
-                    ew[o] = w;
-                    e_idx[o] = k;
-                }
+        }
+        const uint64_t m = ballot64(p);
+        if (!m) continue;
+        int pos = 0;
+        if (lane == 0) pos = atomicAdd(n_out, __popcll(m));
+        pos = __shfl(pos, 0);
+        if (p) {
+            const int64_t o = pos + __popcll(m & lanemask_lt());
+            if (o < cap) {
+                eu[o] = u;
+                ew[o] = w;
+                e_idx[o] = k;
             }
         }
     }
@@ -714,16 +713,15 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
 }
 
 template <typename M>
-void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_col, const M *cert,
-                            const LccTable &tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
-                            int64_t *e_idx, int32_t *n_out, int64_t cap, const SearchArgs &a) {
-    if (n_tasks <= 0) return;
-    int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
-    if (grid > 8192) grid = 8192;
+void launch_edge_candidates(hipStream_t s, int64_t c_m, const int32_t *c_own,
+                            const int32_t *c_col, const M *cert, const LccTable &tab,
+                            uint64_t *c_cert, int32_t *eu, int32_t *ew, int64_t *e_idx,
+                            int32_t *n_out, int64_t cap, const SearchArgs &a) {
+    if (c_m <= 0) return;
+    int64_t grid = (c_m + kSearchBlock - 1) / kSearchBlock;
+    if (grid > 16384) grid = 16384;
     hipLaunchKernelGGL(edge_candidates_kernel<M>, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       tasks, n_tasks, c_rp, c_col, cert, tab, c_cert, eu, ew, e_idx, n_out, cap,
-                       a);
+                       c_m, c_own, c_col, cert, tab, c_cert, eu, ew, e_idx, n_out, cap, a);
 }
 
 template <typename M>
@@ -733,12 +731,23 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
     const int lane = lane_id();
     unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0, tcert = 0, texp = 0;
     ExpandCount ec;
+    // chunks of task_chunk consecutive candidates are handed out in striped
+    // order: chunk c is the (c / S)-th chunk of stripe c % S, so waves
+    // running at the same time work on distant parts of the list (other
+    // vertices) and later chunks of a vertex find more of its edges already
+    // certified
+    const int64_t n_chunks = (n_edges + a.task_chunk - 1) / a.task_chunk;
+    const int64_t S = a.stripes > 1 ? a.stripes : 1;
+    const int64_t R = (n_chunks + S - 1) / S;
     for (;;) {
-        int t0 = 0;
-        if (lane == 0) t0 = atomicAdd(a.task_counter, a.task_chunk);
-        t0 = __shfl(t0, 0);
-        if ((int64_t)t0 >= n_edges) break;
-        const int64_t t1 = (int64_t)t0 + a.task_chunk < n_edges ? (int64_t)t0 + a.task_chunk : n_edges;
+        int c = 0;
+        if (lane == 0) c = atomicAdd(a.task_counter, 1);
+        c = __shfl(c, 0);
+        if ((int64_t)c >= S * R) break;
+        const int64_t pc = ((int64_t)c % S) * R + (int64_t)c / S;
+        if (pc >= n_chunks) continue;
+        const int64_t t0 = pc * a.task_chunk;
+        const int64_t t1 = t0 + a.task_chunk < n_edges ? t0 + a.task_chunk : n_edges;
         for (int64_t t = t0; t < t1; ++t) {
             const int32_t u = eu[t], w = ew[t];
             const int64_t k = e_idx[t];
@@ -797,34 +806,32 @@ void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
 
 // Output edge bits from certified compacted entries (each certified edge
 // holds the bit of its entry u -> w with u < w): both CSR entries of the
-// edge are set; the reverse entry is found in w's compacted row.
+// edge are set; the reverse entry is found in w's compacted row.  One
+// thread per 64-entry word of certificates (c_own gives each entry's row).
 __global__ __launch_bounds__(kSearchBlock) void edges_from_cert_kernel(
-    const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp, const int32_t *c_col,
+    int64_t words, const int64_t *c_rp, const int32_t *c_col, const int32_t *c_own,
     const int32_t *c_off, const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t t = wave; t < n_tasks; t += nwaves) {
-        const int32_t u = tasks[t];
-        const int64_t s = c_rp[u], e = c_rp[u + 1], r0 = rp[u];
-        for (int64_t k = s + lane; k < e; k += kWave) {
-            if (!test_bit(c_cert, k)) continue;
-            set_bit(edge_bits, r0 + c_off[k]);
-            const int32_t w = c_col[k];
+    for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < words;
+         wi += (int64_t)gridDim.x * blockDim.x) {
+        for (uint64_t bits = c_cert[wi]; bits; bits &= bits - 1) {
+            const int64_t k = wi * 64 + __builtin_ctzll(bits);
+            const int32_t u = c_own[k], w = c_col[k];
+            set_bit(edge_bits, rp[u] + c_off[k]);
             const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
             if (kr >= 0) set_bit(edge_bits, rp[w] + c_off[kr]);
         }
     }
 }
 
-void launch_edges_from_cert(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
-                            const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
-    if (n_tasks <= 0) return;
-    int64_t grid = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
-    if (grid > 8192) grid = 8192;
+void launch_edges_from_cert(hipStream_t s, int64_t c_m, const int64_t *c_rp, const int32_t *c_col,
+                            const int32_t *c_own, const int32_t *c_off, const int64_t *rp,
+                            const uint64_t *c_cert, uint64_t *edge_bits) {
+    const int64_t words = (c_m + 63) / 64;
+    if (words <= 0) return;
+    int64_t grid = (words + kSearchBlock - 1) / kSearchBlock;
+    if (grid > 16384) grid = 16384;
     hipLaunchKernelGGL(edges_from_cert_kernel, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       tasks, n_tasks, c_rp, c_col, c_off, rp, c_cert, edge_bits);
+                       words, c_rp, c_col, c_own, c_off, rp, c_cert, edge_bits);
 }
 
 // Edge state implied by role sets (edge elimination rule): bit of entry
@@ -868,10 +875,10 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                                           const SearchArgs &, int);                               \
     template void launch_apply<M>(hipStream_t, const int32_t *, int64_t, M *, M *, uint64_t,      \
                                   int32_t *);                                                     \
-    template void launch_edge_candidates<M>(hipStream_t, const int32_t *, int64_t,                \
-                                            const int64_t *, const int32_t *, const M *,          \
-                                            const LccTable &, uint64_t *, int32_t *, int32_t *,   \
-                                            int64_t *, int32_t *, int64_t, const SearchArgs &);   \
+    template void launch_edge_candidates<M>(hipStream_t, int64_t, const int32_t *,                \
+                                            const int32_t *, const M *, const LccTable &,         \
+                                            uint64_t *, int32_t *, int32_t *, int64_t *,          \
+                                            int32_t *, int64_t, const SearchArgs &);              \
     template void launch_edge_search<M>(hipStream_t, const int32_t *, const int32_t *,            \
                                         const int64_t *, int64_t, const M *, M *,                 \
                                         const int32_t *, int32_t, const SearchArgs &, int);       \

@@ -187,8 +187,8 @@ void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *o
 // binned v (deg_out must be zeroed; hubs accumulate per segment into
 // seg_count and store each segment's keep bits in seg_bits, kHubSegment/64
 // words per segment), then an exclusive scan gives c_rp (n+1) and another
-// one over seg_count gives seg_scan, then the fill pass writes c_col and
-// c_off (offset of the entry within the original row: k - row start, or
+// one over seg_count gives seg_scan, then the fill pass writes c_col, c_own
+// (the row's vertex) and c_off (offset of the entry within the original row: k - row start, or
 // base_off[k] when the source is itself a compacted graph whose c_off is
 // base_off).
 template <typename M>
@@ -204,7 +204,7 @@ void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, c
                          const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
                          const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
                          const uint64_t *seg_bits, const int32_t *base_off, int32_t *c_col,
-                         int32_t *c_off);
+                         int32_t *c_off, int32_t *c_own);
 
 // Vertex-rooted searches.  mode 0: NLCC (certify head roles into sat);
 // mode 1: exact step (certify all roles into sat and edges into edge_bits).
@@ -228,6 +228,7 @@ struct SearchArgs {
     uint64_t *edge_bits;
     int32_t *task_counter;
     int32_t task_chunk;             // consecutive tasks a wavefront takes per atomic
+    int32_t stripes;                // edge searches: chunk order striped S ways
     unsigned long long *n_queries;
     // exact step: certified edges of the compacted subgraph (bit k = entry k
     // = u -> w with u < w), the table of swap scans
@@ -265,10 +266,10 @@ void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, cons
                       int32_t *rl_col, int32_t *rl_ent);
 
 // Output edge bits (both entries) from certified compacted entries u -> w,
-// u < w.
-void launch_edges_from_cert(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_col, const int32_t *c_off,
-                            const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits);
+// u < w; one thread per 64 compacted entries (c_own gives each entry's row).
+void launch_edges_from_cert(hipStream_t s, int64_t c_m, const int64_t *c_rp, const int32_t *c_col,
+                            const int32_t *c_own, const int32_t *c_off, const int64_t *rp,
+                            const uint64_t *c_cert, uint64_t *edge_bits);
 
 template <typename M>
 void launch_vertex_search(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,
@@ -285,10 +286,10 @@ void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega
 // Candidates whose edge a recorded witness certifies by one vertex swap are
 // certified here instead of being listed (a.wit_on).
 template <typename M>
-void launch_edge_candidates(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
-                            const int64_t *c_rp, const int32_t *c_col, const M *cert,
-                            const LccTable &tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
-                            int64_t *e_idx, int32_t *n_out, int64_t cap, const SearchArgs &a);
+void launch_edge_candidates(hipStream_t s, int64_t c_m, const int32_t *c_own,
+                            const int32_t *c_col, const M *cert, const LccTable &tab,
+                            uint64_t *c_cert, int32_t *eu, int32_t *ew, int64_t *e_idx,
+                            int32_t *n_out, int64_t cap, const SearchArgs &a);
 
 template <typename M>
 void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,

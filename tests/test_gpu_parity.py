@@ -284,7 +284,8 @@ def test_count_index_unaligned_labels_and_gather_path_agree(pmmod, torch_dev, mo
 
 
 @pytest.mark.parametrize("env", [{"PM_RELIST": "0"}, {"PM_WITNESS": "1"}, {"PM_EXPAND": "0"},
-                                 {"PM_EXPAND_MAX": "32"}, {"PM_EDGE_CHUNK": "1"}])
+                                 {"PM_EXPAND_MAX": "32"}, {"PM_EDGE_CHUNK": "1"},
+                                 {"PM_EDGE_STRIPES": "1"}, {"PM_EDGE_STRIPES": "7"}])
 def test_exact_step_switches_give_the_same_result(pmmod, torch_dev, monkeypatch, env):
     """The exact step's optional savings (role lists rebuilt from the exact
     roles, witness swaps, swap scans, their length cap, task chunking) only
