@@ -40,10 +40,12 @@ def main():
                     help="run only a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
-    ap.add_argument("--legs", default="batched,learned",
+    ap.add_argument("--legs", default="batched,learned,autotune",
                     help="extra legs on the same resident graph: batched (64 mixed templates, "
                          "one call per template vs concurrent streams), learned (64 multi-cycle "
-                         "templates, fixed vs learned constraint order); '' for none")
+                         "templates, fixed vs learned constraint order), autotune (coordinate "
+                         "search of the tuning settings on the timed template; the timed "
+                         "steps above use the defaults); '' for none")
     ap.add_argument("--batch-streams", type=int, default=4)
     ap.add_argument("--workload", default="tri-square-s22", choices=["tri-square-s22", "theta8-s26"],
                     help="tri-square-s22: one template at scale 22 (default); theta8-s26: scale-26 base template "
@@ -155,7 +157,10 @@ def main():
     counts["result_entries"] = int(np.unpackbits(pm.to_u64(edge[0]).view(np.uint8)).sum())
 
     legs = [x for x in args.legs.split(",") if x]
-    batched = learned = None
+    batched = learned = tuned = None
+    if "autotune" in legs:
+        tuned = autotune_leg(ctx, tid, role, edge)
+        log(f"autotune: {json.dumps(tuned)}")
     if "batched" in legs:
         batched = batched_leg(ctx, g, args.batch_streams)
         log(f"batched: {json.dumps(batched)}")
@@ -196,6 +201,7 @@ def main():
                            "bound": "search latency / random gathers (no roofline claim)"},
         "cpu_baseline": cpu,
         "batched": batched,
+        "autotune": tuned,
         "learned_order": learned,
     }
     print(json.dumps(out), flush=True)
@@ -309,6 +315,27 @@ def exploratory(args, scale=26, graph_seed=26, template_seed=0):
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def autotune_leg(ctx, tid, role, edge):
+    """Coordinate search of the tuning settings on the timed template (best
+    of 3 prunes per candidate), the tuned time against the defaults' on the
+    same timer, and the output with the tuned settings against the timed
+    steps' output.  The defaults are restored afterwards."""
+    import torch
+    from paper_1912_08453_amd import autotune
+    start = ctx.params()
+    best, table = autotune.autotune(ctx, [tid], reps=3)
+    timer = autotune.prune_timer(ctx, [tid], reps=5)
+    tuned_ms = timer()
+    r2, e2, _ = ctx.prune(tid)
+    same = bool(torch.equal(r2, role) and torch.equal(e2, edge))
+    for k, v in start.items():
+        ctx.set_param(k, v)
+    default_ms = timer()
+    return {"defaults": start, "tuned": {k: v for k, v in best.items() if v != start[k]},
+            "candidates_timed": len(table) - 1, "default_ms": round(default_ms, 2),
+            "tuned_ms": round(tuned_ms, 2), "outputs_identical": same}
 
 
 def batched_leg(ctx, g, streams, seed=3, count=64):

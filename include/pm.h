@@ -254,6 +254,22 @@ int pm_inspect_template(const pm_template *t, int32_t *count, int32_t *kinds, in
 int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
              uint64_t *edge_bits, const pm_options *opt, pm_stats *stats);
 
+/* ---- tuning parameters ---------------------------------------------------------
+   Work-saving settings of the final search and the search launch; none
+   changes any result.  Names and values:
+     "expand"        1/0   single-vertex swap scans of found matches (1)
+     "expand_max"    k     skip swap scans of lists longer than k; -1: none (4096)
+     "witness"       1/0   certify candidate edges by witness swaps (0)
+     "relist"        1/0   edge searches on role lists of the exact roles (1)
+     "edge_chunk"    k     edge tasks a wavefront takes at once (16)
+     "edge_stripes"  s     stripes the edge task list is dealt in (64)
+     "search_grid"   b     blocks of the persistent search kernels (8 per CU)
+   The environment variables listed at the top seed these defaults when the
+   context is created.  PM_ERR_INVALID_ARG for an unknown name or a value
+   out of range. */
+int pm_set_param(pm_ctx *ctx, const char *name, int64_t value);
+int pm_get_param(pm_ctx *ctx, const char *name, int64_t *value);
+
 /* ---- learned ordering model ------------------------------------------------
    The perceptron and its training run in the library's kernels; the
    features and model are defined above PM_MLP_PARAMS. */

@@ -540,7 +540,12 @@ struct Pruner {
             }
             PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
             PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
-            a.task_chunk = c->edge_chunk;
+            // the dealing counter is 32-bit: it must stay below 2^31 after
+            // every chunk and every wave's final fetch
+            int64_t chunk = c->edge_chunk;
+            const int64_t waves = (int64_t)c->grid_search * 4;
+            while ((ne + chunk - 1) / chunk + c->edge_stripes + waves >= INT32_MAX) chunk *= 2;
+            a.task_chunk = (int)chunk;
             a.stripes = c->edge_stripes;
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
@@ -912,9 +917,9 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             const char *rl = getenv("PM_RELIST");
             if (rl) c->relist = atoi(rl);
             const char *es = getenv("PM_EDGE_STRIPES");
-            if (es) c->edge_stripes = std::max(1, atoi(es));
+            if (es) c->edge_stripes = std::min(1 << 16, std::max(1, atoi(es)));
             const char *ec = getenv("PM_EDGE_CHUNK");
-            if (ec) c->edge_chunk = std::max(1, atoi(ec));
+            if (ec) c->edge_chunk = std::min(1 << 16, std::max(1, atoi(ec)));
         } catch (...) {
             delete c;
             throw;
@@ -1217,6 +1222,36 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
         }
         PM_HIP(hipStreamSynchronize(c->stream));
         if (stats) *stats = total;
+    });
+}
+
+int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
+    return guarded([&] {
+        if (!c || !name) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        const std::string k(name);
+        if (k == "expand") c->expand = value ? 1 : 0;
+        else if (k == "expand_max") c->expand_max = value < 0 ? INT64_MAX : value;
+        else if (k == "witness") c->witness = value ? 1 : 0;
+        else if (k == "relist") c->relist = value ? 1 : 0;
+        else if (k == "edge_chunk" && value >= 1 && value <= (1 << 16)) c->edge_chunk = (int)value;
+        else if (k == "edge_stripes" && value >= 1 && value <= (1 << 16)) c->edge_stripes = (int)value;
+        else if (k == "search_grid" && value >= 1 && value <= (1 << 16)) c->grid_search = (int)value;
+        else throw Error(PM_ERR_INVALID_ARG, "unknown parameter or value out of range: " + k);
+    });
+}
+
+int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
+    return guarded([&] {
+        if (!c || !name || !value) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        const std::string k(name);
+        if (k == "expand") *value = c->expand;
+        else if (k == "expand_max") *value = c->expand_max == INT64_MAX ? -1 : c->expand_max;
+        else if (k == "witness") *value = c->witness;
+        else if (k == "relist") *value = c->relist;
+        else if (k == "edge_chunk") *value = c->edge_chunk;
+        else if (k == "edge_stripes") *value = c->edge_stripes;
+        else if (k == "search_grid") *value = c->grid_search;
+        else throw Error(PM_ERR_INVALID_ARG, "unknown parameter: " + k);
     });
 }
 

@@ -38,7 +38,7 @@ ERRORS = {
 SYMBOLS = ["pm_last_error", "pm_version", "pm_create", "pm_destroy", "pm_load_graph",
            "pm_unload_graph", "pm_load_templates", "pm_template_constraints",
            "pm_inspect_template", "pm_prune", "pm_load_model", "pm_mlp_forward", "pm_mlp_grad",
-           "pm_mlp_train"]
+           "pm_mlp_train", "pm_set_param", "pm_get_param"]
 
 
 class PMError(RuntimeError):
@@ -123,6 +123,8 @@ def load_library(path: str = None):
     lib.pm_prune.argtypes = [P, I32, I32, P, P, ctypes.POINTER(pm_options),
                              ctypes.POINTER(pm_stats)]
     lib.pm_load_model.argtypes = [P, P, ctypes.c_size_t]
+    lib.pm_set_param.argtypes = [P, ctypes.c_char_p, I64]
+    lib.pm_get_param.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I64)]
     lib.pm_mlp_forward.argtypes = [P, P, P, I64, P]
     lib.pm_mlp_grad.argtypes = [P, P, P, P, I64, P, P]
     lib.pm_mlp_train.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, P]
@@ -276,6 +278,21 @@ class PM:
         if tr is not None:
             out["trace"] = [tr[i].as_dict() for i in range(int(st.trace_entries))]
         return role_mask[:, :self.n], edge_bits[:, :words], out
+
+    # ------------------------------------------------------------ tuning
+    TUNING = ("expand", "expand_max", "witness", "relist", "edge_chunk", "edge_stripes",
+              "search_grid")
+
+    def set_param(self, name: str, value: int) -> None:
+        _check(self.lib, self.lib.pm_set_param(self.h, name.encode(), int(value)))
+
+    def get_param(self, name: str) -> int:
+        v = ctypes.c_int64()
+        _check(self.lib, self.lib.pm_get_param(self.h, name.encode(), ctypes.byref(v)))
+        return int(v.value)
+
+    def params(self) -> dict:
+        return {k: self.get_param(k) for k in self.TUNING}
 
     # ----------------------------------------------------- ordering model
     def load_model(self, w) -> None:
