@@ -89,11 +89,11 @@ struct Scratch {
         coff2, cown2,
         segcnt, segscan, segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
-        actbits, ord;
+        actbits, ord, afilt;
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
                           &ccol, &coff, &cown, &crp2, &ccol2, &coff2, &cown2, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
-                          &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord})
+                          &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord, &afilt})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
@@ -350,7 +350,14 @@ struct Pruner {
         crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
         int64_t *deg = w->cdeg.as<int64_t>();
         PM_HIP(hipMemsetAsync(deg, 0, sizeof(int64_t) * (size_t)(n + 1), s));
-        launch_compact_count<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, deg,
+        if (!from_candidate) {
+            // coarse filter of the active set; it stays valid (a superset)
+            // for later compactions of this prune, since role sets only shrink
+            w->afilt.ensure(sizeof(uint32_t) * (size_t)std::max<int64_t>((n + 255) / 256, 1));
+            launch_active_filter<M>(s, n, om, w->afilt.as<uint32_t>());
+        }
+        const uint32_t *filt = w->afilt.as<uint32_t>();
+        launch_compact_count<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, filt, deg,
                                 w->segcnt.as<int64_t>(), w->segbits.as<uint64_t>());
         int64_t sl = scan_scratch_len(std::max<int64_t>(n, nseg));
         w->scan_scratch.ensure(sizeof(int64_t) * (size_t)sl);
@@ -366,7 +373,7 @@ struct Pruner {
         ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
         coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
         cown.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
-        launch_compact_fill<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, new_rp,
+        launch_compact_fill<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, filt, new_rp,
                                w->segscan.as<int64_t>(), w->segbits.as<uint64_t>(), base_off,
                                ccol.as<int32_t>(), coff.as<int32_t>(), cown.as<int32_t>());
         c_rp = new_rp;
@@ -507,9 +514,9 @@ struct Pruner {
         const int64_t cap = c_m / 2 + 1;
         w->eu.ensure(sizeof(int32_t) * (size_t)cap);
         w->ew.ensure(sizeof(int32_t) * (size_t)cap);
-        w->eidx.ensure(sizeof(int64_t) * (size_t)cap);
+        w->eidx.ensure(2 * sizeof(int64_t) * (size_t)cap);   // (entry, reverse entry)
         PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
-        launch_edge_candidates<M>(s, c_m, c_own, c_col, sat, T.lcc, c_cert,
+        launch_edge_candidates<M>(s, c_m, c_rp, c_own, c_col, sat, T.lcc, c_cert,
                                   w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ctr + C_NOUT, cap, a);
         a.wit_on = 0;

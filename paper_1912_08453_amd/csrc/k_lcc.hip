@@ -397,57 +397,41 @@ void launch_bin(hipStream_t s, const int32_t *in, int64_t n_in, const int64_t *r
 
 // Hub vertices are split into segments of kHubSegment entries, one wavefront
 // each; a single block assigns segments with a block-wide exclusive scan.
-__global__ __launch_bounds__(1024) void hub_segments_kernel(const int64_t *rp, Worklists wl) {
-    __shared__ int64_t sc[1024];
-    __shared__ int64_t running_s;
-    const int tid = threadIdx.x;
+// Hub segments: one thread per hub vertex takes a contiguous range of
+// segment slots from the shared counter *n_seg (zeroed by the caller) and
+// writes its segments in row order; hubs may take their ranges in any order
+// (consumers only need each hub's segments contiguous and ascending).
+// Slots and per-hub records beyond the capacities are not written, but
+// *n_seg still counts every segment so the host can detect the overflow.
+__global__ __launch_bounds__(kBlock) void hub_segments_kernel(const int64_t *__restrict__ rp,
+                                                              Worklists wl) {
     const int64_t n_hubs = wl.count[3];
-    if (tid == 0) running_s = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < n_hubs; base += 1024) {
-        int64_t i = base + tid;
-        int32_t v = 0;
-        int64_t b = 0, d = 0, ns = 0;
-        if (i < n_hubs) {
-            v = wl.list[3][i];
-            b = rp[v];
-            d = rp[v + 1] - b;
-            ns = (d + kHubSegment - 1) / kHubSegment;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hubs;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = wl.list[3][i];
+        const int64_t b = rp[v];
+        const int64_t d = rp[v + 1] - b;
+        const int64_t ns = (d + kHubSegment - 1) / kHubSegment;
+        const int64_t first = atomicAdd(wl.n_seg, (int32_t)ns);
+        if (i >= wl.hub_capacity) continue;
+        for (int64_t k = 0; k < ns; ++k) {
+            const int64_t seg = first + k;
+            if (seg >= wl.seg_capacity) break;
+            wl.hub_seg_v[seg] = v;
+            wl.hub_seg_begin[seg] = b + k * kHubSegment;
+            wl.hub_seg_end[seg] = (k + 1) * kHubSegment < d ? b + (k + 1) * kHubSegment : b + d;
+            wl.hub_seg_slot[seg] = (int32_t)i;
         }
-        sc[tid] = ns;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int64_t t = tid >= off ? sc[tid - off] : 0;
-            __syncthreads();
-            sc[tid] += t;
-            __syncthreads();
-        }
-        int64_t first = running_s + sc[tid] - ns;
-        if (i < n_hubs && i < wl.hub_capacity) {
-            for (int64_t k = 0; k < ns; ++k) {
-                int64_t seg = first + k;
-                if (seg < wl.seg_capacity) {
-                    wl.hub_seg_v[seg] = v;
-                    wl.hub_seg_begin[seg] = b + k * kHubSegment;
-                    wl.hub_seg_end[seg] = (k + 1) * kHubSegment < d ? b + (k + 1) * kHubSegment : b + d;
-                    wl.hub_seg_slot[seg] = (int32_t)i;
-                }
-            }
-            wl.hub_nseg[i] = (int32_t)ns;
-            wl.hub_seg_first[i] = (int32_t)first;
-            wl.hub_cover[i] = 0;
-            wl.hub_ticket[i] = 0;
-            for (int c = 0; c < kMaxCount; ++c) wl.hub_count[i * kMaxCount + c] = 0;
-        }
-        __syncthreads();
-        if (tid == 1023) running_s += sc[1023];
-        __syncthreads();
+        wl.hub_nseg[i] = (int32_t)ns;
+        wl.hub_seg_first[i] = (int32_t)first;
+        wl.hub_cover[i] = 0;
+        wl.hub_ticket[i] = 0;
+        for (int c = 0; c < kMaxCount; ++c) wl.hub_count[i * kMaxCount + c] = 0;
     }
-    if (tid == 0) *wl.n_seg = (int32_t)running_s;
 }
 
 void launch_hub_segments(hipStream_t s, const int64_t *rp, Worklists &wl, int64_t) {
-    hipLaunchKernelGGL(hub_segments_kernel, dim3(1), dim3(1024), 0, s, rp, wl);
+    hipLaunchKernelGGL(hub_segments_kernel, dim3(256), dim3(kBlock), 0, s, rp, wl);
 }
 
 // ------------------------------------------------------------- LCC sweep
@@ -625,12 +609,53 @@ void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *o
 // Entry u->w is kept iff omega(w) meets the roles adjacent to omega(u): the
 // edge elimination of the LCC description (edges to eliminated neighbours
 // and to neighbours of non-adjacent roles are dropped).
+// Coarse filter of the vertices active when it was built: bit g of the
+// filter is set iff one of the vertices 8g .. 8g+7 had a role then.  Role
+// sets only shrink during a prune, so a clear bit proves omega[x] == 0 and
+// the compaction skips the gather of omega[x]; one bit per eight vertices
+// keeps the filter small enough (n/64 bytes) to stay in L2 while the role
+// sets of a large graph do not.  A null filter passes every vertex.
+constexpr int kFiltShift = 3;
+__device__ __forceinline__ bool may_be_active(const uint32_t *__restrict__ f, int32_t x) {
+    return !f || ((f[x >> (kFiltShift + 5)] >> ((x >> kFiltShift) & 31)) & 1u);
+}
+template <typename M>
+__device__ __forceinline__ uint64_t omega_filtered(const M *__restrict__ omega,
+                                                   const uint32_t *__restrict__ f, int32_t x) {
+    return may_be_active(f, x) ? (uint64_t)omega[x] : 0ull;
+}
+
+// One thread per vertex over ceil(n / 256) * 256 threads: a wavefront's
+// ballot of non-empty role sets (64 vertices) folds to 8 filter bits, one
+// byte of the filter, so every byte is written and no clearing is needed.
+template <typename M>
+__global__ __launch_bounds__(kBlock) void active_filter_kernel(int64_t n, const M *omega,
+                                                               uint8_t *filt) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t b = ballot64(v < n && omega[v] != 0);
+    if (lane_id() == 0) {
+        uint32_t byte = 0;
+        for (int g = 0; g < 8; ++g)
+            if ((b >> (8 * g)) & 0xFFull) byte |= 1u << g;
+        filt[v >> 6] = (uint8_t)byte;
+    }
+}
+
+template <typename M>
+void launch_active_filter(hipStream_t s, int64_t n, const M *omega, uint32_t *filt) {
+    const int64_t words = (n + 255) / 256;
+    if (words <= 0) return;
+    hipLaunchKernelGGL(active_filter_kernel<M>, dim3((unsigned)words), dim3(kBlock), 0, s, n,
+                       omega, reinterpret_cast<uint8_t *>(filt));
+}
+
 template <typename M, int G>
 __global__ __launch_bounds__(kBlock) void compact_count_group(const int64_t *__restrict__ rp,
                                                               const int32_t *__restrict__ col,
                                                               const M *__restrict__ omega,
                                                               const int32_t *__restrict__ list,
                                                               int64_t count, LccTable tab,
+                                                              const uint32_t *__restrict__ filt,
                                                               int64_t *deg_out) {
     const int sl = lane_id() & (G - 1);
     const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
@@ -651,9 +676,10 @@ __global__ __launch_bounds__(kBlock) void compact_count_group(const int64_t *__r
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) cc[u] = col[k + (int64_t)u * G];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) c += ((uint64_t)omega[cc[u]] & reach) != 0ull;
+            for (int u = 0; u < kUnroll; ++u)
+                c += (omega_filtered(omega, filt, cc[u]) & reach) != 0ull;
         }
-        for (; k < e; k += G) c += ((uint64_t)omega[col[k]] & reach) != 0ull;
+        for (; k < e; k += G) c += (omega_filtered(omega, filt, col[k]) & reach) != 0ull;
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, G);
@@ -669,7 +695,9 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
                                                             const int32_t *__restrict__ col,
                                                             const M *__restrict__ omega,
                                                             Worklists wl, int64_t n_seg,
-                                                            LccTable tab, int64_t *deg_out,
+                                                            LccTable tab,
+                                                            const uint32_t *__restrict__ filt,
+                                                            int64_t *deg_out,
                                                             int64_t *seg_count,
                                                             uint64_t *seg_bits) {
     const int lane = lane_id();
@@ -689,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
             for (int u = 0; u < kUnroll; ++u) cc[u] = col[k0 + (int64_t)u * kWave + lane];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t m = ballot64(((uint64_t)omega[cc[u]] & reach) != 0ull);
+                const uint64_t m = ballot64((omega_filtered(omega, filt, cc[u]) & reach) != 0ull);
                 if (lane == 0) bits[chunk + u] = m;
                 c += __popcll(m);
             }
@@ -697,7 +725,8 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
         }
         for (; k0 < e; k0 += kWave, ++chunk) {
             const int64_t k = k0 + lane;
-            const uint64_t m = ballot64(k < e && ((uint64_t)omega[col[k]] & reach) != 0ull);
+            const uint64_t m =
+                ballot64(k < e && (omega_filtered(omega, filt, col[k]) & reach) != 0ull);
             if (lane == 0) bits[chunk] = m;
             c += __popcll(m);
         }
@@ -711,8 +740,9 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
 template <typename M, int G>
 __global__ __launch_bounds__(kBlock) void compact_fill_group(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
-    const int32_t *__restrict__ list, int64_t count, LccTable tab, const int64_t *__restrict__ c_rp,
-    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off, int32_t *c_own) {
+    const int32_t *__restrict__ list, int64_t count, LccTable tab, const uint32_t *__restrict__ filt,
+    const int64_t *__restrict__ c_rp, const int32_t *__restrict__ base_off, int32_t *c_col,
+    int32_t *c_off, int32_t *c_own) {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
     const int sub_shift = lane & ~(G - 1);
@@ -742,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_group(
         int32_t x = 0;
         if (k < e) {
             x = col[k];
-            keep = ((uint64_t)omega[x] & reach) != 0ull;
+            keep = (omega_filtered(omega, filt, x) & reach) != 0ull;
         }
         const uint64_t m = ballot64(keep) & gmask;
         if (keep) {
@@ -760,7 +790,8 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const M *__restrict__ omega,
     Worklists wl, int64_t n_seg, LccTable tab, const int64_t *__restrict__ c_rp,
     const int64_t *__restrict__ seg_scan, const uint64_t *__restrict__ seg_bits,
-    const int32_t *__restrict__ base_off, int32_t *c_col, int32_t *c_off, int32_t *c_own) {
+    const int32_t *__restrict__ base_off, int32_t *__restrict__ c_col,
+    int32_t *__restrict__ c_off, int32_t *__restrict__ c_own) {
     const int lane = lane_id();
     const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (seg >= n_seg) return;
@@ -770,68 +801,77 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
     if (!reach) return;
     // offset of this segment in v's compacted row: kept entries of the
     // slot's earlier segments (exclusive scan over all segments)
-    int64_t pos = c_rp[v] + seg_scan[seg] - seg_scan[wl.hub_seg_first[slot]];
+    const int64_t pos = c_rp[v] + seg_scan[seg] - seg_scan[wl.hub_seg_first[slot]];
     const int64_t row0 = rp[v];
     const int64_t b = wl.hub_seg_begin[seg], e = wl.hub_seg_end[seg];
-    const uint64_t *bits = seg_bits + seg * (kHubSegment / kWave);
-    int chunk = 0;
-    for (int64_t base = b; base < e; base += kWave, ++chunk) {
-        const uint64_t m = bits[chunk];
-        if (!m) continue;
+    // lane c holds the keep ballot of chunk c (at most 64 chunks per
+    // segment) and the number of kept entries of the chunks before it, so
+    // the chunks are independent: no chain of dependent loads
+    const int nchunks = (int)((e - b + kWave - 1) / kWave);
+    const uint64_t mine = lane < nchunks ? seg_bits[seg * (kHubSegment / kWave) + lane] : 0ull;
+    int32_t before = __popcll(mine);
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t t = __shfl_up(before, off, kWave);
+        if (lane >= off) before += t;
+    }
+    before -= __popcll(mine);
+    for (uint64_t live = ballot64(mine != 0ull); live; live &= live - 1) {
+        const int chunk = __builtin_ctzll(live);
+        const uint64_t m = read_lane_u64(mine, chunk);
         if ((m >> lane) & 1ull) {
-            const int64_t k = base + lane;
-            const int64_t p = pos + __popcll(m & lanemask_lt());
+            const int64_t k = b + (int64_t)chunk * kWave + lane;
+            const int64_t p = pos + read_lane32(before, chunk) + __popcll(m & lanemask_lt());
             c_col[p] = col[k];
             c_off[p] = base_off ? base_off[k] : (int32_t)(k - row0);
             c_own[p] = v;
         }
-        pos += __popcll(m);
     }
 }
 
 template <typename M>
 void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                           const Worklists &wl, const int64_t *hc, int64_t n_seg,
-                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count,
-                          uint64_t *seg_bits) {
+                          const LccTable &tab, const uint32_t *filt, int64_t *deg_out,
+                          int64_t *seg_count, uint64_t *seg_bits) {
     if (hc[0] > 0)
         hipLaunchKernelGGL((compact_count_group<M, 4>),
                            dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           rp, col, omega, wl.list[0], hc[0], tab, deg_out);
+                           rp, col, omega, wl.list[0], hc[0], tab, filt, deg_out);
     if (hc[1] > 0)
         hipLaunchKernelGGL((compact_count_group<M, 16>),
                            dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[1], hc[1], tab, deg_out);
+                           s, rp, col, omega, wl.list[1], hc[1], tab, filt, deg_out);
     if (hc[2] > 0)
         hipLaunchKernelGGL((compact_count_group<M, 64>),
                            dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[2], hc[2], tab, deg_out);
+                           s, rp, col, omega, wl.list[2], hc[2], tab, filt, deg_out);
     if (n_seg > 0)
         hipLaunchKernelGGL((compact_count_hub<M>),
                            dim3((unsigned)((n_seg * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl, n_seg, tab, deg_out, seg_count, seg_bits);
+                           s, rp, col, omega, wl, n_seg, tab, filt, deg_out, seg_count, seg_bits);
 }
 
 template <typename M>
 void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                          const Worklists &wl, const int64_t *hc, int64_t n_seg,
-                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
-                         const uint64_t *seg_bits, const int32_t *base_off, int32_t *c_col,
-                         int32_t *c_off, int32_t *c_own) {
+                         const LccTable &tab, const uint32_t *filt, const int64_t *c_rp,
+                         const int64_t *seg_scan, const uint64_t *seg_bits,
+                         const int32_t *base_off, int32_t *c_col, int32_t *c_off,
+                         int32_t *c_own) {
     if (hc[0] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 4>),
                            dim3((unsigned)((hc[0] * 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           rp, col, omega, wl.list[0], hc[0], tab, c_rp, base_off, c_col, c_off,
+                           rp, col, omega, wl.list[0], hc[0], tab, filt, c_rp, base_off, c_col, c_off,
                            c_own);
     if (hc[1] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 16>),
                            dim3((unsigned)((hc[1] * 16 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[1], hc[1], tab, c_rp, base_off, c_col, c_off,
+                           s, rp, col, omega, wl.list[1], hc[1], tab, filt, c_rp, base_off, c_col, c_off,
                            c_own);
     if (hc[2] > 0)
         hipLaunchKernelGGL((compact_fill_group<M, 64>),
                            dim3((unsigned)((hc[2] * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, rp, col, omega, wl.list[2], hc[2], tab, c_rp, base_off, c_col, c_off,
+                           s, rp, col, omega, wl.list[2], hc[2], tab, filt, c_rp, base_off, c_col, c_off,
                            c_own);
     if (n_seg > 0)
         hipLaunchKernelGGL((compact_fill_hub<M>),
@@ -1013,10 +1053,13 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
                                       const LccTable &, int32_t *, bool);                         \
     template void launch_compact_count<M>(hipStream_t, const int64_t *, const int32_t *,           \
                                           const M *, const Worklists &, const int64_t *, int64_t, \
-                                          const LccTable &, int64_t *, int64_t *, uint64_t *);    \
+                                          const LccTable &, const uint32_t *, int64_t *,          \
+                                          int64_t *, uint64_t *);                                 \
+    template void launch_active_filter<M>(hipStream_t, int64_t, const M *, uint32_t *);          \
     template void launch_compact_fill<M>(hipStream_t, const int64_t *, const int32_t *, const M *, \
                                          const Worklists &, const int64_t *, int64_t,             \
-                                         const LccTable &, const int64_t *, const int64_t *,      \
+                                         const LccTable &, const uint32_t *, const int64_t *,     \
+                                         const int64_t *,                                         \
                                          const uint64_t *, const int32_t *, int32_t *, int32_t *,  \
                                          int32_t *);                                              \
     template void launch_widen<M>(hipStream_t, int64_t, const M *, uint64_t *);                  \

@@ -45,6 +45,13 @@ __device__ __forceinline__ uint64_t load_fresh(const M *p) {
     return (uint64_t)__atomic_load_n(p, __ATOMIC_RELAXED);
 }
 
+// A read that may be stale (workgroup scope: it may hit the CU's cache);
+// used only where a stale value costs redundant work, never correctness.
+template <typename M>
+__device__ __forceinline__ uint64_t load_hint(const M *p) {
+    return (uint64_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <typename M>
 __device__ __forceinline__ uint64_t reach_mask(uint64_t w, const LccTable &tab) {
     uint64_t r = 0;
@@ -321,10 +328,23 @@ __device__ void certify_roles(const SearchPlan *__restrict__ P, int32_t img_r, M
         atomic_or_elem<M>(sat, img_r, 1ull << lane);
 }
 
-// An edge is certified through one bit: that of its compacted entry from
-// the smaller to the larger vertex id.
+// An edge is certified through the bit of either of its two compacted
+// entries (certify_match uses the one from the smaller to the larger vertex
+// id; swaps use the entry whose position they already hold).  The word is
+// read first: most certifications repeat, and a stale read only costs a
+// redundant atomic.
+__device__ __forceinline__ void set_bit_once(uint64_t *bits, int64_t e) {
+    const uint64_t b = 1ull << (e & 63);
+    if (!(load_hint(bits + (e >> 6)) & b)) atomicOr((unsigned long long *)(bits + (e >> 6)), b);
+}
 __device__ __forceinline__ void set_entry(const SearchArgs &a, int64_t rl_index) {
-    set_bit(a.c_cert, a.rl_ent[rl_index]);
+    set_bit_once(a.c_cert, a.rl_ent[rl_index]);
+}
+
+// Role bit q of element x, set with the same read-first rule.
+template <typename M>
+__device__ __forceinline__ void certify_role(M *cert, int32_t x, int q) {
+    if (!((load_hint(cert + x) >> q) & 1ull)) atomic_or_elem<M>(cert, x, 1ull << q);
 }
 
 // Certify edge {u, w} where u holds role qu and w role qw in the match: the
@@ -428,7 +448,6 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
         }
         const int32_t s = read_lane32(lb_r, js), e = read_lane32(le_r, js);
         if (e - s > a.expand_max) continue;
-        const int32_t ys = read_lane32(img_r, js);
         {
             uint64_t h = mix64((uint64_t)q + 1ull);
             for (uint64_t m = nb; m; m &= m - 1)
@@ -492,32 +511,23 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             ec.valid += (unsigned long long)__popcll(ballot64(ok));
             if (a.wit_on) record_witness(a, P->vmask, img_r, ok, x, q, q, x);
             if (ok) {
-                atomic_or_elem<M>(cert, x, 1ull << q);
-                // the scanned entry ys -> x is at kk of ys's list
-                if (ys < x) set_entry(a, kk);
-                else certify_pair(a, x, q, ys, js);
+                certify_role<M>(cert, x, q);
+                // every edge at x is certified through its entry y -> x in
+                // y's list of role-q vertices: the scanned list holds it at
+                // kk, the tested lists at the positions found above
+                set_entry(a, kk);
                 for (int i = 0; i < nord; ++i) {
                     const int j = (int)((ordc >> (6 * i)) & 63ull);
-                    const int32_t y = read_lane32(img_r, j);
-                    if (y < x) {
-                        int64_t p = i == 0 ? p0 : (i == 1 ? p1 : (i == 2 ? p2 : -1));
-                        if (p < 0)
-                            p = find_sorted(rlc, read_lane32(lb_r, j), read_lane32(le_r, j), x);
-                        if (p >= 0) set_entry(a, p);
-                    } else {
-                        certify_pair(a, x, q, y, j);
-                    }
+                    int64_t p = i == 0 ? p0 : (i == 1 ? p1 : (i == 2 ? p2 : -1));
+                    if (p < 0)
+                        p = find_sorted(rlc, read_lane32(lb_r, j), read_lane32(le_r, j), x);
+                    if (p >= 0) set_entry(a, p);
                 }
                 for (uint64_t m = rest; m; m &= m - 1) {
                     const int j = __builtin_ctzll(m);
-                    const int32_t y = read_lane32(img_r, j);
-                    if (y < x) {
-                        const int64_t p =
-                            find_sorted(rlc, read_lane32(lb_r, j), read_lane32(le_r, j), x);
-                        if (p >= 0) set_entry(a, p);
-                    } else {
-                        certify_pair(a, x, q, y, j);
-                    }
+                    const int64_t p =
+                        find_sorted(rlc, read_lane32(lb_r, j), read_lane32(le_r, j), x);
+                    if (p >= 0) set_entry(a, p);
                 }
             }
         }
@@ -663,15 +673,16 @@ __device__ bool witness_swap(const SearchArgs &a, const LccTable &tab, uint64_t 
 
 // Candidate edges: entries a -> b (a < b) of the compacted subgraph whose
 // certified roles are adjacent in G0 and that no found match certified yet
-// (a certified edge has the bit of exactly this entry set); those a witness
-// swap certifies are certified here instead.  One thread per compacted
-// entry (c_own gives its row), so hub rows do not serialise on one
-// wavefront.
+// (neither the bit of this entry nor that of its reverse b -> a is set; the
+// reverse entry's index goes with the task, e_idx holding both); those a
+// witness swap certifies are certified here instead.  One thread per
+// compacted entry (c_own gives its row), so hub rows do not serialise on
+// one wavefront.
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
-    int64_t c_m, const int32_t *__restrict__ c_own, const int32_t *__restrict__ c_col,
-    const M *cert, LccTable tab, uint64_t *c_cert, int32_t *eu, int32_t *ew, int64_t *e_idx,
-    int32_t *n_out, int64_t cap, SearchArgs a) {
+    int64_t c_m, const int64_t *__restrict__ c_rp, const int32_t *__restrict__ c_own,
+    const int32_t *__restrict__ c_col, const M *cert, LccTable tab, uint64_t *c_cert, int32_t *eu,
+    int32_t *ew, int64_t *e_idx, int32_t *n_out, int64_t cap, SearchArgs a) {
     const int lane = lane_id();
     unsigned long long swapped = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -680,6 +691,7 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
         const int64_t k = base + threadIdx.x;
         bool p = false;
         int32_t u = 0, w = 0;
+        int64_t kr = -1;
         if (k < c_m) {
             u = c_own[k];
             w = c_col[k];
@@ -687,6 +699,11 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
                 const uint64_t cu = (uint64_t)cert[u];
                 const uint64_t cw = cu ? (uint64_t)cert[w] : 0ull;
                 p = cw != 0ull && (cw & reach_mask<M>(cu, tab)) != 0ull && !test_bit(c_cert, k);
+                // the edge may be certified through its reverse entry
+                if (p) {
+                    kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
+                    p = kr < 0 || !test_bit(c_cert, kr);
+                }
                 if (p && a.wit_on && witness_swap(a, tab, cu, cw, u, w)) {
                     set_bit(c_cert, k);
                     ++swapped;
@@ -704,7 +721,8 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
             if (o < cap) {
                 eu[o] = u;
                 ew[o] = w;
-                e_idx[o] = k;
+                e_idx[2 * o] = k;
+                e_idx[2 * o + 1] = kr;
             }
         }
     }
@@ -713,15 +731,15 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
 }
 
 template <typename M>
-void launch_edge_candidates(hipStream_t s, int64_t c_m, const int32_t *c_own,
-                            const int32_t *c_col, const M *cert, const LccTable &tab,
-                            uint64_t *c_cert, int32_t *eu, int32_t *ew, int64_t *e_idx,
-                            int32_t *n_out, int64_t cap, const SearchArgs &a) {
+void launch_edge_candidates(hipStream_t s, int64_t c_m, const int64_t *c_rp,
+                            const int32_t *c_own, const int32_t *c_col, const M *cert,
+                            const LccTable &tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
+                            int64_t *e_idx, int32_t *n_out, int64_t cap, const SearchArgs &a) {
     if (c_m <= 0) return;
     int64_t grid = (c_m + kSearchBlock - 1) / kSearchBlock;
     if (grid > 16384) grid = 16384;
     hipLaunchKernelGGL(edge_candidates_kernel<M>, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       c_m, c_own, c_col, cert, tab, c_cert, eu, ew, e_idx, n_out, cap, a);
+                       c_m, c_rp, c_own, c_col, cert, tab, c_cert, eu, ew, e_idx, n_out, cap, a);
 }
 
 template <typename M>
@@ -750,10 +768,15 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
         const int64_t t1 = t0 + a.task_chunk < n_edges ? t0 + a.task_chunk : n_edges;
         for (int64_t t = t0; t < t1; ++t) {
             const int32_t u = eu[t], w = ew[t];
-            const int64_t k = e_idx[t];
+            const int64_t k = e_idx[2 * t], kr = e_idx[2 * t + 1];
             const uint64_t cu = (uint64_t)om[u], cw = (uint64_t)om[w];
+            // the reverse entry's word is read even when kr < 0 (k's word
+            // again), so both loads are issued together
+            const int64_t kq = kr >= 0 ? kr : k;
             for (int i = 0; i < n_edge_plans; ++i) {
-                if ((load_fresh(a.c_cert + (k >> 6)) >> (k & 63)) & 1ull) break;
+                const uint64_t wk = load_fresh(a.c_cert + (k >> 6));
+                const uint64_t wq = load_fresh(a.c_cert + (kq >> 6));
+                if (((wk >> (k & 63)) | (wq >> (kq & 63))) & 1ull) break;
                 const SearchPlan *P = a.plans + edge_plan[i];
                 if (!((cu >> P->pin[0]) & 1ull) || !((cw >> P->pin[1]) & 1ull)) continue;
                 int32_t img = 0;
@@ -804,34 +827,33 @@ void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
                        e_idx, n_edges, omega, cert, edge_plan_dev, n_edge_plans, a);
 }
 
-// Output edge bits from certified compacted entries (each certified edge
-// holds the bit of its entry u -> w with u < w): both CSR entries of the
-// edge are set; the reverse entry is found in w's compacted row.  One
-// thread per 64-entry word of certificates (c_own gives each entry's row).
+// Output edge bits from certified compacted entries (a certified edge holds
+// the bit of one or both of its entries).  One thread per entry u -> w with
+// u < w (c_own gives its row): the reverse entry is found in w's compacted
+// row, and if either bit is set both CSR entries of the edge are set.
 __global__ __launch_bounds__(kSearchBlock) void edges_from_cert_kernel(
-    int64_t words, const int64_t *c_rp, const int32_t *c_col, const int32_t *c_own,
+    int64_t c_m, const int64_t *c_rp, const int32_t *c_col, const int32_t *c_own,
     const int32_t *c_off, const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
-    for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < words;
-         wi += (int64_t)gridDim.x * blockDim.x) {
-        for (uint64_t bits = c_cert[wi]; bits; bits &= bits - 1) {
-            const int64_t k = wi * 64 + __builtin_ctzll(bits);
-            const int32_t u = c_own[k], w = c_col[k];
-            set_bit(edge_bits, rp[u] + c_off[k]);
-            const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
-            if (kr >= 0) set_bit(edge_bits, rp[w] + c_off[kr]);
-        }
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < c_m;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = c_own[k], w = c_col[k];
+        if (u >= w) continue;
+        const bool fwd = test_bit(c_cert, k);
+        const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
+        if (!fwd && (kr < 0 || !test_bit(c_cert, kr))) continue;
+        set_bit(edge_bits, rp[u] + c_off[k]);
+        if (kr >= 0) set_bit(edge_bits, rp[w] + c_off[kr]);
     }
 }
 
 void launch_edges_from_cert(hipStream_t s, int64_t c_m, const int64_t *c_rp, const int32_t *c_col,
                             const int32_t *c_own, const int32_t *c_off, const int64_t *rp,
                             const uint64_t *c_cert, uint64_t *edge_bits) {
-    const int64_t words = (c_m + 63) / 64;
-    if (words <= 0) return;
-    int64_t grid = (words + kSearchBlock - 1) / kSearchBlock;
+    if (c_m <= 0) return;
+    int64_t grid = (c_m + kSearchBlock - 1) / kSearchBlock;
     if (grid > 16384) grid = 16384;
     hipLaunchKernelGGL(edges_from_cert_kernel, dim3((unsigned)grid), dim3(kSearchBlock), 0, s,
-                       words, c_rp, c_col, c_own, c_off, rp, c_cert, edge_bits);
+                       c_m, c_rp, c_col, c_own, c_off, rp, c_cert, edge_bits);
 }
 
 // Edge state implied by role sets (edge elimination rule): bit of entry
@@ -875,8 +897,9 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                                           const SearchArgs &, int);                               \
     template void launch_apply<M>(hipStream_t, const int32_t *, int64_t, M *, M *, uint64_t,      \
                                   int32_t *);                                                     \
-    template void launch_edge_candidates<M>(hipStream_t, int64_t, const int32_t *,                \
-                                            const int32_t *, const M *, const LccTable &,         \
+    template void launch_edge_candidates<M>(hipStream_t, int64_t, const int64_t *,                \
+                                            const int32_t *, const int32_t *, const M *,          \
+                                            const LccTable &,                                     \
                                             uint64_t *, int32_t *, int32_t *, int64_t *,          \
                                             int32_t *, int64_t, const SearchArgs &);              \
     template void launch_edge_search<M>(hipStream_t, const int32_t *, const int32_t *,            \

@@ -194,15 +194,20 @@ void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *o
 template <typename M>
 void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                           const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
-                          const LccTable &tab, int64_t *deg_out, int64_t *seg_count,
-                          uint64_t *seg_bits);
+                          const LccTable &tab, const uint32_t *filt, int64_t *deg_out,
+                          int64_t *seg_count, uint64_t *seg_bits);
+// Coarse filter of the active vertices (bit g: one of vertices 8g..8g+7
+// has a non-empty role set), ceil(n / 256) 32-bit words, fully written.
+template <typename M>
+void launch_active_filter(hipStream_t s, int64_t n, const M *omega, uint32_t *filt);
 void launch_exclusive_scan(hipStream_t s, const int64_t *in, int64_t *out, int64_t n,
                            int64_t *scratch, int64_t scratch_len);
 int64_t scan_scratch_len(int64_t n);
 template <typename M>
 void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                          const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
-                         const LccTable &tab, const int64_t *c_rp, const int64_t *seg_scan,
+                         const LccTable &tab, const uint32_t *filt, const int64_t *c_rp,
+                         const int64_t *seg_scan,
                          const uint64_t *seg_bits, const int32_t *base_off, int32_t *c_col,
                          int32_t *c_off, int32_t *c_own);
 
@@ -286,10 +291,10 @@ void launch_apply(hipStream_t s, const int32_t *tasks, int64_t n_tasks, M *omega
 // Candidates whose edge a recorded witness certifies by one vertex swap are
 // certified here instead of being listed (a.wit_on).
 template <typename M>
-void launch_edge_candidates(hipStream_t s, int64_t c_m, const int32_t *c_own,
-                            const int32_t *c_col, const M *cert, const LccTable &tab,
-                            uint64_t *c_cert, int32_t *eu, int32_t *ew, int64_t *e_idx,
-                            int32_t *n_out, int64_t cap, const SearchArgs &a);
+void launch_edge_candidates(hipStream_t s, int64_t c_m, const int64_t *c_rp,
+                            const int32_t *c_own, const int32_t *c_col, const M *cert,
+                            const LccTable &tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
+                            int64_t *e_idx, int32_t *n_out, int64_t cap, const SearchArgs &a);
 
 template <typename M>
 void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
