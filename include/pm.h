@@ -36,7 +36,10 @@
  *    once the edge searches use relisted roles), PM_RELIST=0 keeps the edge
  *    searches on the pre-search role lists, PM_EDGE_CHUNK=k sets the edge
  *    tasks a wavefront takes at once (default 16), PM_EDGE_STRIPES=s the
- *    number of stripes the edge task list is dealt in (default 64).  Read by pm_load_graph:
+ *    number of stripes the edge task list is dealt in (default 64),
+ *    PM_SPLIT_BUDGET=s the steps after which an edge-rooted search hands
+ *    its unexplored candidate ranges on (default 8192; 0 never).  These seed
+ *    the settings of pm_set_param.  Read by pm_load_graph:
  *    PM_NO_COUNT_INDEX=1 skips the neighbour-label count index (the first
  *    LCC sweep then gathers over the CSR).
  */
@@ -188,7 +191,8 @@ typedef struct {
                                       count index (else 0)                     */
     int64_t witness_edges;         /* candidate edges certified by moving one
                                       template vertex of a recorded match      */
-    int64_t reserved[1];
+    int64_t split_tasks;           /* unexplored ranges handed on by edge-rooted
+                                      searches that ran past their step budget */
 } pm_stats;
 
 /* Returns the message for the last error on this thread ("" if none). */
@@ -264,6 +268,9 @@ int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
      "edge_chunk"    k     edge tasks a wavefront takes at once (16)
      "edge_stripes"  s     stripes the edge task list is dealt in (64)
      "search_grid"   b     blocks of the persistent search kernels (8 per CU)
+     "split_budget"  s     steps after which an edge-rooted search hands its
+                           unexplored candidate ranges on to other
+                           wavefronts; 0: never (8192)
    The environment variables listed at the top seed these defaults when the
    context is created.  PM_ERR_INVALID_ARG for an unknown name or a value
    out of range. */

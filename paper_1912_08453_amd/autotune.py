@@ -28,6 +28,7 @@ def default_space(ctx) -> Dict[str, List[int]]:
         "witness": [0, 1],
         "relist": [0, 1],
         "search_grid": sorted({max(1, g // 2), g, 2 * g}),
+        "split_budget": [0, 2048, 8192, 32768],
     }
 
 

@@ -89,11 +89,11 @@ struct Scratch {
         coff2, cown2,
         segcnt, segscan, segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
-        actbits, ord, afilt;
+        actbits, ord, afilt, split[2];
     void release() {
         for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
                           &ccol, &coff, &cown, &crp2, &ccol2, &coff2, &cown2, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
-                          &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord, &afilt})
+                          &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord, &afilt, &split[0], &split[1]})
             b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
@@ -136,6 +136,7 @@ struct pm_ctx {
     int edge_chunk = 16;
     int relist = 1;
     int edge_stripes = 64;
+    int64_t split_budget = 8192;
     int64_t wall_khz = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
@@ -161,6 +162,7 @@ enum : int {
     C_TASK = 6,
     C_ACTIVE = 7,
     C_NOUT = 8,
+    C_SPLIT = 9,       // split tasks appended
     C_QUERIES_U64 = 16,   // byte offset 64: unsigned long long
     C_ENTRIES_U64 = 18,   // byte offset 72: unsigned long long
     C_TOTAL_BYTES = 256,      // bytes 128..207: query statistics [10]
@@ -422,6 +424,10 @@ struct Pruner {
         a.expand = 0;
         a.expand_max = c->expand_max;
         a.check_om = 0;
+        a.split_budget = 0;
+        a.split_out = nullptr;
+        a.split_n = nullptr;
+        a.split_cap = 0;
         return a;
     }
 
@@ -554,10 +560,42 @@ struct Pruner {
             while ((ne + chunk - 1) / chunk + c->edge_stripes + waves >= INT32_MAX) chunk *= 2;
             a.task_chunk = (int)chunk;
             a.stripes = c->edge_stripes;
+            if (c->split_budget > 0) {
+                // searches past the budget hand on their unexplored ranges,
+                // which later launches (double-buffered lists) search
+                for (DevBuf *b : {&w->split[0], &w->split[1]})
+                    b->ensure(sizeof(SplitTask) * (size_t)kSplitCap);
+                PM_HIP(hipMemsetAsync(ctr + C_SPLIT, 0, sizeof(int32_t), s));
+                a.split_budget = c->split_budget;
+                a.split_out = w->split[0].as<SplitTask>();
+                a.split_n = ctr + C_SPLIT;
+                a.split_cap = kSplitCap;
+            }
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
                                   w->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
                                   a, c->grid_search);
+            if (c->split_budget > 0) {
+                int cur = 0;
+                int64_t rounds = 0;
+                for (int64_t nt = read_ctr(C_SPLIT); nt > 0; nt = read_ctr(C_SPLIT)) {
+                    // every split task covers strictly less of its search
+                    // than the search that made it; this bound only guards
+                    // against a broken invariant
+                    if (++rounds > (int64_t)1 << 20)
+                        throw Error(PM_ERR_CAPACITY, "split searches did not finish");
+                    st.split_tasks += nt;
+                    const SplitTask *in = w->split[cur].as<SplitTask>();
+                    cur ^= 1;
+                    a.split_out = w->split[cur].as<SplitTask>();
+                    PM_HIP(hipMemsetAsync(ctr + C_SPLIT, 0, sizeof(int32_t), s));
+                    PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
+                    launch_split_search<M>(s, in, nt, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
+                                           w->eidx.as<int64_t>(), sat, sat,
+                                           w->edge_plan_ids.as<int32_t>(), a, c->grid_search);
+                }
+                a.split_budget = 0;
+            }
             d2h(s, &q1, queries, 1);
         }
         launch_edges_from_cert(s, c_m, c_rp, c_col, c_own, c_off, c->rp, c_cert, edge_out);
@@ -925,6 +963,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             if (rl) c->relist = atoi(rl);
             const char *es = getenv("PM_EDGE_STRIPES");
             if (es) c->edge_stripes = std::min(1 << 16, std::max(1, atoi(es)));
+            const char *sb = getenv("PM_SPLIT_BUDGET");
+            if (sb) c->split_budget = std::max(0LL, atoll(sb));
             const char *ec = getenv("PM_EDGE_CHUNK");
             if (ec) c->edge_chunk = std::min(1 << 16, std::max(1, atoi(ec)));
         } catch (...) {
@@ -1225,6 +1265,7 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
             total.expand_valid += st.expand_valid;
             total.first_sweep_bytes += st.first_sweep_bytes;
             total.witness_edges += st.witness_edges;
+            total.split_tasks += st.split_tasks;
             total.trace_entries += st.trace_entries;
         }
         PM_HIP(hipStreamSynchronize(c->stream));
@@ -1243,6 +1284,7 @@ int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
         else if (k == "edge_chunk" && value >= 1 && value <= (1 << 16)) c->edge_chunk = (int)value;
         else if (k == "edge_stripes" && value >= 1 && value <= (1 << 16)) c->edge_stripes = (int)value;
         else if (k == "search_grid" && value >= 1 && value <= (1 << 16)) c->grid_search = (int)value;
+        else if (k == "split_budget" && value >= 0) c->split_budget = value;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter or value out of range: " + k);
     });
 }
@@ -1258,6 +1300,7 @@ int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
         else if (k == "edge_chunk") *value = c->edge_chunk;
         else if (k == "edge_stripes") *value = c->edge_stripes;
         else if (k == "search_grid") *value = c->grid_search;
+        else if (k == "split_budget") *value = c->split_budget;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter: " + k);
     });
 }

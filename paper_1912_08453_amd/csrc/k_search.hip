@@ -213,20 +213,40 @@ __device__ __forceinline__ int64_t rl_end(const SearchArgs &a, int32_t y, int q)
 // partial match from exact list lengths): every open template vertex's lane
 // reads its list lengths under the placed neighbours in parallel and a
 // wavefront minimum picks the shortest (ties: lowest vertex, then lowest
-// neighbour).  Returns true with img_r (and rb_r) holding a full embedding.
+// neighbour).
+//
+// With rt set the search is a split task: rt's prefix vertices are placed
+// as well and the first level scans rt's candidate range.  With `split`,
+// every a.split_budget steps (chunk scans and descents) the search hands
+// the untried candidates of its shallowest open level -- the largest
+// subtrees left -- to other wavefronts as split tasks (the vertices placed
+// above that level, and a piece of its candidate range) and carries on
+// with the rest.  The handed-on pieces and what the search keeps partition
+// its tree, so together they find a match if there is one; a miss here
+// only says that this search's own part holds none.
+enum { kSearchMiss = 0, kSearchFound = 1 };
+
 template <typename M>
-__device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
-                           const M *__restrict__ om, int32_t v0, int32_t v1, int32_t &img_r,
-                           int32_t &rb_r) {
+__device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
+                          const M *__restrict__ om, int32_t v0, int32_t v1,
+                          const SplitTask *__restrict__ rt, int64_t task, int plan, bool split,
+                          int32_t &img_r, int32_t &rb_r) {
     const int lane = lane_id();
     const int k = P->k;
     const int npin = P->npin;
     const uint64_t vmask = P->vmask;
     const int p0 = P->pin[0], p1 = P->pin[1];
     img_r = lane == p0 ? v0 : ((npin == 2 && lane == p1) ? v1 : -1);
-    rb_r = img_r >= 0 ? a.rl_pos[img_r] * a.n0 : 0;
     uint64_t placed = (1ull << p0) | (npin == 2 ? (1ull << p1) : 0ull);
-    if (k <= npin) return true;
+    const int rt_np = rt ? (int)rt->np : 0;
+    for (int i = 0; i < rt_np; ++i) {
+        const int q = rt->pq[i];
+        if (lane == q) img_r = rt->px[i];
+        placed |= 1ull << q;
+    }
+    rb_r = img_r >= 0 ? a.rl_pos[img_r] * a.n0 : 0;
+    const int base_lvl = npin + rt_np;
+    if (!rt && k <= npin) return kSearchFound;
     const int32_t *__restrict__ rlc = a.rl_col;
     const int64_t *__restrict__ rlo = a.rl_off;
     // role-list positions fit in 32 bits (checked when the lists are built)
@@ -266,15 +286,99 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
             par_r = bj;
         }
     };
-    int lvl = npin;
-    select(lvl);
+
+    // Hand on the rest of the shallowest level l < lvl that still has
+    // candidates to try, cut into up to kSplitPieces tasks of near-equal
+    // length, and drop it from this search.  Only levels above the current
+    // one qualify: their placed candidate's subtree stays here, so every
+    // handed-on task covers strictly less than this search (a search never
+    // hands on all of its own work, and the rounds of split tasks end).
+    // Returns false if nothing could be handed on for want of room.
+    auto hand_off = [&](int lvl) -> bool {
+        int l = base_lvl;
+        int32_t r0 = 0, len = 0;
+        for (; l < lvl; ++l) {
+            const uint64_t pend = read_lane_u64(pend_r, l);
+            r0 = pend ? read_lane32(base_r, l) + __builtin_ctzll(pend) : read_lane32(cur_r, l);
+            len = read_lane32(end_r, l) - r0;
+            if (len > 0) break;
+        }
+        if (l >= lvl) return true;      // nothing left above the current level
+        const int np = rt_np + (l - base_lvl);
+        if (np > kSplitPrefix) return false;
+        const int pieces = len < kSplitPieces ? len : kSplitPieces;
+        int32_t first = -1;
+        if (lane == 0) {
+            int32_t old = __hip_atomic_load(a.split_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (;;) {
+                if ((int64_t)old + pieces > a.split_cap) break;
+                const int32_t prev = atomicCAS(a.split_n, old, old + pieces);
+                if (prev == old) {
+                    first = old;
+                    break;
+                }
+                old = prev;
+            }
+        }
+        first = __shfl(first, 0);
+        if (first < 0) return false;
+        const int qv = read_lane32(pv_r, l), pv = read_lane32(par_r, l);
+        // lane i < np: prefix vertex i (the task's own prefix, then the
+        // vertices placed at levels base_lvl .. l-1) and its image
+        int pq_l = 0;
+        if (lane < rt_np) pq_l = rt->pq[lane];
+        for (int i = rt_np; i < np; ++i) {
+            const int q = read_lane32(pv_r, base_lvl + (i - rt_np));
+            if (lane == i) pq_l = q;
+        }
+        const int32_t px_l = __shfl(img_r, pq_l);
+        for (int p = 0; p < pieces; ++p) {
+            SplitTask *o = a.split_out + first + p;
+            if (lane == 0) {
+                o->t = task;
+                o->r0 = r0 + (int32_t)((int64_t)len * p / pieces);
+                o->r1 = r0 + (int32_t)((int64_t)len * (p + 1) / pieces);
+                o->plan = (int16_t)plan;
+                o->q = (uint8_t)qv;
+                o->par = (uint8_t)pv;
+                o->np = (uint8_t)np;
+            }
+            if (lane < np) {
+                o->pq[lane] = (uint8_t)pq_l;
+                o->px[lane] = px_l;
+            }
+        }
+        if (lane == l) {
+            pend_r = 0;
+            cur_r = end_r;
+        }
+        return true;
+    };
+
+    int lvl = base_lvl;
+    if (rt) {
+        if (lane == lvl) {
+            cur_r = rt->r0;
+            end_r = rt->r1;
+            pend_r = 0;
+            pv_r = rt->q;
+            par_r = rt->par;
+        }
+    } else {
+        select(lvl);
+    }
+    int64_t steps = 0;
     for (;;) {
+        if (split && ++steps > a.split_budget) {
+            steps = 0;
+            split = hand_off(lvl);
+        }
         uint64_t pend = read_lane_u64(pend_r, lvl);
         if (pend == 0) {
             const int32_t cur = read_lane32(cur_r, lvl);
             const int32_t end = read_lane32(end_r, lvl);
             if (cur >= end) {
-                if (--lvl < npin) return false;
+                if (--lvl < base_lvl) return kSearchMiss;
                 placed &= ~(1ull << read_lane32(pv_r, lvl));
                 continue;
             }
@@ -314,7 +418,7 @@ __device__ bool dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P
             rb_r = a.rl_pos[x] * a.n0;
         }
         placed |= 1ull << q;
-        if (lvl == k - 1) return true;
+        if (lvl == k - 1) return kSearchFound;
         ++lvl;
         select(lvl);
     }
@@ -559,7 +663,8 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                 int32_t rb = 0;
                 ++queries;
                 const uint64_t c0 = wall_clock64();
-                const bool found = dfs_search<M>(a, P, om, v, -1, img, rb);
+                const bool found =
+                    dfs_search<M>(a, P, om, v, -1, nullptr, 0, 0, false, img, rb) == kSearchFound;
                 const uint64_t c1 = wall_clock64();
                 if (found) {
                     ++npos;
@@ -742,13 +847,74 @@ void launch_edge_candidates(hipStream_t s, int64_t c_m, const int64_t *c_rp,
                        c_m, c_rp, c_own, c_col, cert, tab, c_cert, eu, ew, e_idx, n_out, cap, a);
 }
 
+// One edge-rooted query (plan P with its pins at u, w; or split task rt):
+// a found match certifies its roles and edges and its single-vertex swaps.
+struct QueryCount {
+    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0, tcert = 0, texp = 0;
+    ExpandCount ec;
+};
+
+template <typename M>
+__device__ bool edge_query(const SearchArgs &a, const SearchPlan *__restrict__ P,
+                           const M *__restrict__ om, M *cert, int32_t u, int32_t w,
+                           const SplitTask *rt, int64_t t, int plan, QueryCount &qc) {
+    int32_t img = 0;
+    int32_t rb = 0;
+    ++qc.queries;
+    const uint64_t c0 = wall_clock64();
+    const int r = dfs_search<M>(a, P, om, u, w, rt, t, plan, a.split_budget > 0, img, rb);
+    const uint64_t c1 = wall_clock64();
+    if (r != kSearchFound) {
+        qc.tneg += c1 - c0;
+        return false;
+    }
+    ++qc.npos;
+    qc.tpos += c1 - c0;
+    certify_match<M>(a, P, img, cert);
+    if (a.expand) {
+        const uint64_t c2 = wall_clock64();
+        expand_match<M>(a, P, img, rb, om, cert, qc.ec);
+        qc.texp += wall_clock64() - c2;
+    }
+    qc.tcert += wall_clock64() - c1;
+    return true;
+}
+
+__device__ __forceinline__ void flush_edge_stats(const SearchArgs &a, const QueryCount &qc) {
+    if (lane_id() == 0 && qc.queries) {
+        atomicAdd(a.n_queries, qc.queries);
+        if (a.qstats) {
+            atomicAdd(a.qstats + 4, qc.npos);
+            atomicAdd(a.qstats + 5, qc.queries - qc.npos);
+            atomicAdd(a.qstats + 6, qc.tpos);
+            atomicAdd(a.qstats + 7, qc.tneg);
+            atomicAdd(a.qstats + 9, qc.tcert);
+            atomicAdd(a.qstats + 10, qc.texp);
+            atomicAdd(a.qstats + 11, qc.ec.scans);
+            atomicAdd(a.qstats + 12, qc.ec.cands);
+            atomicAdd(a.qstats + 13, qc.ec.valid);
+        }
+    }
+}
+
+// Is the edge of task t certified (through either of its entries)?  The
+// reverse entry's word is read even when there is none (k's word again),
+// so both loads are issued together.
+__device__ __forceinline__ bool edge_certified(const SearchArgs &a, const int64_t *e_idx,
+                                               int64_t t) {
+    const int64_t k = e_idx[2 * t], kr = e_idx[2 * t + 1];
+    const int64_t kq = kr >= 0 ? kr : k;
+    const uint64_t wk = load_fresh(a.c_cert + (k >> 6));
+    const uint64_t wq = load_fresh(a.c_cert + (kq >> 6));
+    return ((wk >> (k & 63)) | (wq >> (kq & 63))) & 1ull;
+}
+
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
     const int32_t *eu, const int32_t *ew, const int64_t *e_idx, int64_t n_edges, const M *om,
     M *cert, const int32_t *edge_plan, int32_t n_edge_plans, SearchArgs a) {
     const int lane = lane_id();
-    unsigned long long queries = 0, npos = 0, tpos = 0, tneg = 0, tcert = 0, texp = 0;
-    ExpandCount ec;
+    QueryCount qc;
     // chunks of task_chunk consecutive candidates are handed out in striped
     // order: chunk c is the (c / S)-th chunk of stripe c % S, so waves
     // running at the same time work on distant parts of the list (other
@@ -768,53 +934,18 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
         const int64_t t1 = t0 + a.task_chunk < n_edges ? t0 + a.task_chunk : n_edges;
         for (int64_t t = t0; t < t1; ++t) {
             const int32_t u = eu[t], w = ew[t];
-            const int64_t k = e_idx[2 * t], kr = e_idx[2 * t + 1];
             const uint64_t cu = (uint64_t)om[u], cw = (uint64_t)om[w];
-            // the reverse entry's word is read even when kr < 0 (k's word
-            // again), so both loads are issued together
-            const int64_t kq = kr >= 0 ? kr : k;
+            // a plan whose search splits is finished by its split tasks;
+            // the next plans are tried meanwhile
             for (int i = 0; i < n_edge_plans; ++i) {
-                const uint64_t wk = load_fresh(a.c_cert + (k >> 6));
-                const uint64_t wq = load_fresh(a.c_cert + (kq >> 6));
-                if (((wk >> (k & 63)) | (wq >> (kq & 63))) & 1ull) break;
+                if (edge_certified(a, e_idx, t)) break;
                 const SearchPlan *P = a.plans + edge_plan[i];
                 if (!((cu >> P->pin[0]) & 1ull) || !((cw >> P->pin[1]) & 1ull)) continue;
-                int32_t img = 0;
-                int32_t rb = 0;
-                ++queries;
-                const uint64_t c0 = wall_clock64();
-                const bool found = dfs_search<M>(a, P, om, u, w, img, rb);
-                const uint64_t c1 = wall_clock64();
-                if (found) {
-                    ++npos;
-                    tpos += c1 - c0;
-                    certify_match<M>(a, P, img, cert);
-                    if (a.expand) {
-                        const uint64_t c2 = wall_clock64();
-                        expand_match<M>(a, P, img, rb, om, cert, ec);
-                        texp += wall_clock64() - c2;
-                    }
-                    tcert += wall_clock64() - c1;
-                    break;
-                }
-                tneg += c1 - c0;
+                if (edge_query<M>(a, P, om, cert, u, w, nullptr, t, i, qc)) break;
             }
         }
     }
-    if (lane == 0 && queries) {
-        atomicAdd(a.n_queries, queries);
-        if (a.qstats) {
-            atomicAdd(a.qstats + 4, npos);
-            atomicAdd(a.qstats + 5, queries - npos);
-            atomicAdd(a.qstats + 6, tpos);
-            atomicAdd(a.qstats + 7, tneg);
-            atomicAdd(a.qstats + 9, tcert);
-            atomicAdd(a.qstats + 10, texp);
-            atomicAdd(a.qstats + 11, ec.scans);
-            atomicAdd(a.qstats + 12, ec.cands);
-            atomicAdd(a.qstats + 13, ec.valid);
-        }
-    }
+    flush_edge_stats(a, qc);
 }
 
 template <typename M>
@@ -825,6 +956,40 @@ void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
     if (n_edges <= 0) return;
     hipLaunchKernelGGL(edge_search_kernel<M>, dim3(grid), dim3(kSearchBlock), 0, s, eu, ew,
                        e_idx, n_edges, omega, cert, edge_plan_dev, n_edge_plans, a);
+}
+
+// Split tasks, one per fetch (each is a long search); skipped once their
+// edge is certified.
+template <typename M>
+__global__ __launch_bounds__(kSearchBlock) void split_search_kernel(
+    const SplitTask *tasks, int64_t n_tasks, const int32_t *eu, const int32_t *ew,
+    const int64_t *e_idx, const M *om, M *cert, const int32_t *edge_plan, SearchArgs a) {
+    const int lane = lane_id();
+    QueryCount qc;
+    for (;;) {
+        int i = 0;
+        if (lane == 0) i = atomicAdd(a.task_counter, 1);
+        i = __shfl(i, 0);
+        if ((int64_t)i >= n_tasks) break;
+        const SplitTask *rt = tasks + i;
+        const int64_t t = rt->t;
+        if (edge_certified(a, e_idx, t)) continue;
+        const int plan = rt->plan;
+        edge_query<M>(a, a.plans + edge_plan[plan], om, cert, eu[t], ew[t], rt, t, plan, qc);
+    }
+    flush_edge_stats(a, qc);
+}
+
+template <typename M>
+void launch_split_search(hipStream_t s, const SplitTask *tasks, int64_t n_tasks,
+                         const int32_t *eu, const int32_t *ew, const int64_t *e_idx,
+                         const M *omega, M *cert, const int32_t *edge_plan, const SearchArgs &a,
+                         int grid) {
+    if (n_tasks <= 0) return;
+    int64_t g = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
+    if (g > grid) g = grid;
+    hipLaunchKernelGGL(split_search_kernel<M>, dim3((unsigned)g), dim3(kSearchBlock), 0, s, tasks,
+                       n_tasks, eu, ew, e_idx, omega, cert, edge_plan, a);
 }
 
 // Output edge bits from certified compacted entries (a certified edge holds
@@ -902,6 +1067,10 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                                             const LccTable &,                                     \
                                             uint64_t *, int32_t *, int32_t *, int64_t *,          \
                                             int32_t *, int64_t, const SearchArgs &);              \
+    template void launch_split_search<M>(hipStream_t, const SplitTask *, int64_t,                 \
+                                         const int32_t *, const int32_t *, const int64_t *,       \
+                                         const M *, M *, const int32_t *, const SearchArgs &,     \
+                                         int);                                                    \
     template void launch_edge_search<M>(hipStream_t, const int32_t *, const int32_t *,            \
                                         const int64_t *, int64_t, const M *, M *,                 \
                                         const int32_t *, int32_t, const SearchArgs &, int);       \

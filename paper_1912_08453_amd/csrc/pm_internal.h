@@ -213,6 +213,23 @@ void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, c
 
 // Vertex-rooted searches.  mode 0: NLCC (certify head roles into sat);
 // mode 1: exact step (certify all roles into sat and edges into edge_bits).
+// An unexplored part of an edge-rooted search, handed on when the search
+// ran past its step budget: the plan's pins at the task's edge, np further
+// placed vertices (pq[i] at image px[i]), and the candidates still to try
+// for template vertex q at the next level, rl_col[r0, r1) (the role-q list
+// of the image of the placed vertex par).
+constexpr int kSplitPrefix = 8;
+constexpr int kSplitPieces = 16;         // tasks per handed-on range, at most
+constexpr int64_t kSplitCap = 1 << 18;   // split tasks per launch (two lists)
+struct alignas(16) SplitTask {
+    int64_t t;                      // edge task index (eu / ew / e_idx)
+    int32_t r0, r1;
+    int16_t plan;                   // index into the edge plan list
+    uint8_t q, par, np;
+    uint8_t pq[kSplitPrefix];
+    int32_t px[kSplitPrefix];
+};
+
 struct SearchArgs {
     const int64_t *c_rp;
     const int32_t *c_col;
@@ -255,6 +272,13 @@ struct SearchArgs {
     int64_t expand_max;             // longest list a swap scan reads
     int32_t check_om;               // candidates' role sets may have shrunk since
                                     // the role lists were built: test them
+    // splitting of long edge-rooted searches: one that takes more than
+    // split_budget steps (0: never) stops and appends its unexplored
+    // candidate ranges to split_out (capacity split_cap, count *split_n)
+    int64_t split_budget;
+    SplitTask *split_out;
+    int32_t *split_n;
+    int64_t split_cap;
 };
 
 // Role lists of the vertices in tasks over the compacted subgraph: pass 1
@@ -295,6 +319,14 @@ void launch_edge_candidates(hipStream_t s, int64_t c_m, const int64_t *c_rp,
                             const int32_t *c_own, const int32_t *c_col, const M *cert,
                             const LccTable &tab, uint64_t *c_cert, int32_t *eu, int32_t *ew,
                             int64_t *e_idx, int32_t *n_out, int64_t cap, const SearchArgs &a);
+
+// Searches of split tasks (edge-rooted searches handed on by a search
+// that ran past its step budget); they may split again into a.split_out.
+template <typename M>
+void launch_split_search(hipStream_t s, const SplitTask *tasks, int64_t n_tasks,
+                         const int32_t *eu, const int32_t *ew, const int64_t *e_idx,
+                         const M *omega, M *cert, const int32_t *edge_plan, const SearchArgs &a,
+                         int grid);
 
 template <typename M>
 void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,

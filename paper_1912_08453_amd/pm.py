@@ -84,8 +84,8 @@ class pm_stats(ctypes.Structure):
                 ("lcc_sweeps", "constraints", "first_sweep_vertices", "first_sweep_entries",
                  "candidate_entries", "vertex_queries", "edge_queries", "result_vertices",
                  "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries", "expand_scans",
-                 "expand_candidates", "expand_valid", "first_sweep_bytes", "witness_edges")] + \
-               [("reserved", ctypes.c_int64 * 1)]
+                 "expand_candidates", "expand_valid", "first_sweep_bytes", "witness_edges",
+                 "split_tasks")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -281,7 +281,7 @@ class PM:
 
     # ------------------------------------------------------------ tuning
     TUNING = ("expand", "expand_max", "witness", "relist", "edge_chunk", "edge_stripes",
-              "search_grid")
+              "search_grid", "split_budget")
 
     def set_param(self, name: str, value: int) -> None:
         _check(self.lib, self.lib.pm_set_param(self.h, name.encode(), int(value)))

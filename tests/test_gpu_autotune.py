@@ -50,10 +50,13 @@ def _ctx(pmmod, torch_dev, g, ts):
 
 
 def _check(pmmod, ctx, tid, refs, what):
+    splits = 0
     for i, ref in enumerate(refs):
-        role, edge, _ = ctx.prune(tid + i)
+        role, edge, st = ctx.prune(tid + i)
         assert np.array_equal(pmmod.to_u64(role[0]), ref.role_mask), f"{what}: template {i} roles"
         assert np.array_equal(pmmod.to_u64(edge[0]), ref.edge_bits), f"{what}: template {i} edges"
+        splits += st["split_tasks"]
+    return splits
 
 
 def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
@@ -62,12 +65,13 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
     p = ctx.params()
     assert p["expand"] == 1 and p["witness"] == 0 and p["relist"] == 1
     assert p["edge_chunk"] == 16 and p["edge_stripes"] == 64 and p["expand_max"] == 4096
-    assert p["search_grid"] >= 256
+    assert p["search_grid"] >= 256 and p["split_budget"] == 8192
     for k, v in (("edge_chunk", 3), ("edge_stripes", 5), ("expand_max", -1), ("search_grid", 9),
                  ("witness", 1), ("relist", 0), ("expand", 0)):
         ctx.set_param(k, v)
         assert ctx.get_param(k) == v
-    for k, v in (("edge_chunk", 0), ("edge_stripes", 1 << 17), ("search_grid", 0), ("nope", 1)):
+    for k, v in (("edge_chunk", 0), ("edge_stripes", 1 << 17), ("search_grid", 0),
+                 ("split_budget", -1), ("nope", 1)):
         with pytest.raises(pmmod.PMError):
             ctx.set_param(k, v)
     with pytest.raises(pmmod.PMError):
@@ -78,14 +82,20 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
 @pytest.mark.parametrize("setting", [
     {"search_grid": 1}, {"search_grid": 7, "edge_chunk": 1, "edge_stripes": 3},
     {"expand": 0, "relist": 0, "search_grid": 4096},
-    {"witness": 1, "expand_max": 8, "edge_chunk": 64, "edge_stripes": 1024}])
+    {"witness": 1, "expand_max": 8, "edge_chunk": 64, "edge_stripes": 1024},
+    {"split_budget": 1}, {"split_budget": 2, "search_grid": 3}, {"split_budget": 0}])
 def test_extreme_settings_keep_the_complete_set(pmmod, torch_dev, case, setting):
     g, ts, refs = case
     ctx, tid = _ctx(pmmod, torch_dev, g, ts)
     for k, v in setting.items():
         ctx.set_param(k, v)
     log(f"settings {ctx.params()}")
-    _check(pmmod, ctx, tid, refs, str(setting))
+    splits = _check(pmmod, ctx, tid, refs, str(setting))
+    log(f"split tasks {splits}")
+    if setting.get("split_budget") == 1:
+        assert splits > 0, "a one-step budget must split searches"
+    if setting.get("split_budget") == 0:
+        assert splits == 0
     ctx.close()
 
 

@@ -285,12 +285,16 @@ def test_count_index_unaligned_labels_and_gather_path_agree(pmmod, torch_dev, mo
 
 @pytest.mark.parametrize("env", [{"PM_RELIST": "0"}, {"PM_WITNESS": "1"}, {"PM_EXPAND": "0"},
                                  {"PM_EXPAND_MAX": "32"}, {"PM_EDGE_CHUNK": "1"},
-                                 {"PM_EDGE_STRIPES": "1"}, {"PM_EDGE_STRIPES": "7"}])
+                                 {"PM_EDGE_STRIPES": "1"}, {"PM_EDGE_STRIPES": "7"},
+                                 {"PM_SPLIT_BUDGET": "0"}, {"PM_SPLIT_BUDGET": "1"},
+                                 {"PM_SPLIT_BUDGET": "5", "PM_EDGE_CHUNK": "1"}])
 def test_exact_step_switches_give_the_same_result(pmmod, torch_dev, monkeypatch, env):
     """The exact step's optional savings (role lists rebuilt from the exact
-    roles, witness swaps, swap scans, their length cap, task chunking) only
-    change how much work is done: the complete set equals the oracle's with
-    each one switched off or changed."""
+    roles, witness swaps, swap scans, their length cap, task chunking,
+    splitting of long searches) only change how much work is done: the
+    complete set equals the oracle's with each one switched off or changed
+    (a split budget of one step splits nearly every search, down to the
+    deepest level, and fills the split lists)."""
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     rp, col = I.rmat_csr(14, seed=91)

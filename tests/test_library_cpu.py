@@ -128,7 +128,7 @@ int main(void) {
     F(pm_options, reserved);
     F(pm_trace_entry, roles_before); F(pm_trace_entry, ms); F(pm_trace_entry, score);
     F(pm_trace_entry, predicted); F(pm_trace_entry, features);
-    F(pm_stats, lcc_sweeps); F(pm_stats, trace_entries); F(pm_stats, reserved);
+    F(pm_stats, lcc_sweeps); F(pm_stats, trace_entries); F(pm_stats, split_tasks);
     return 0;
 }
 ''')
