@@ -38,7 +38,8 @@
  *    tasks a wavefront takes at once (default 16), PM_EDGE_STRIPES=s the
  *    number of stripes the edge task list is dealt in (default 64),
  *    PM_SPLIT_BUDGET=s the steps after which an edge-rooted search hands
- *    its unexplored candidate ranges on (default 8192; 0 never).  These seed
+ *    its unexplored candidate ranges on (default 8192; 0 never),
+ *    PM_EDGE_TAIL=k the trailing edge tasks dealt singly (default 0).  These seed
  *    the settings of pm_set_param.  Read by pm_load_graph:
  *    PM_NO_COUNT_INDEX=1 skips the neighbour-label count index (the first
  *    LCC sweep then gathers over the CSR).
@@ -270,7 +271,9 @@ int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
      "search_grid"   b     blocks of the persistent search kernels (8 per CU)
      "split_budget"  s     steps after which an edge-rooted search hands its
                            unexplored candidate ranges on to other
-                           wavefronts; 0: never (8192)
+                           wavefronts; 0: never (8192; four times more in
+                           each later round of split tasks)
+     "edge_tail"     k     trailing edge tasks dealt one at a time (0)
    The environment variables listed at the top seed these defaults when the
    context is created.  PM_ERR_INVALID_ARG for an unknown name or a value
    out of range. */

@@ -137,6 +137,7 @@ struct pm_ctx {
     int relist = 1;
     int edge_stripes = 64;
     int64_t split_budget = 8192;
+    int64_t edge_tail = 0;
     int64_t wall_khz = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
@@ -413,6 +414,7 @@ struct Pruner {
         a.task_counter = ctr + C_TASK;
         a.task_chunk = 4;
         a.stripes = 1;
+        a.tail_single = 0;
         a.n_queries = queries;
         a.c_cert = nullptr;
         a.exp_seen = nullptr;
@@ -557,9 +559,12 @@ struct Pruner {
             // every chunk and every wave's final fetch
             int64_t chunk = c->edge_chunk;
             const int64_t waves = (int64_t)c->grid_search * 4;
-            while ((ne + chunk - 1) / chunk + c->edge_stripes + waves >= INT32_MAX) chunk *= 2;
+            const int64_t tail = std::min<int64_t>(c->edge_tail, std::min<int64_t>(ne, 1 << 24));
+            while ((ne + chunk - 1) / chunk + tail + c->edge_stripes + waves >= INT32_MAX)
+                chunk *= 2;
             a.task_chunk = (int)chunk;
             a.stripes = c->edge_stripes;
+            a.tail_single = tail;
             if (c->split_budget > 0) {
                 // searches past the budget hand on their unexplored ranges,
                 // which later launches (double-buffered lists) search
@@ -585,6 +590,10 @@ struct Pruner {
                     if (++rounds > (int64_t)1 << 20)
                         throw Error(PM_ERR_CAPACITY, "split searches did not finish");
                     st.split_tasks += nt;
+                    // split tasks of later rounds are parts of searches
+                    // already cut: a budget four times larger per round
+                    // keeps them from being cut into ever smaller pieces
+                    a.split_budget = std::min<int64_t>(a.split_budget * 4, (int64_t)1 << 40);
                     const SplitTask *in = w->split[cur].as<SplitTask>();
                     cur ^= 1;
                     a.split_out = w->split[cur].as<SplitTask>();
@@ -965,6 +974,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             if (es) c->edge_stripes = std::min(1 << 16, std::max(1, atoi(es)));
             const char *sb = getenv("PM_SPLIT_BUDGET");
             if (sb) c->split_budget = std::max(0LL, atoll(sb));
+            const char *et = getenv("PM_EDGE_TAIL");
+            if (et) c->edge_tail = std::max(0LL, atoll(et));
             const char *ec = getenv("PM_EDGE_CHUNK");
             if (ec) c->edge_chunk = std::min(1 << 16, std::max(1, atoi(ec)));
         } catch (...) {
@@ -1285,6 +1296,7 @@ int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
         else if (k == "edge_stripes" && value >= 1 && value <= (1 << 16)) c->edge_stripes = (int)value;
         else if (k == "search_grid" && value >= 1 && value <= (1 << 16)) c->grid_search = (int)value;
         else if (k == "split_budget" && value >= 0) c->split_budget = value;
+        else if (k == "edge_tail" && value >= 0) c->edge_tail = value;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter or value out of range: " + k);
     });
 }
@@ -1301,6 +1313,7 @@ int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
         else if (k == "edge_stripes") *value = c->edge_stripes;
         else if (k == "search_grid") *value = c->grid_search;
         else if (k == "split_budget") *value = c->split_budget;
+        else if (k == "edge_tail") *value = c->edge_tail;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter: " + k);
     });
 }

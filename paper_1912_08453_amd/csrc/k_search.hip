@@ -919,19 +919,28 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
     // order: chunk c is the (c / S)-th chunk of stripe c % S, so waves
     // running at the same time work on distant parts of the list (other
     // vertices) and later chunks of a vertex find more of its edges already
-    // certified
-    const int64_t n_chunks = (n_edges + a.task_chunk - 1) / a.task_chunk;
+    // certified.  The last tail_single candidates follow one at a time, so
+    // the waves finish close together.
+    const int64_t n_single = a.tail_single < n_edges ? a.tail_single : n_edges;
+    const int64_t n_head = n_edges - n_single;
+    const int64_t n_chunks = (n_head + a.task_chunk - 1) / a.task_chunk;
     const int64_t S = a.stripes > 1 ? a.stripes : 1;
     const int64_t R = (n_chunks + S - 1) / S;
     for (;;) {
         int c = 0;
         if (lane == 0) c = atomicAdd(a.task_counter, 1);
         c = __shfl(c, 0);
-        if ((int64_t)c >= S * R) break;
-        const int64_t pc = ((int64_t)c % S) * R + (int64_t)c / S;
-        if (pc >= n_chunks) continue;
-        const int64_t t0 = pc * a.task_chunk;
-        const int64_t t1 = t0 + a.task_chunk < n_edges ? t0 + a.task_chunk : n_edges;
+        int64_t t0, t1;
+        if ((int64_t)c < S * R) {
+            const int64_t pc = ((int64_t)c % S) * R + (int64_t)c / S;
+            if (pc >= n_chunks) continue;
+            t0 = pc * a.task_chunk;
+            t1 = t0 + a.task_chunk < n_head ? t0 + a.task_chunk : n_head;
+        } else {
+            t0 = n_head + ((int64_t)c - S * R);
+            if (t0 >= n_edges) break;
+            t1 = t0 + 1;
+        }
         for (int64_t t = t0; t < t1; ++t) {
             const int32_t u = eu[t], w = ew[t];
             const uint64_t cu = (uint64_t)om[u], cw = (uint64_t)om[w];

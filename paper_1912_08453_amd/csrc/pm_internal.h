@@ -251,6 +251,7 @@ struct SearchArgs {
     int32_t *task_counter;
     int32_t task_chunk;             // consecutive tasks a wavefront takes per atomic
     int32_t stripes;                // edge searches: chunk order striped S ways
+    int64_t tail_single;            // edge searches: trailing tasks dealt one at a time
     unsigned long long *n_queries;
     // exact step: certified edges of the compacted subgraph (bit k = entry k
     // = u -> w with u < w), the table of swap scans
