@@ -45,12 +45,6 @@ __device__ __forceinline__ uint64_t load_fresh(const M *p) {
     return (uint64_t)__atomic_load_n(p, __ATOMIC_RELAXED);
 }
 
-// A read that may be stale (workgroup scope: it may hit the CU's cache);
-// used only where a stale value costs redundant work, never correctness.
-template <typename M>
-__device__ __forceinline__ uint64_t load_hint(const M *p) {
-    return (uint64_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
 template <typename M>
 __device__ __forceinline__ uint64_t reach_mask(uint64_t w, const LccTable &tab) {
@@ -434,21 +428,16 @@ __device__ void certify_roles(const SearchPlan *__restrict__ P, int32_t img_r, M
 
 // An edge is certified through the bit of either of its two compacted
 // entries (certify_match uses the one from the smaller to the larger vertex
-// id; swaps use the entry whose position they already hold).  The word is
-// read first: most certifications repeat, and a stale read only costs a
-// redundant atomic.
-__device__ __forceinline__ void set_bit_once(uint64_t *bits, int64_t e) {
-    const uint64_t b = 1ull << (e & 63);
-    if (!(load_hint(bits + (e >> 6)) & b)) atomicOr((unsigned long long *)(bits + (e >> 6)), b);
-}
+// id; swaps use the entry whose position they already hold).  Plain atomics
+// without a return value: the wavefront does not wait for them (reading the
+// word first to skip repeats measured slower).
 __device__ __forceinline__ void set_entry(const SearchArgs &a, int64_t rl_index) {
-    set_bit_once(a.c_cert, a.rl_ent[rl_index]);
+    set_bit(a.c_cert, a.rl_ent[rl_index]);
 }
 
-// Role bit q of element x, set with the same read-first rule.
 template <typename M>
 __device__ __forceinline__ void certify_role(M *cert, int32_t x, int q) {
-    if (!((load_hint(cert + x) >> q) & 1ull)) atomic_or_elem<M>(cert, x, 1ull << q);
+    atomic_or_elem<M>(cert, x, 1ull << q);
 }
 
 // Certify edge {u, w} where u holds role qu and w role qw in the match: the
