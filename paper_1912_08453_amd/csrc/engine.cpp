@@ -138,6 +138,8 @@ struct pm_ctx {
     int edge_stripes = 64;
     int64_t split_budget = 8192;
     int64_t edge_tail = 0;
+    int exp_log2 = kExpSeenLog2;
+    int64_t split_cap = kSplitCap;
     int64_t wall_khz = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
@@ -487,18 +489,18 @@ struct Pruner {
         unsigned long long q0 = 0, q1 = 0;
         const int64_t cwords = (c_m + 63) / 64;
         w->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
-        w->expseen.ensure(sizeof(uint64_t) << kExpSeenLog2);
+        w->expseen.ensure(sizeof(uint64_t) << c->exp_log2);
         uint64_t *c_cert = w->ccert.as<uint64_t>();
         role_lists();
         launch_fill_u64(s, c_cert, cwords, 0ull);
-        launch_fill_u64(s, w->expseen.as<uint64_t>(), 1ll << kExpSeenLog2, 0ull);
+        launch_fill_u64(s, w->expseen.as<uint64_t>(), 1ll << c->exp_log2, 0ull);
         PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 16, s));
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
         SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
         a.c_cert = c_cert;
         a.exp_seen = w->expseen.as<unsigned long long>();
-        a.exp_log2 = kExpSeenLog2;
+        a.exp_log2 = c->exp_log2;
         // witnesses of certified (vertex, role) pairs, for single-swap
         // certification of candidate edges (small templates only)
         const int64_t wit_words = nA * (int64_t)T.n0 * T.n0;
@@ -569,12 +571,12 @@ struct Pruner {
                 // searches past the budget hand on their unexplored ranges,
                 // which later launches (double-buffered lists) search
                 for (DevBuf *b : {&w->split[0], &w->split[1]})
-                    b->ensure(sizeof(SplitTask) * (size_t)kSplitCap);
+                    b->ensure(sizeof(SplitTask) * (size_t)c->split_cap);
                 PM_HIP(hipMemsetAsync(ctr + C_SPLIT, 0, sizeof(int32_t), s));
                 a.split_budget = c->split_budget;
                 a.split_out = w->split[0].as<SplitTask>();
                 a.split_n = ctr + C_SPLIT;
-                a.split_cap = kSplitCap;
+                a.split_cap = c->split_cap;
             }
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
@@ -976,6 +978,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             if (sb) c->split_budget = std::max(0LL, atoll(sb));
             const char *et = getenv("PM_EDGE_TAIL");
             if (et) c->edge_tail = std::max(0LL, atoll(et));
+            const char *xt = getenv("PM_EXPAND_TABLE_LOG2");
+            if (xt) c->exp_log2 = std::min(30, std::max(10, atoi(xt)));
             const char *ec = getenv("PM_EDGE_CHUNK");
             if (ec) c->edge_chunk = std::min(1 << 16, std::max(1, atoi(ec)));
         } catch (...) {
@@ -1297,6 +1301,8 @@ int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
         else if (k == "search_grid" && value >= 1 && value <= (1 << 16)) c->grid_search = (int)value;
         else if (k == "split_budget" && value >= 0) c->split_budget = value;
         else if (k == "edge_tail" && value >= 0) c->edge_tail = value;
+        else if (k == "expand_table_log2" && value >= 10 && value <= 30) c->exp_log2 = (int)value;
+        else if (k == "split_capacity" && value >= 1 && value <= ((int64_t)1 << 28)) c->split_cap = value;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter or value out of range: " + k);
     });
 }
@@ -1314,6 +1320,8 @@ int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
         else if (k == "search_grid") *value = c->grid_search;
         else if (k == "split_budget") *value = c->split_budget;
         else if (k == "edge_tail") *value = c->edge_tail;
+        else if (k == "expand_table_log2") *value = c->exp_log2;
+        else if (k == "split_capacity") *value = c->split_cap;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter: " + k);
     });
 }

@@ -19,7 +19,7 @@ constexpr int kBinSmallMaxDeg = 8;   // 4 lanes per vertex
 constexpr int kBinMidMaxDeg = 64;    // 16 lanes per vertex
 constexpr int kBinWaveMaxDeg = 4096; // one wavefront per vertex
 constexpr int kHubSegment = 4096;    // entries per wavefront for larger vertices
-constexpr int kExpSeenLog2 = 22;     // slots of the swap-scan table (32 MiB)
+constexpr int kExpSeenLog2 = 22;     // default slots of the swap-scan table (32 MiB)
 constexpr int kNumBins = 4;          // small, mid, wave, hub
 
 // Local-rule tables of one template (LCC algorithm; distinct-count rule of
@@ -220,7 +220,7 @@ void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, c
 // of the image of the placed vertex par).
 constexpr int kSplitPrefix = 8;
 constexpr int kSplitPieces = 16;         // tasks per handed-on range, at most
-constexpr int64_t kSplitCap = 1 << 18;   // split tasks per launch (two lists)
+constexpr int64_t kSplitCap = 1 << 18;   // default split tasks per launch (two lists)
 struct alignas(16) SplitTask {
     int64_t t;                      // edge task index (eu / ew / e_idx)
     int32_t r0, r1;

@@ -71,7 +71,8 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
         ctx.set_param(k, v)
         assert ctx.get_param(k) == v
     for k, v in (("edge_chunk", 0), ("edge_stripes", 1 << 17), ("search_grid", 0),
-                 ("split_budget", -1), ("nope", 1)):
+                 ("split_budget", -1), ("split_capacity", 0), ("expand_table_log2", 31),
+                 ("nope", 1)):
         with pytest.raises(pmmod.PMError):
             ctx.set_param(k, v)
     with pytest.raises(pmmod.PMError):
@@ -83,7 +84,8 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
     {"search_grid": 1}, {"search_grid": 7, "edge_chunk": 1, "edge_stripes": 3},
     {"expand": 0, "relist": 0, "search_grid": 4096},
     {"witness": 1, "expand_max": 8, "edge_chunk": 64, "edge_stripes": 1024},
-    {"split_budget": 1}, {"split_budget": 2, "search_grid": 3}, {"split_budget": 0}])
+    {"split_budget": 1}, {"split_budget": 2, "search_grid": 3}, {"split_budget": 0},
+    {"split_budget": 1, "split_capacity": 20}, {"expand_table_log2": 10}])
 def test_extreme_settings_keep_the_complete_set(pmmod, torch_dev, case, setting):
     g, ts, refs = case
     ctx, tid = _ctx(pmmod, torch_dev, g, ts)

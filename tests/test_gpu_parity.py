@@ -161,9 +161,12 @@ def test_given_orders_same_final_output(pmmod, torch_dev, seed):
     ctx.close()
 
 
+@pytest.mark.parametrize("split_budget", [8192, 1])
 @pytest.mark.parametrize("n0", [10, 20, 40])
-def test_wider_role_masks(pmmod, torch_dev, n0):
-    """Templates of 10/20/40 vertices exercise 16/32/64-bit role masks."""
+def test_wider_role_masks(pmmod, torch_dev, n0, split_budget):
+    """Templates of 10/20/40 vertices exercise 16/32/64-bit role masks; with
+    a one-step split budget the searches hand work on at every step, up to
+    the prefix limit of a split task (deeper levels then stay unsplit)."""
     rng = np.random.Generator(np.random.Philox(n0))
     nl = n0 // 2 + 1
     g = I.random_graph(400, 0.05, nl, n0)
@@ -171,6 +174,7 @@ def test_wider_role_masks(pmmod, torch_dev, n0):
     labels = [q % nl for q in range(n0)]
     t = I.Template(labels, edges)
     ctx = load(pmmod, torch_dev, g)
+    ctx.set_param("split_budget", split_budget)
     tid = ctx.load_templates([t])
     compare(pmmod, ctx, tid, g, t, stop_after=0, what=f"n0={n0} lcc")
     compare(pmmod, ctx, tid, g, t, what=f"n0={n0} full")
