@@ -40,7 +40,8 @@
  *    PM_SPLIT_BUDGET=s the steps after which an edge-rooted search hands
  *    its unexplored candidate ranges on (default 8192; 0 never),
  *    PM_EDGE_TAIL=k the trailing edge tasks dealt singly (default 0),
- *    PM_EXPAND_TABLE_LOG2=t the swap-scan table size (default 22).  These seed
+ *    PM_EXPAND_TABLE_LOG2=t the swap-scan table size (default 22),
+ *    PM_READ_FIRST=1 reads certificate words before setting them.  These seed
  *    the settings of pm_set_param.  Read by pm_load_graph:
  *    PM_NO_COUNT_INDEX=1 skips the neighbour-label count index (the first
  *    LCC sweep then gathers over the CSR).
@@ -278,6 +279,7 @@ int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
      "expand_table_log2" t log2 of the slots of the swap-scan table (22)
      "split_capacity" c    split tasks one launch may hand on; a search
                            that finds no room carries on unsplit (2^18)
+     "read_first"    1/0   read certificate words before setting them (0)
    The environment variables listed at the top seed these defaults when the
    context is created.  PM_ERR_INVALID_ARG for an unknown name or a value
    out of range. */

@@ -30,6 +30,7 @@ def default_space(ctx) -> Dict[str, List[int]]:
         "search_grid": sorted({max(1, g // 2), g, 2 * g}),
         "split_budget": [0, 2048, 8192, 32768],
         "edge_tail": [0, 16384, 65536],
+        "read_first": [0, 1],
     }
 
 

@@ -140,6 +140,7 @@ struct pm_ctx {
     int64_t edge_tail = 0;
     int exp_log2 = kExpSeenLog2;
     int64_t split_cap = kSplitCap;
+    int read_first = 0;
     int64_t wall_khz = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
@@ -429,6 +430,7 @@ struct Pruner {
         a.expand_max = c->expand_max;
         a.check_om = 0;
         a.split_budget = 0;
+        a.read_first = c->read_first;
         a.split_out = nullptr;
         a.split_n = nullptr;
         a.split_cap = 0;
@@ -980,6 +982,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             if (et) c->edge_tail = std::max(0LL, atoll(et));
             const char *xt = getenv("PM_EXPAND_TABLE_LOG2");
             if (xt) c->exp_log2 = std::min(30, std::max(10, atoi(xt)));
+            const char *rf = getenv("PM_READ_FIRST");
+            if (rf) c->read_first = atoi(rf) ? 1 : 0;
             const char *ec = getenv("PM_EDGE_CHUNK");
             if (ec) c->edge_chunk = std::min(1 << 16, std::max(1, atoi(ec)));
         } catch (...) {
@@ -1303,6 +1307,7 @@ int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
         else if (k == "edge_tail" && value >= 0) c->edge_tail = value;
         else if (k == "expand_table_log2" && value >= 10 && value <= 30) c->exp_log2 = (int)value;
         else if (k == "split_capacity" && value >= 1 && value <= ((int64_t)1 << 28)) c->split_cap = value;
+        else if (k == "read_first") c->read_first = value ? 1 : 0;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter or value out of range: " + k);
     });
 }
@@ -1322,6 +1327,7 @@ int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
         else if (k == "edge_tail") *value = c->edge_tail;
         else if (k == "expand_table_log2") *value = c->exp_log2;
         else if (k == "split_capacity") *value = c->split_cap;
+        else if (k == "read_first") *value = c->read_first;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter: " + k);
     });
 }

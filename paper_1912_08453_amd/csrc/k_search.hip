@@ -428,15 +428,25 @@ __device__ void certify_roles(const SearchPlan *__restrict__ P, int32_t img_r, M
 
 // An edge is certified through the bit of either of its two compacted
 // entries (certify_match uses the one from the smaller to the larger vertex
-// id; swaps use the entry whose position they already hold).  Plain atomics
-// without a return value: the wavefront does not wait for them (reading the
-// word first to skip repeats measured slower).
+// id; swaps use the entry whose position they already hold).  By default a
+// plain atomic without a return value, which the wavefront does not wait
+// for; with a.read_first the word is read first (workgroup scope, may be
+// stale: a stale read only costs a redundant atomic) and the atomic skipped
+// when the bit is already set -- fewer atomics, but a load to wait for.
+template <typename M>
+__device__ __forceinline__ uint64_t load_hint(const M *p) {
+    return (uint64_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ void set_entry(const SearchArgs &a, int64_t rl_index) {
-    set_bit(a.c_cert, a.rl_ent[rl_index]);
+    const int64_t e = a.rl_ent[rl_index];
+    if (a.read_first && ((load_hint(a.c_cert + (e >> 6)) >> (e & 63)) & 1ull)) return;
+    set_bit(a.c_cert, e);
 }
 
 template <typename M>
-__device__ __forceinline__ void certify_role(M *cert, int32_t x, int q) {
+__device__ __forceinline__ void certify_role(const SearchArgs &a, M *cert, int32_t x, int q) {
+    if (a.read_first && ((load_hint(cert + x) >> q) & 1ull)) return;
     atomic_or_elem<M>(cert, x, 1ull << q);
 }
 
@@ -604,7 +614,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             ec.valid += (unsigned long long)__popcll(ballot64(ok));
             if (a.wit_on) record_witness(a, P->vmask, img_r, ok, x, q, q, x);
             if (ok) {
-                certify_role<M>(cert, x, q);
+                certify_role<M>(a, cert, x, q);
                 // every edge at x is certified through its entry y -> x in
                 // y's list of role-q vertices: the scanned list holds it at
                 // kk, the tested lists at the positions found above

@@ -277,6 +277,7 @@ struct SearchArgs {
     // split_budget steps (0: never) stops and appends its unexplored
     // candidate ranges to split_out (capacity split_cap, count *split_n)
     int64_t split_budget;
+    int32_t read_first;             // read certificate words before setting them
     SplitTask *split_out;
     int32_t *split_n;
     int64_t split_cap;

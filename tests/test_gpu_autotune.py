@@ -85,7 +85,8 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
     {"expand": 0, "relist": 0, "search_grid": 4096},
     {"witness": 1, "expand_max": 8, "edge_chunk": 64, "edge_stripes": 1024},
     {"split_budget": 1}, {"split_budget": 2, "search_grid": 3}, {"split_budget": 0},
-    {"split_budget": 1, "split_capacity": 20}, {"expand_table_log2": 10}])
+    {"split_budget": 1, "split_capacity": 20}, {"expand_table_log2": 10},
+    {"read_first": 1, "witness": 1}])
 def test_extreme_settings_keep_the_complete_set(pmmod, torch_dev, case, setting):
     g, ts, refs = case
     ctx, tid = _ctx(pmmod, torch_dev, g, ts)
