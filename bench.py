@@ -45,7 +45,9 @@ def main():
                          "one call per template vs concurrent streams), learned (64 multi-cycle "
                          "templates, fixed vs learned constraint order), autotune (coordinate "
                          "search of the tuning settings on the timed template; the timed "
-                         "steps above use the defaults); '' for none")
+                         "steps above use the defaults), explore (opt-in: exploratory search "
+                         "from the 6-clique on the timed template's labels, relaxed level "
+                         "by level until a variant matches); '' for none")
     ap.add_argument("--batch-streams", type=int, default=4)
     ap.add_argument("--workload", default="tri-square-s22", choices=["tri-square-s22", "theta8-s26"],
                     help="tri-square-s22: one template at scale 22 (default); theta8-s26: scale-26 base template "
@@ -161,6 +163,10 @@ def main():
     if "autotune" in legs:
         tuned = autotune_leg(ctx, tid, role, edge)
         log(f"autotune: {json.dumps(tuned)}")
+    explored = None
+    if "explore" in legs:
+        explored = explore_leg(ctx, tmpl)
+        log(f"explore: {json.dumps(explored)}")
     if "batched" in legs:
         batched = batched_leg(ctx, g, args.batch_streams)
         log(f"batched: {json.dumps(batched)}")
@@ -202,6 +208,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "autotune": tuned,
+        "explore": explored,
         "learned_order": learned,
     }
     print(json.dumps(out), flush=True)
@@ -315,6 +322,25 @@ def exploratory(args, scale=26, graph_seed=26, template_seed=0):
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def explore_leg(ctx, tmpl, max_deletions=4):
+    """Exploratory search (the paper's 6-clique scenario): the complete
+    graph on the timed template's vertex labels, relaxed level by level
+    (connected variants, one per isomorphism class) until a variant has a
+    match; per-level variant counts, matches and wall time."""
+    from paper_1912_08453_amd import explore
+    n0 = len(tmpl.labels)
+    clique = [(a, b) for a in range(n0) for b in range(a + 1, n0)]
+    t0 = time.perf_counter()
+    res = explore.explore(ctx, tmpl.labels, clique, max_deletions=max_deletions, log=log)
+    total = 1e3 * (time.perf_counter() - t0)
+    out = {"workload": f"K{n0} on labels {list(tmpl.labels)}, up to {max_deletions} edges "
+                       f"removed", "levels": res.levels, "stop_level": res.level,
+           "total_ms": round(total, 1)}
+    if res.level >= 0:
+        out["union_vertices"] = int((res.role_union != 0).sum().item())
+    return out
 
 
 def autotune_leg(ctx, tid, role, edge):
