@@ -28,7 +28,10 @@
 // (vertex, role) pair, giving the exact role sets; then from every candidate
 // edge not yet covered by a found match, giving the exact edge set.  Every
 // match found certifies all its roles and edges, and every single-vertex
-// swap of it that is again a match.
+// swap of it that is again a match.  An edge-rooted search that runs long
+// hands the untried candidates of its shallowest open level to other
+// wavefronts (split tasks, searched by the next launch), so one hard query
+// does not hold the GPU while a single wavefront works on it.
 #include "device_util.h"
 #include "pm_internal.h"
 
