@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <atomic>
 #include <cstdio>
 #include <cstdlib>
@@ -1222,6 +1223,18 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
         if (nw == 1) {
             for (int32_t i = 0; i < count; ++i) run_one(c->scratch[0].get(), i);
         } else {
+            // the templates likely to take longest go first (more
+            // independent cycles, then more edges and vertices), so the
+            // long ones overlap each other and the short ones fill in at
+            // the end instead of one long template running alone
+            std::vector<int32_t> deal((size_t)count);
+            for (int32_t i = 0; i < count; ++i) deal[(size_t)i] = i;
+            auto cost = [&](int32_t i) {
+                const CompiledTemplate &T = *c->templates[(size_t)(first_id + i)];
+                return std::make_tuple(T.m0 - T.n0 + 1, T.m0, T.n0);
+            };
+            std::stable_sort(deal.begin(), deal.end(),
+                             [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
             std::atomic<int32_t> next{0};
             std::vector<std::string> errs((size_t)nw);
             std::vector<int> codes((size_t)nw, PM_OK);
@@ -1231,9 +1244,9 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
                     try {
                         PM_HIP(hipSetDevice(c->device));
                         for (;;) {
-                            int32_t i = next.fetch_add(1);
-                            if (i >= count) break;
-                            run_one(c->scratch[(size_t)k].get(), i);
+                            const int32_t j = next.fetch_add(1);
+                            if (j >= count) break;
+                            run_one(c->scratch[(size_t)k].get(), deal[(size_t)j]);
                         }
                         PM_HIP(hipStreamSynchronize(c->scratch[(size_t)k]->stream));
                     } catch (const Error &e) {
