@@ -67,6 +67,7 @@ extern "C" {
 #define PM_ERR_OOM         (-7)   /* device memory exhausted                */
 #define PM_ERR_NOT_FOUND   (-8)   /* unknown template id                    */
 #define PM_ERR_MODEL       (-9)   /* no ordering model loaded, or bad one   */
+#define PM_ERR_WORKSPACE  (-10)   /* caller workspace too small or misaligned */
 
 /* ---- limits -------------------------------------------------------------- */
 #define PM_MAX_TEMPLATE_VERTICES 64   /* role masks are 64-bit              */
@@ -116,6 +117,28 @@ typedef struct {
 #define PM_MLP_OUTPUTS  2
 #define PM_MLP_PARAMS   5122
 
+/* Pruning modes (pm_options.mode). */
+#define PM_MODE_FULL      0   /* complete set of the template                */
+#define PM_MODE_CANDIDATE 1   /* candidate set of the interactive incremental
+                                 search: local constraints only, with the rule
+                                 relaxed so that the result holds the complete
+                                 set of EVERY connected template obtained from
+                                 this one by deleting edges (role q of v stays
+                                 while some neighbour of v holds a role
+                                 adjacent to q in G0).  Outputs omega and the
+                                 edge state it implies; no non-local
+                                 constraint and no final search run.          */
+
+/* Ablations of the paper's design decisions (pm_options.ablate bits), for
+   measurement only: the output does not change. */
+#define PM_ABLATE_EDGE_ELIMINATION 1u  /* the candidate subgraph keeps every
+                                          entry of an active vertex's row
+                                          (only vertex elimination prunes)   */
+#define PM_ABLATE_WORK_AGGREGATION 2u  /* a found embedding certifies only the
+                                          query it answers (its root role, or
+                                          its root edge); no single-vertex
+                                          swap expansion                     */
+
 /* One step of the constraint loop, recorded when options.trace is set. */
 typedef struct {
     int32_t constraint;            /* generation index; -1: the learned loop
@@ -153,6 +176,30 @@ typedef struct {
     pm_trace_entry *trace;         /* host array or NULL; count must be 1.
                                       stats.trace_entries receives the number
                                       written (at most trace_cap)            */
+    int32_t mode;                  /* PM_MODE_FULL or PM_MODE_CANDIDATE      */
+    uint32_t ablate;               /* PM_ABLATE_* bits                       */
+    const uint64_t *init_state;    /* device uint64[count][n] or NULL: role
+                                      masks known to hold the complete set of
+                                      each template (an exported state, a
+                                      candidate set, the complete set of a
+                                      template this one adds edges to); the
+                                      prune starts from omega0(v) AND
+                                      init_state[v].  A state that is not a
+                                      superset of the complete set gives a
+                                      wrong (too small) result.              */
+    uint64_t skip_mask;            /* with init_state: non-local constraints
+                                      (bit = generation index) already applied
+                                      to that state; they are not checked
+                                      again and count towards stop_after     */
+    const uint64_t *known_roles;   /* device uint64[count][n] or NULL: roles
+                                      known to belong to the complete set
+                                      (the complete set of a template this one
+                                      deletes edges from); the final search
+                                      takes them as certified.  Must be a
+                                      subset of the complete set.             */
+    const uint64_t *known_edges;   /* device uint64[count][ceil(m/64)] or
+                                      NULL: edge bits known to belong to the
+                                      complete set (same conditions)          */
     int32_t reserved[4];
 } pm_options;
 
@@ -196,6 +243,12 @@ typedef struct {
                                       template vertex of a recorded match      */
     int64_t split_tasks;           /* unexplored ranges handed on by edge-rooted
                                       searches that ran past their step budget */
+    uint64_t done_mask;            /* non-local constraints applied to the
+                                      final state (bit = generation index),
+                                      including options.skip_mask; OR over the
+                                      templates when count > 1               */
+    int64_t workspace_bytes;       /* peak device scratch of one template's
+                                      prune (largest over the templates)      */
 } pm_stats;
 
 /* Returns the message for the last error on this thread ("" if none). */
@@ -312,6 +365,88 @@ int pm_mlp_grad(pm_ctx *ctx, const float *w, const float *x, const float *t, int
    the loss before each step, or NULL. */
 int pm_mlp_train(pm_ctx *ctx, float *w, const float *x, const float *t, int64_t N,
                  int32_t steps, float lr, float *loss_history);
+
+/* ---- pruning state: export and resume --------------------------------------
+   The whole pruning state is the role-set array omega (the edge state is
+   derived from it: an entry is active iff its ends hold roles adjacent in
+   G0) plus the set of non-local constraints already applied.  Any state
+   that holds the complete set is a valid starting point, which is what
+   lets the paper's checkpoint-and-resume (load balancing subsection) and
+   its incremental searches restart from a saved solution or candidate set. */
+
+/* Run template `id` through its first LCC fixpoint and the first
+   stop_after non-local constraints (in the order opt selects; opt may be
+   NULL), then write omega widened to uint64 into state (device uint64[n],
+   caller-owned) and the applied constraints (bit = generation index) into
+   *done_mask (host).  stop_after < 0 applies every constraint; the final
+   search does not run. */
+int pm_export_state(pm_ctx *ctx, int32_t id, int32_t stop_after, const pm_options *opt,
+                    uint64_t *state, uint64_t *done_mask);
+
+/* Resume template `id` from an exported state: omega starts at
+   omega0 AND state (device uint64[n]), the constraints in done_mask are not
+   checked again, and the prune continues as pm_prune does (LCC fixpoint,
+   the remaining constraints, the final search; opt->stop_after counts the
+   skipped constraints too).  The state must hold the complete set (any
+   state pm_export_state wrote for this template and graph does).  Outputs
+   as pm_prune; opt->init_state and opt->skip_mask are ignored. */
+int pm_import_state(pm_ctx *ctx, int32_t id, const uint64_t *state, uint64_t done_mask,
+                    uint64_t *role_mask, uint64_t *edge_bits, const pm_options *opt,
+                    pm_stats *stats);
+
+/* ---- caller-owned workspace ----------------------------------------------------
+   By default the library allocates its scratch (grow-only, kept until
+   pm_destroy).  After pm_set_workspace every prune takes all its scratch
+   from the caller's device buffer instead and allocates nothing: the buffer
+   is split into batch_streams equal slices (one per concurrent template),
+   each slice used from its start by every template the worker prunes.
+
+   pm_workspace_size: an upper bound of the bytes pm_prune(first_id, count,
+   opt) can need with the current graph and settings (the compacted
+   subgraph bounded by the entries of the vertices whose label occurs in the
+   template, the role lists by that times the largest number of template
+   vertices sharing a label).  A smaller workspace works whenever the data
+   allow it: pm_stats.workspace_bytes of an earlier prune is the peak one
+   template actually used.  A prune that runs out fails with
+   PM_ERR_WORKSPACE (outputs undefined) and leaves the context usable. */
+int pm_workspace_size(pm_ctx *ctx, int32_t first_id, int32_t count, const pm_options *opt,
+                      size_t *bytes);
+
+/* Use ws (device memory of the context's device, 256-byte aligned,
+   caller-owned; the library never frees it) of `bytes` bytes for all
+   scratch from now on; ws = NULL returns to library-owned scratch.  The
+   caller must keep the buffer alive and must not use it while a prune
+   runs. */
+int pm_set_workspace(pm_ctx *ctx, void *ws, size_t bytes);
+
+/* ---- match counting and enumeration on the pruned graph --------------------
+   Match enumeration and counting run on the reduced graph that pruning
+   leaves (termination and output section): a full-template walk with
+   aggregation off, every match verified.  Here: depth-first searches from
+   every background edge that can hold one chosen template edge (both
+   orientations counted separately), restricted to the role sets of
+   `state`, counting every injective label-preserving map (Definition 1)
+   once. */
+typedef struct {
+    uint64_t maps;             /* matches as maps phi (Definition 1)            */
+    uint64_t automorphisms;    /* label-preserving automorphisms of G0 (0 if
+                                  more than 2^40 or too costly to count)        */
+    uint64_t subgraphs;        /* maps / automorphisms: distinct matched
+                                  subgraphs (0 when automorphisms is 0)         */
+    int64_t written;           /* maps written to the output array            */
+    int64_t roots;             /* edge-rooted searches run                    */
+    double ms_total;           /* device time of the whole call               */
+} pm_match_count;
+
+/* Count (and optionally list) the matches of template `id` within state
+   (device uint64[n]: role masks that hold the complete set -- the roles
+   pm_prune returned for this template, an exported state -- or NULL for
+   the label roles, which counts over the whole graph).  Role bits whose
+   label differs from the vertex's are ignored.  maps_out: device
+   int32[cap][n0] or NULL; receives min(cap, maps) maps (images of template
+   vertices 0 .. n0-1), in no particular order.  Result in *out (host). */
+int pm_count_matches(pm_ctx *ctx, int32_t id, const uint64_t *state, int32_t *maps_out,
+                     int64_t cap, pm_match_count *out);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,11 @@ non-local constraints, initialise vertex state, LCC to a fixpoint, then for
 each constraint NLCC followed by LCC when anything changed) and finishes with
 the full-template search that makes the result exact.  `bruteforce` computes
 the plain definition of the output (union of all exact matches,
-Definition 1) by enumeration, and pins `prune` on small inputs.
+Definition 1) by enumeration, and pins `prune` on small inputs;
+`enumerate_maps` lists those matches (counting and enumeration on the
+reduced graph).  `candidate_set` is the local-only superset of the complete
+sets of every edge-deleted variant of a template (interactive incremental
+search).
 """
 from __future__ import annotations
 
@@ -68,6 +72,8 @@ def _load():
     lib.orc_exact_subset.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64]
     lib.orc_exact_sample.restype = I64
     lib.orc_exact_sample.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64, P, P, P]
+    lib.orc_enumerate.restype = I64
+    lib.orc_enumerate.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64]
     lib.orc_num_threads.restype = I32
     lib.orc_set_threads.restype = None
     lib.orc_set_threads.argtypes = [I32]
@@ -272,3 +278,51 @@ def bruteforce(row_ptr, col, labels, t_labels, t_edges):
     if cnt < 0:
         raise ValueError("bad or disconnected template")
     return role[:g.n], edge[:nwords(g.m)], int(cnt)
+
+
+def enumerate_maps(row_ptr, col, labels, t_labels, t_edges, cap: int = 1 << 20):
+    """Every match as a map (Definition 1): (count, maps int32[min(count,
+    cap)][n0], rows sorted).  Plain enumeration, tiny inputs only."""
+    g = _G(row_ptr, col, labels)
+    t = _T(t_labels, t_edges)
+    maps = np.zeros((max(cap, 1), t.n0), dtype=np.int32)
+    cnt = _load().orc_enumerate(g.n, _p(g.row_ptr), _p(g.col), _p(g.labels), t.n0, t.m0,
+                                _p(t.labels), _p(t.edges), _p(maps), cap)
+    if cnt < 0:
+        raise ValueError("bad or disconnected template")
+    k = min(int(cnt), cap)
+    out = maps[:k]
+    if k:
+        out = out[np.lexsort(out.T[::-1])]
+    return int(cnt), out
+
+
+def candidate_set(row_ptr, col, labels, t_labels, t_edges):
+    """Candidate set of the interactive incremental search: role sets after
+    local checking to a fixpoint with the rule every connected template
+    obtained by deleting edges satisfies -- role q of v stays while some
+    neighbour of v holds a role adjacent to q in G0 (synchronous sweeps,
+    each reading only the previous sweep's state).  Returns (omega
+    uint64[n], derived edge bits)."""
+    g = _G(row_ptr, col, labels)
+    t = _T(t_labels, t_edges)
+    om = init_roles(g, t)
+    if t.n0 > 1 and g.n > 0:
+        adj = [0] * t.n0
+        for a, b in t.edge_list:
+            adj[a] |= 1 << b
+            adj[b] |= 1 << a
+        src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        while True:
+            cover = np.zeros(g.n, dtype=np.uint64)
+            if g.m:
+                np.bitwise_or.at(cover, src, om[g.col[:g.m]])
+            new = np.zeros_like(om)
+            for q in range(t.n0):
+                bit = np.uint64(1 << q)
+                keep = ((om & bit) != 0) & ((cover & np.uint64(adj[q])) != 0)
+                new |= np.where(keep, bit, np.uint64(0))
+            if np.array_equal(new, om):
+                break
+            om = new
+    return om, active_edges(g, t, om)

@@ -42,6 +42,9 @@
  *                       enumerate every injective, label-preserving map of V0
  *                       that maps E0 into E, and take the union of their
  *                       vertices (with roles) and edges.
+ *   orc_enumerate    -- the same enumeration, writing every map phi out
+ *                       (match enumeration and counting on the reduced
+ *                       graph, termination and output section).
  *   orc_active_edges -- the edge state implied by omega during LCC/NLCC:
  *                       u->w is active iff some q in omega(u) and q' in
  *                       omega(w) are adjacent in G0 (edge elimination rule).
@@ -360,10 +363,19 @@ typedef struct {
     uint64_t *edge_out;
     int64_t count;
     int64_t limit;
+    int32_t *maps;           /* orc_enumerate: maps written here (or NULL) */
+    int64_t cap, written;
 } bf_t;
 
 static void bf_record(bf_t *B, const int32_t *img) {
     const plan_t *P = &B->P;
+    if (B->maps) {
+        int64_t at;
+        #pragma omp atomic capture
+        at = B->written++;
+        if (at < B->cap)
+            for (int i = 0; i < P->k; ++i) B->maps[at * B->T->n0 + P->q[i]] = img[i];
+    }
     for (int i = 0; i < P->k; ++i) {
         #pragma omp atomic
         B->role_out[img[i]] |= 1ull << P->q[i];
@@ -414,6 +426,7 @@ int64_t orc_bruteforce(int64_t n, const int64_t *row_ptr, const int32_t *col,
     memset(role_out, 0, (size_t)n * sizeof(uint64_t));
     memset(edge_out, 0, (size_t)((m + 63) / 64) * sizeof(uint64_t));
     bf_t B;
+    memset(&B, 0, sizeof(B));
     B.G = &G; B.T = &T; B.role_out = role_out; B.edge_out = edge_out;
     uint64_t vmask = (n0 == 64) ? ~0ull : ((1ull << n0) - 1ull);
     make_plan(&B.P, vmask, T.adj, 0, -1);
@@ -564,4 +577,38 @@ int64_t orc_exact_sample(int64_t n, const int64_t *row_ptr, const int32_t *col,
     }
     free(eplan);
     return searches;
+}
+
+/* ---- enumeration (Definition 1 written out) ------------------------------- */
+/* Every map phi of the brute force above, as n0 images in template-vertex
+   order, the first `cap` of them written to maps[cap][n0] (in no fixed
+   order: the vertex loop is parallel).  Returns the number of maps, or -1. */
+int64_t orc_enumerate(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                      const int32_t *vlabel, int n0, int m0, const int32_t *tl,
+                      const int32_t *te, int32_t *maps, int64_t cap) {
+    const int64_t m = row_ptr[n];
+    uint64_t *role = (uint64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+    uint64_t *edge = (uint64_t *)calloc((size_t)((m + 63) / 64 + 1), sizeof(uint64_t));
+    tmpl_t T;
+    if (load_tmpl(&T, n0, m0, tl, te)) { free(role); free(edge); return -1; }
+    graph_t G = {n, row_ptr, col, vlabel};
+    bf_t B;
+    memset(&B, 0, sizeof(B));
+    B.G = &G; B.T = &T; B.role_out = role; B.edge_out = edge;
+    B.maps = maps; B.cap = cap;
+    uint64_t vmask = (n0 == 64) ? ~0ull : ((1ull << n0) - 1ull);
+    make_plan(&B.P, vmask, T.adj, 0, -1);
+    if (B.P.k != n0) { free(role); free(edge); return -1; }
+    int64_t total = 0;
+    #pragma omp parallel for schedule(dynamic, 64) reduction(+:total)
+    for (int64_t v = 0; v < n; ++v) {
+        if (vlabel[v] != T.label[0]) continue;
+        int32_t img[64];
+        img[0] = (int32_t)v;
+        int64_t c = 0;
+        bf_extend(&B, 1, img, &c);
+        total += c;
+    }
+    free(role); free(edge);
+    return total;
 }

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -38,21 +39,45 @@ static thread_local std::string g_last_error;
                         std::string(#call) + ": " + hipGetErrorString(_e));                  \
     } while (0)
 
-// Grow-only device buffer.
+// Caller-owned device memory that a worker's buffers are carved from (bump
+// allocation, 256-byte aligned); reset at the start of every template.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0, peak = 0;
+    void *take(size_t want) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off > cap || want > cap - off)
+            throw Error(PM_ERR_WORKSPACE, "workspace too small: needs more than " +
+                                              std::to_string(cap) + " bytes (" +
+                                              std::to_string(off + want) + " requested so far)");
+        used = off + want;
+        peak = std::max(peak, used);
+        return base + off;
+    }
+};
+
+// Grow-only device buffer: library-owned (hipMalloc) unless it draws from an
+// arena, where growing takes a new block and abandons the old one.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    Arena *arena = nullptr;
     void ensure(size_t want) {
         if (want <= bytes) return;
+        size_t alloc = std::max<size_t>(want, 256);
+        if (arena) {
+            p = arena->take(alloc);
+            bytes = alloc;
+            return;
+        }
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
-        size_t alloc = std::max<size_t>(want, 256);
         PM_HIP(hipMalloc(&p, alloc));
         bytes = alloc;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !arena) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -86,16 +111,49 @@ struct Timer {
 struct Scratch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    Arena arena;
+    bool in_arena = false;
     DevBuf omega, sat, alist[2], bins, counters, hub, cdeg, crp, ccol, coff, cown, crp2, ccol2,
         coff2, cown2,
         segcnt, segscan, segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
         actbits, ord, afilt, split[2];
-    void release() {
-        for (DevBuf *b : {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
-                          &ccol, &coff, &cown, &crp2, &ccol2, &coff2, &cown2, &segcnt, &segscan, &segbits, &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids,
-                          &ccert, &expseen, &wit, &witflag, &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord, &afilt, &split[0], &split[1]})
+    std::vector<DevBuf *> all() {
+        return {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
+                &ccol, &coff, &cown, &crp2, &ccol2, &coff2, &cown2, &segcnt, &segscan, &segbits,
+                &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids, &ccert, &expseen, &wit, &witflag,
+                &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord, &afilt, &split[0],
+                &split[1]};
+    }
+    // Draw every buffer from [base, base + cap) from now on (library-owned
+    // buffers are freed first), or, with base == nullptr, return to
+    // library-owned buffers.
+    void use_arena(char *base, size_t cap) {
+        for (DevBuf *b : all()) {
             b->release();
+            b->arena = base ? &arena : nullptr;
+        }
+        arena = Arena{};
+        arena.base = base;
+        arena.cap = cap;
+        in_arena = base != nullptr;
+    }
+    // Start of a template's prune in arena mode: every buffer is taken
+    // again from the start of the arena.
+    void reset_arena() {
+        if (!in_arena) return;
+        for (DevBuf *b : all()) b->release();
+        arena.used = 0;
+        arena.peak = 0;
+    }
+    size_t bytes_held() {
+        if (in_arena) return arena.peak;
+        size_t t = 0;
+        for (DevBuf *b : all()) t += b->bytes;
+        return t;
+    }
+    void release() {
+        for (DevBuf *b : all()) b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
         own_stream = false;
@@ -119,6 +177,7 @@ struct pm_ctx {
     int label_bytes = 1;
     DevBuf own_rp, own_col, own_labels;
     std::vector<int64_t> label_freq;
+    std::vector<int64_t> label_degsum;   // sum of degrees per label
     // neighbour-label count index (uint8 labels below kCountLabels): count
     // of neighbours of v with label L at lab_cnt[L * n + v]; nlab = 0: none
     DevBuf lab_cnt;
@@ -143,6 +202,9 @@ struct pm_ctx {
     int64_t split_cap = kSplitCap;
     int read_first = 0;
     int64_t wall_khz = 0;
+    // caller-owned workspace (pm_set_workspace); null: library-owned scratch
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
     // learned-order model and the workspace of its training kernels
     DevBuf model;
     bool has_model = false;
@@ -170,7 +232,9 @@ enum : int {
     C_SPLIT = 9,       // split tasks appended
     C_QUERIES_U64 = 16,   // byte offset 64: unsigned long long
     C_ENTRIES_U64 = 18,   // byte offset 72: unsigned long long
-    C_TOTAL_BYTES = 256,      // bytes 128..207: query statistics [10]
+    C_COUNT_U64 = 64,     // byte offset 256: maps counted (unsigned long long)
+    C_WRITTEN_U64 = 66,   // byte offset 264: maps written
+    C_TOTAL_BYTES = 512,      // bytes 128..255: query statistics [16]
 };
 
 struct Graph {
@@ -202,9 +266,31 @@ struct Pruner {
     int32_t *c_own = nullptr;
     int64_t c_m = 0;
     pm_stats st{};
+    // per-call options and the state brought in with them
+    const pm_options *opt = nullptr;
+    LccTable lcc;                   // the template's local rule, per mode
+    bool candidate = false;         // PM_MODE_CANDIDATE
+    uint32_t ablate = 0;
+    const uint64_t *init_state = nullptr;
+    uint64_t skip_mask = 0;
+    const uint64_t *known_roles = nullptr;
+    const uint64_t *known_edges = nullptr;
+    uint64_t done_mask = 0;
+    int exp_log2;
+    int64_t split_cap;
 
-    Pruner(pm_ctx *ctx, Scratch *scr, const CompiledTemplate &t)
-        : c(ctx), w(scr), T(t), s(scr->stream) {
+    Pruner(pm_ctx *ctx, Scratch *scr, const CompiledTemplate &t, const pm_options *o = nullptr)
+        : c(ctx), w(scr), T(t), s(scr->stream), opt(o), lcc(t.lcc), exp_log2(ctx->exp_log2),
+          split_cap(ctx->split_cap) {
+        if (opt) {
+            candidate = opt->mode == PM_MODE_CANDIDATE;
+            ablate = opt->ablate;
+        }
+        if (candidate) {
+            lcc.any = 1;
+            lcc.ncount = 0;
+        }
+        if (ablate & PM_ABLATE_EDGE_ELIMINATION) lcc.keep_all = 1;
         const int64_t n = c->n;
         w->omega.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
         w->sat.ensure(sizeof(M) * (size_t)std::max<int64_t>(n, 1));
@@ -290,7 +376,7 @@ struct Pruner {
             PM_HIP(hipEventCreate(&a));
             PM_HIP(hipEventCreate(&b));
             PM_HIP(hipEventRecord(a, s));
-            launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, T.lcc, ctr + C_CHANGED, true);
+            launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, lcc, ctr + C_CHANGED, true);
             PM_HIP(hipEventRecord(b, s));
             PM_HIP(hipEventSynchronize(b));
             float ms = 0;
@@ -299,7 +385,7 @@ struct Pruner {
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
         } else {
-            launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, T.lcc, ctr + C_CHANGED, false);
+            launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, lcc, ctr + C_CHANGED, false);
         }
         st.lcc_sweeps++;
         return read_ctr(C_CHANGED);
@@ -364,7 +450,7 @@ struct Pruner {
             launch_active_filter<M>(s, n, om, w->afilt.as<uint32_t>());
         }
         const uint32_t *filt = w->afilt.as<uint32_t>();
-        launch_compact_count<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, filt, deg,
+        launch_compact_count<M>(s, src_rp, src_col, om, wl, hc, nseg, lcc, filt, deg,
                                 w->segcnt.as<int64_t>(), w->segbits.as<uint64_t>());
         int64_t sl = scan_scratch_len(std::max<int64_t>(n, nseg));
         w->scan_scratch.ensure(sizeof(int64_t) * (size_t)sl);
@@ -380,7 +466,7 @@ struct Pruner {
         ccol.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
         coff.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
         cown.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(new_m, 1));
-        launch_compact_fill<M>(s, src_rp, src_col, om, wl, hc, nseg, T.lcc, filt, new_rp,
+        launch_compact_fill<M>(s, src_rp, src_col, om, wl, hc, nseg, lcc, filt, new_rp,
                                w->segscan.as<int64_t>(), w->segbits.as<uint64_t>(), base_off,
                                ccol.as<int32_t>(), coff.as<int32_t>(), cown.as<int32_t>());
         c_rp = new_rp;
@@ -435,6 +521,7 @@ struct Pruner {
         a.split_out = nullptr;
         a.split_n = nullptr;
         a.split_cap = 0;
+        a.aggregate = (ablate & PM_ABLATE_WORK_AGGREGATION) ? 0 : 1;
         return a;
     }
 
@@ -492,18 +579,22 @@ struct Pruner {
         unsigned long long q0 = 0, q1 = 0;
         const int64_t cwords = (c_m + 63) / 64;
         w->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
-        w->expseen.ensure(sizeof(uint64_t) << c->exp_log2);
+        w->expseen.ensure(sizeof(uint64_t) << exp_log2);
         uint64_t *c_cert = w->ccert.as<uint64_t>();
         role_lists();
         launch_fill_u64(s, c_cert, cwords, 0ull);
-        launch_fill_u64(s, w->expseen.as<uint64_t>(), 1ll << c->exp_log2, 0ull);
+        launch_fill_u64(s, w->expseen.as<uint64_t>(), 1ll << exp_log2, 0ull);
+        // roles and edges known to be in the complete set count as
+        // certified: no search is run for them
+        if (known_roles) launch_known_roles<M>(s, A, nA, om, known_roles, sat);
+        if (known_edges) launch_known_edges(s, c_m, c_own, c_off, c->rp, known_edges, c_cert);
         PM_HIP(hipMemsetAsync(qstats, 0, sizeof(unsigned long long) * 16, s));
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
         SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
         a.c_cert = c_cert;
         a.exp_seen = w->expseen.as<unsigned long long>();
-        a.exp_log2 = c->exp_log2;
+        a.exp_log2 = exp_log2;
         // witnesses of certified (vertex, role) pairs, for single-swap
         // certification of candidate edges (small templates only)
         const int64_t wit_words = nA * (int64_t)T.n0 * T.n0;
@@ -516,7 +607,7 @@ struct Pruner {
             a.wit_on = 1;
         }
         a.qstats = qstats;
-        a.expand = c->expand;
+        a.expand = a.aggregate ? c->expand : 0;
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
         d2h(s, &q0, queries, 1);
         // edge part over vertices with certified roles
@@ -529,7 +620,7 @@ struct Pruner {
         w->ew.ensure(sizeof(int32_t) * (size_t)cap);
         w->eidx.ensure(2 * sizeof(int64_t) * (size_t)cap);   // (entry, reverse entry)
         PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
-        launch_edge_candidates<M>(s, c_m, c_rp, c_own, c_col, sat, T.lcc, c_cert,
+        launch_edge_candidates<M>(s, c_m, c_rp, c_own, c_col, sat, lcc, c_cert,
                                   w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ctr + C_NOUT, cap, a);
         a.wit_on = 0;
@@ -574,12 +665,12 @@ struct Pruner {
                 // searches past the budget hand on their unexplored ranges,
                 // which later launches (double-buffered lists) search
                 for (DevBuf *b : {&w->split[0], &w->split[1]})
-                    b->ensure(sizeof(SplitTask) * (size_t)c->split_cap);
+                    b->ensure(sizeof(SplitTask) * (size_t)split_cap);
                 PM_HIP(hipMemsetAsync(ctr + C_SPLIT, 0, sizeof(int32_t), s));
                 a.split_budget = c->split_budget;
                 a.split_out = w->split[0].as<SplitTask>();
                 a.split_n = ctr + C_SPLIT;
-                a.split_cap = c->split_cap;
+                a.split_cap = split_cap;
             }
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
@@ -685,26 +776,36 @@ struct Pruner {
 
     // Main loop over the non-local constraints: NLCC, then LCC to the
     // fixpoint when anything changed.  In the learned mode the next
-    // constraint is the remaining one of largest model score.
+    // constraint is the remaining one of largest model score.  Constraints
+    // in skip_mask (applied to an imported state already) are not checked
+    // again but count as done.
     int64_t n_trace = 0;
-    void constraint_loop(const std::vector<int> &order, bool learned, int stop_after,
-                         const pm_options *opt) {
+    void constraint_loop(const std::vector<int> &order, bool learned, int stop_after) {
         const int K = (int)T.constraints.size();
         pm_trace_entry *trace = opt && opt->trace && opt->trace_cap > 0 ? opt->trace : nullptr;
         const int64_t cap = trace ? opt->trace_cap : 0;
         const bool featured = learned || trace;
+        const uint64_t all = K == 64 ? ~0ull : ((1ull << K) - 1ull);
+        const uint64_t skipped = skip_mask & all;
+        done_mask = skipped;
         if (featured && K > 0) {
             w->ord.ensure(sizeof(unsigned long long) * 2 * kMaxK + sizeof(OrderPick) + 64);
             role_totals(ord_counts0());
         }
-        uint64_t remaining = K == 64 ? ~0ull : ((1ull << K) - 1ull);
-        int done = 0;
+        uint64_t remaining = all & ~skipped;
+        int done = __builtin_popcountll(skipped);
+        size_t pos = 0;
         int64_t pending_after = -1;   // trace entry waiting for roles_after
         while (done < K) {
             if (stop_after >= 0 && done >= stop_after) break;
             if (nA == 0) break;
             OrderPick pk{};
-            int k = learned ? -1 : order[(size_t)done];
+            int k = -1;
+            if (!learned) {
+                while (pos < order.size() && ((skipped >> order[pos]) & 1ull)) ++pos;
+                if (pos >= order.size()) break;
+                k = order[pos++];
+            }
             const int64_t active_before = nA;
             if (featured) {
                 pk = pick(learned ? -1 : k, remaining, done);
@@ -738,6 +839,7 @@ struct Pruner {
             }
             const double ms = tt.stop();
             remaining &= ~(1ull << k);
+            done_mask |= 1ull << k;
             ++done;
             if (trace && n_trace < cap) {
                 pm_trace_entry &e = trace[n_trace];
@@ -758,12 +860,13 @@ struct Pruner {
         st.trace_entries = n_trace;
     }
 
-    void run(uint64_t *role_out, uint64_t *edge_out, const pm_options *opt) {
-        Timer total(s);
-        const int64_t n = c->n, m = c->m;
-        zero_counters();
-        launch_fill_u64(s, edge_out, (m + 63) / 64, 0ull);
-        const bool counted = c->nlab > 0 && T.n0 > 1;
+    // Role initialisation (vertex state and initialisation algorithm) and,
+    // from the neighbour-label count index when there is one, the first LCC
+    // sweep; an imported state is intersected in; omega's active list.
+    // Returns true when the first sweep has been applied.
+    bool init_state_and_first_sweep(bool allow_counted) {
+        const int64_t n = c->n;
+        const bool counted = allow_counted && c->nlab > 0 && T.n0 > 1 && !candidate;
         if (counted) {
             // first LCC sweep from the neighbour-label count index (it also
             // initialises omega)
@@ -798,6 +901,7 @@ struct Pruner {
             st.first_sweep_vertices = n;
             st.first_sweep_entries = 0;
             st.first_sweep_bytes = n + reads + (int64_t)sizeof(M) * n;
+            if (init_state) launch_and_state<M>(s, n, om, init_state);
             PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
             collect(true);
             st.ms_first_sweep = t.stop();
@@ -809,10 +913,27 @@ struct Pruner {
             wl.act_bits = w->actbits.as<uint64_t>();
             launch_init_roles<M>(s, n, c->labels, c->label_bytes, T.d_init_lut, T.init_lut_len, om,
                                  w->actbits.as<uint64_t>());
+            if (init_state) launch_and_state<M>(s, n, om, init_state);
             PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
             collect(true);
             st.ms_init += t.stop();
         }
+        return counted;
+    }
+
+    // Whole prune.  edge_out may be null (state export: no edge output).
+    void run(uint64_t *role_out, uint64_t *edge_out) {
+        Timer total(s);
+        const int64_t n = c->n, m = c->m;
+        if (opt) {
+            init_state = opt->init_state;
+            skip_mask = init_state ? opt->skip_mask : 0;
+            known_roles = opt->known_roles;
+            known_edges = opt->known_edges;
+        }
+        zero_counters();
+        if (edge_out) launch_fill_u64(s, edge_out, (m + 63) / 64, 0ull);
+        const bool counted = init_state_and_first_sweep(true);
         Graph full{c->rp, c->col};
         if (!counted && T.n0 > 1 && nA > 0) {
             // first sweep over the full graph
@@ -846,19 +967,119 @@ struct Pruner {
         } else {
             for (int i = 0; i < K; ++i) order.push_back(i);
         }
-        constraint_loop(order, learned, stop_after, opt);
-        if (stop_after >= 0 || T.acyclic_unique || T.n0 == 1) {
+        if (!candidate) constraint_loop(order, learned, stop_after);
+        if (candidate || stop_after >= 0 || T.acyclic_unique || T.n0 == 1 || !edge_out) {
             // omega and its implied edge state (exact for acyclic unique-label
             // templates: LCC alone suffices)
             launch_widen<M>(s, n, om, role_out);
-            if (T.n0 > 1)
-                launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, T.lcc, edge_out);
+            if (T.n0 > 1 && edge_out)
+                launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, lcc, edge_out);
             st.result_vertices = nA;
         } else {
             if (nA > 0) compact(true);
             exact(role_out, edge_out);
         }
+        st.done_mask = done_mask;
         st.ms_total = total.stop();
+        st.workspace_bytes = (int64_t)w->bytes_held();
+    }
+
+    // ---- match counting (termination and output: enumeration/counting on
+    // the pruned graph) ----------------------------------------------------
+    // Maps of the full template within omega0 AND state, counted from every
+    // compacted entry that can hold the chosen template edge.
+    pm_match_count count_matches(const uint64_t *state, int32_t *maps_out, int64_t cap) {
+        Timer total(s);
+        pm_match_count r{};
+        init_state = state;
+        zero_counters();
+        init_state_and_first_sweep(false);
+        const int64_t n = c->n;
+        (void)n;
+        if (T.n0 == 1) {
+            r.maps = (uint64_t)nA;
+            r.roots = nA;
+            const int64_t wr = std::min<int64_t>(std::max<int64_t>(cap, 0), nA);
+            if (maps_out && wr > 0)
+                PM_HIP(hipMemcpyAsync(maps_out, A, sizeof(int32_t) * (size_t)wr,
+                                      hipMemcpyDeviceToDevice, s));
+            r.written = maps_out ? wr : 0;
+        } else if (nA > 0) {
+            compact();
+            role_lists();
+            // root template edge: the one whose end roles are held by the
+            // fewest vertices
+            w->ord.ensure(sizeof(unsigned long long) * 2 * kMaxK + sizeof(OrderPick) + 64);
+            role_totals(ord_counts());
+            unsigned long long h[kMaxK];
+            d2h(s, h, ord_counts(), kMaxK);
+            int best = 0;
+            unsigned long long bc = ~0ull;
+            for (int i = 0; i < T.m0; ++i) {
+                const unsigned long long cc = h[T.edges[(size_t)i].first] + h[T.edges[(size_t)i].second];
+                if (cc < bc) {
+                    bc = cc;
+                    best = i;
+                }
+            }
+            const int32_t plan = T.edge_plans[(size_t)(2 * best)];
+            const SearchPlan &P = T.plans[(size_t)plan];
+            w->edge_plan_ids.ensure(sizeof(int32_t));
+            PM_HIP(hipMemcpyAsync(w->edge_plan_ids.p, &plan, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            const int64_t cap_t = std::max<int64_t>(c_m, 1);
+            w->eu.ensure(sizeof(int32_t) * (size_t)cap_t);
+            w->ew.ensure(sizeof(int32_t) * (size_t)cap_t);
+            PM_HIP(hipMemsetAsync(ctr + C_NOUT, 0, sizeof(int32_t), s));
+            launch_count_tasks<M>(s, c_m, c_own, c_col, om, P.pin[0], P.pin[1], w->eu.as<int32_t>(),
+                                  w->ew.as<int32_t>(), ctr + C_NOUT, cap_t);
+            const int64_t ne = read_ctr(C_NOUT);
+            if (ne > cap_t) throw Error(PM_ERR_CAPACITY, "count task capacity exceeded");
+            r.roots = ne;
+            unsigned long long *tot = reinterpret_cast<unsigned long long *>(ctr + C_COUNT_U64);
+            unsigned long long *wrt = reinterpret_cast<unsigned long long *>(ctr + C_WRITTEN_U64);
+            if (ne > 0) {
+                const uint64_t allr = T.n0 == 64 ? ~0ull : ((1ull << T.n0) - 1ull);
+                SearchArgs a = search_args(1, allr, T.vertex_plan, nullptr);
+                a.task_chunk = std::max(1, c->edge_chunk);
+                PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
+                if (c->split_budget > 0) {
+                    for (DevBuf *b : {&w->split[0], &w->split[1]})
+                        b->ensure(sizeof(SplitTask) * (size_t)split_cap);
+                    PM_HIP(hipMemsetAsync(ctr + C_SPLIT, 0, sizeof(int32_t), s));
+                    a.split_budget = c->split_budget;
+                    a.split_out = w->split[0].as<SplitTask>();
+                    a.split_n = ctr + C_SPLIT;
+                    a.split_cap = split_cap;
+                }
+                launch_count_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(), ne, om,
+                                       w->edge_plan_ids.as<int32_t>(), a, maps_out,
+                                       maps_out ? cap : 0, wrt, tot, c->grid_search);
+                if (c->split_budget > 0) {
+                    int cur = 0;
+                    int64_t rounds = 0;
+                    for (int64_t nt = read_ctr(C_SPLIT); nt > 0; nt = read_ctr(C_SPLIT)) {
+                        if (++rounds > (int64_t)1 << 20)
+                            throw Error(PM_ERR_CAPACITY, "split searches did not finish");
+                        st.split_tasks += nt;
+                        a.split_budget = std::min<int64_t>(a.split_budget * 4, (int64_t)1 << 40);
+                        const SplitTask *in = w->split[cur].as<SplitTask>();
+                        cur ^= 1;
+                        a.split_out = w->split[cur].as<SplitTask>();
+                        PM_HIP(hipMemsetAsync(ctr + C_SPLIT, 0, sizeof(int32_t), s));
+                        PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
+                        launch_count_split<M>(s, in, nt, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
+                                              om, w->edge_plan_ids.as<int32_t>(), a, maps_out,
+                                              maps_out ? cap : 0, wrt, tot, c->grid_search);
+                    }
+                }
+            }
+            unsigned long long both[2] = {0, 0};
+            d2h(s, both, tot, 2);
+            r.maps = both[0];
+            r.written = maps_out ? (int64_t)std::min<unsigned long long>(both[1], (unsigned long long)std::max<int64_t>(cap, 0)) : 0;
+        }
+        r.ms_total = total.stop();
+        return r;
     }
 };
 
@@ -940,6 +1161,296 @@ int guarded(F &&f) {
         g_last_error = e.what();
         return PM_ERR_HIP;
     }
+}
+
+int workers_for(const pm_options *opt, int32_t count) {
+    int nw = 1;
+    if (opt && opt->batch_streams > 1 && count > 1)
+        nw = std::min<int>(std::min<int>(opt->batch_streams, 16), count);
+    return nw;
+}
+
+void ensure_workers(pm_ctx *c, int nw) {
+    while ((int)c->scratch.size() < nw) {
+        auto sc = std::make_unique<Scratch>();
+        if (c->scratch.empty()) {
+            sc->stream = c->stream;
+        } else {
+            PM_HIP(hipStreamCreateWithFlags(&sc->stream, hipStreamNonBlocking));
+            sc->own_stream = true;
+        }
+        c->scratch.push_back(std::move(sc));
+    }
+}
+
+// Upper bound of the scratch one template's prune takes (see
+// pm_workspace_size): every buffer at its largest, the compacted subgraph
+// bounded by mt = the entries of the vertices whose label occurs in the
+// template, the active vertices by nt = the vertices of those labels, the
+// role lists by mt times the largest number of template vertices sharing a
+// label.  Each buffer is rounded up to the arena's 256-byte alignment.
+size_t workspace_bound(const pm_ctx *c, const CompiledTemplate &T, int exp_log2, int64_t split_cap) {
+    const int64_t n = std::max<int64_t>(c->n, 1);
+    int64_t mt = 0, nt = 0;
+    std::vector<int> mult;
+    for (int q = 0; q < T.n0; ++q) {
+        const int L = T.labels[(size_t)q];
+        bool seen = false;
+        for (int r = 0; r < q; ++r)
+            if (T.labels[(size_t)r] == L) seen = true;
+        if (seen) continue;
+        if ((size_t)L < c->label_degsum.size()) mt += c->label_degsum[(size_t)L];
+        if ((size_t)L < c->label_freq.size()) nt += c->label_freq[(size_t)L];
+    }
+    int maxmult = 1;
+    for (int q = 0; q < T.n0; ++q) {
+        int k = 0;
+        for (int r = 0; r < T.n0; ++r) k += T.labels[(size_t)r] == T.labels[(size_t)q];
+        maxmult = std::max(maxmult, k);
+    }
+    mt = std::max<int64_t>(mt, 1);
+    nt = std::max<int64_t>(nt, 1);
+    const int64_t M = T.mask_bytes;
+    const int64_t segs = std::max<int64_t>(c->seg_cap, 1), hubs = std::max<int64_t>(c->hub_cap, 1);
+    const int64_t n0 = T.n0;
+    size_t total = 0;
+    auto add = [&](int64_t b) { total += (size_t)((std::max<int64_t>(b, 256) + 255) / 256 * 256); };
+    add(M * n); add(M * n);                                   // omega, sat
+    add(4 * n); add(4 * n);                                   // active lists
+    add(4 * n * kNumBins);                                    // degree bins
+    add(C_TOTAL_BYTES);                                       // counters
+    add(segs * (4 + 8 + 8 + 4) + hubs * (4 + 4 + 8 + 4 * kMaxCount + 4) + 256);
+    add(8 * segs); add(8 * (segs + 1)); add(8 * segs * (kHubSegment / kWave));
+    add(8 * (n + 1)); add(8 * (n + 1)); add(8 * (n + 1));     // cdeg, crp, crp2
+    add(8 * scan_scratch_len(std::max<int64_t>(n, segs)));
+    for (int i = 0; i < 6; ++i) add(4 * mt);                  // two sets of c_col/c_off/c_own
+    add(4 * ((n + 255) / 256));                               // active filter
+    add(8 * ((n + 63) / 64));                                 // initial-role bitmap
+    add(8 * ((mt + 63) / 64));                                // certified entries
+    add((int64_t)sizeof(uint64_t) << exp_log2);               // swap-scan table
+    add(4 * (mt / 2 + 1)); add(4 * (mt / 2 + 1)); add(16 * (mt / 2 + 1));   // edge tasks
+    add(4 * std::max<int64_t>(2 * T.m0, 1));
+    add(4 * std::max<int64_t>(mt, 1)); add(4 * std::max<int64_t>(mt, 1));    // count tasks
+    if (c->witness && T.n0 <= 16) {
+        add(4 * std::min<int64_t>(nt * n0 * n0, (int64_t)1 << 29));
+        add(4 * nt * n0);
+    }
+    add(8 * (nt * n0 + 1)); add(8 * (nt * n0 + 1));           // role-list counts, offsets
+    add(4 * n);                                               // list positions
+    add(4 * mt * maxmult); add(4 * mt * maxmult);             // role lists, entries
+    add(8 * scan_scratch_len(nt * n0));
+    add((int64_t)sizeof(unsigned long long) * 2 * kMaxK + (int64_t)sizeof(OrderPick) + 64);
+    if (c->split_budget > 0) {
+        add((int64_t)sizeof(SplitTask) * split_cap);
+        add((int64_t)sizeof(SplitTask) * split_cap);
+    }
+    return total;
+}
+
+// Label-preserving automorphisms of G0 (backtracking over images in vertex
+// order, adjacency to every earlier vertex checked both ways); 0 when the
+// count exceeds 2^40 or the search runs past 10^8 steps.
+uint64_t count_automorphisms(const CompiledTemplate &T) {
+    const int n0 = T.n0;
+    std::vector<uint64_t> adj((size_t)n0, 0);
+    for (auto &e : T.edges) {
+        adj[(size_t)e.first] |= 1ull << e.second;
+        adj[(size_t)e.second] |= 1ull << e.first;
+    }
+    std::vector<int> img((size_t)n0, -1);
+    uint64_t used = 0, count = 0, steps = 0;
+    bool abort = false;
+    std::function<void(int)> rec = [&](int q) {
+        if (abort) return;
+        if (q == n0) {
+            if (++count > (1ull << 40)) abort = true;
+            return;
+        }
+        for (int r = 0; r < n0 && !abort; ++r) {
+            if ((used >> r) & 1ull) continue;
+            if (++steps > 100000000ull) { abort = true; return; }
+            if (T.labels[(size_t)r] != T.labels[(size_t)q]) continue;
+            if (__builtin_popcountll(adj[(size_t)r]) != __builtin_popcountll(adj[(size_t)q])) continue;
+            bool ok = true;
+            for (int j = 0; j < q && ok; ++j)
+                ok = (((adj[(size_t)q] >> j) & 1ull) != 0) == (((adj[(size_t)r] >> img[(size_t)j]) & 1ull) != 0);
+            if (!ok) continue;
+            img[(size_t)q] = r;
+            used |= 1ull << r;
+            rec(q + 1);
+            used &= ~(1ull << r);
+        }
+    };
+    rec(0);
+    return abort ? 0 : count;
+}
+
+// Scratch of the no-allocation prune: the static device array.
+struct NoAlloc {
+    char *base = nullptr;
+    size_t bytes = 0;
+};
+
+// pm_prune's body.  With na, all scratch comes from the static array, one
+// worker, and the swap-scan table and split lists are shrunk to fit.
+void prune_impl(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask,
+                uint64_t *edge_bits, const pm_options *opt, pm_stats *stats, const NoAlloc *na) {
+    if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
+    if (count <= 0 || first_id < 0 || first_id + count > (int32_t)c->templates.size())
+        throw Error(PM_ERR_NOT_FOUND, "template id range out of bounds");
+    if (!role_mask) throw Error(PM_ERR_INVALID_ARG, "null output");
+    if (opt && (opt->order_mode < PM_ORDER_FIXED || opt->order_mode > PM_ORDER_LEARNED))
+        throw Error(PM_ERR_INVALID_ARG, "unknown order mode");
+    if (opt && (opt->mode != PM_MODE_FULL && opt->mode != PM_MODE_CANDIDATE))
+        throw Error(PM_ERR_INVALID_ARG, "unknown mode");
+    if (opt && (opt->ablate & ~(PM_ABLATE_EDGE_ELIMINATION | PM_ABLATE_WORK_AGGREGATION)))
+        throw Error(PM_ERR_INVALID_ARG, "unknown ablation bit");
+    if (opt && opt->order_mode == PM_ORDER_LEARNED && !c->has_model)
+        throw Error(PM_ERR_MODEL, "learned order without a loaded model");
+    if (opt && opt->trace && opt->trace_cap > 0 && count != 1)
+        throw Error(PM_ERR_INVALID_ARG, "a trace records one template: count must be 1");
+    set_device(c);
+    const int64_t words = (c->m + 63) / 64;
+    // workers: each prunes whole templates on its own stream with its own
+    // scratch; worker 0 uses the context stream
+    const int nw = na ? 1 : workers_for(opt, count);
+    ensure_workers(c, nw);
+    int na_exp = c->exp_log2;
+    int64_t na_split = c->split_cap;
+    if (na) {
+        // work-saving tables sized for the static array
+        na_exp = std::min(na_exp, 16);
+        na_split = std::min<int64_t>(na_split, 4096);
+        const CompiledTemplate &T = *c->templates[(size_t)first_id];
+        const size_t need = workspace_bound(c, T, na_exp, na_split);
+        if (need > na->bytes)
+            throw Error(PM_ERR_WORKSPACE, "graph and template need up to " + std::to_string(need) +
+                                              " bytes of scratch; the static array holds " +
+                                              std::to_string(na->bytes));
+        c->scratch[0]->use_arena(na->base, na->bytes);
+    } else if (c->ws) {
+        const size_t slice = (c->ws_bytes / (size_t)nw) & ~(size_t)255;
+        for (int k = 0; k < nw; ++k)
+            c->scratch[(size_t)k]->use_arena(c->ws + (size_t)k * slice, slice);
+    } else {
+        for (int k = 0; k < nw; ++k)
+            if (c->scratch[(size_t)k]->in_arena) c->scratch[(size_t)k]->use_arena(nullptr, 0);
+    }
+    if (nw > 1) {
+        // the caller's pending work on its stream precedes the workers
+        PM_HIP(hipStreamSynchronize(c->stream));
+    }
+    std::vector<pm_stats> per((size_t)count);
+    auto run_one = [&](Scratch *w, int32_t i) {
+        const CompiledTemplate &T = *c->templates[(size_t)(first_id + i)];
+        uint64_t *ro = role_mask + (size_t)i * (size_t)c->n;
+        uint64_t *eo = edge_bits ? edge_bits + (size_t)i * (size_t)words : nullptr;
+        pm_options o = opt ? *opt : pm_options{};
+        if (!opt) o.stop_after = -1;
+        if (o.init_state) o.init_state += (size_t)i * (size_t)c->n;
+        if (o.known_roles) o.known_roles += (size_t)i * (size_t)c->n;
+        if (o.known_edges) o.known_edges += (size_t)i * (size_t)words;
+        w->reset_arena();
+        auto go = [&](auto &p) {
+            if (na) {
+                p.exp_log2 = na_exp;
+                p.split_cap = na_split;
+            }
+            p.run(ro, eo);
+            per[(size_t)i] = p.st;
+        };
+        switch (T.mask_bytes) {
+        case 1: { Pruner<uint8_t> p(c, w, T, &o); go(p); break; }
+        case 2: { Pruner<uint16_t> p(c, w, T, &o); go(p); break; }
+        case 4: { Pruner<uint32_t> p(c, w, T, &o); go(p); break; }
+        default: { Pruner<uint64_t> p(c, w, T, &o); go(p); break; }
+        }
+    };
+    if (nw == 1) {
+        for (int32_t i = 0; i < count; ++i) run_one(c->scratch[0].get(), i);
+    } else {
+        // the templates likely to take longest go first (more
+        // independent cycles, then more edges and vertices), so the
+        // long ones overlap each other and the short ones fill in at
+        // the end instead of one long template running alone
+        std::vector<int32_t> deal((size_t)count);
+        for (int32_t i = 0; i < count; ++i) deal[(size_t)i] = i;
+        auto cost = [&](int32_t i) {
+            const CompiledTemplate &T = *c->templates[(size_t)(first_id + i)];
+            return std::make_tuple(T.m0 - T.n0 + 1, T.m0, T.n0);
+        };
+        std::stable_sort(deal.begin(), deal.end(),
+                         [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+        std::atomic<int32_t> next{0};
+        std::vector<std::string> errs((size_t)nw);
+        std::vector<int> codes((size_t)nw, PM_OK);
+        std::vector<std::thread> th;
+        for (int k = 0; k < nw; ++k)
+            th.emplace_back([&, k] {
+                try {
+                    PM_HIP(hipSetDevice(c->device));
+                    for (;;) {
+                        const int32_t j = next.fetch_add(1);
+                        if (j >= count) break;
+                        run_one(c->scratch[(size_t)k].get(), deal[(size_t)j]);
+                    }
+                    PM_HIP(hipStreamSynchronize(c->scratch[(size_t)k]->stream));
+                } catch (const Error &e) {
+                    errs[(size_t)k] = e.what();
+                    codes[(size_t)k] = e.code;
+                    next.store(count);
+                } catch (const std::exception &e) {
+                    errs[(size_t)k] = e.what();
+                    codes[(size_t)k] = PM_ERR_HIP;
+                    next.store(count);
+                }
+            });
+        for (auto &t : th) t.join();
+        for (int k = 0; k < nw; ++k)
+            if (codes[(size_t)k] != PM_OK) throw Error(codes[(size_t)k], errs[(size_t)k]);
+    }
+    pm_stats total{};
+    for (const pm_stats &st : per) {
+        total.ms_total += st.ms_total;
+        total.ms_init += st.ms_init;
+        total.ms_lcc += st.ms_lcc;
+        total.ms_compact += st.ms_compact;
+        total.ms_nlcc += st.ms_nlcc;
+        total.ms_exact += st.ms_exact;
+        total.ms_first_sweep += st.ms_first_sweep;
+        total.ms_sweep_kernel += st.ms_sweep_kernel;
+        total.lcc_sweeps += st.lcc_sweeps;
+        total.constraints += st.constraints;
+        total.first_sweep_vertices += st.first_sweep_vertices;
+        total.first_sweep_entries += st.first_sweep_entries;
+        total.candidate_entries += st.candidate_entries;
+        total.vertex_queries += st.vertex_queries;
+        total.edge_queries += st.edge_queries;
+        total.result_vertices += st.result_vertices;
+        total.edge_candidates += st.edge_candidates;
+        total.vq_pos += st.vq_pos;
+        total.vq_neg += st.vq_neg;
+        total.eq_pos += st.eq_pos;
+        total.eq_neg += st.eq_neg;
+        total.wave_ms_vq_pos += st.wave_ms_vq_pos;
+        total.wave_ms_vq_neg += st.wave_ms_vq_neg;
+        total.wave_ms_eq_pos += st.wave_ms_eq_pos;
+        total.wave_ms_eq_neg += st.wave_ms_eq_neg;
+        total.wave_ms_certify += st.wave_ms_certify;
+        total.wave_ms_expand += st.wave_ms_expand;
+        total.expand_scans += st.expand_scans;
+        total.expand_candidates += st.expand_candidates;
+        total.expand_valid += st.expand_valid;
+        total.first_sweep_bytes += st.first_sweep_bytes;
+        total.witness_edges += st.witness_edges;
+        total.split_tasks += st.split_tasks;
+        total.trace_entries += st.trace_entries;
+        total.done_mask |= st.done_mask;
+        total.workspace_bytes = std::max(total.workspace_bytes, st.workspace_bytes);
+    }
+    PM_HIP(hipStreamSynchronize(c->stream));
+    if (na) c->scratch[0]->use_arena(nullptr, 0);
+    if (stats) *stats = total;
 }
 
 }  // namespace
@@ -1082,8 +1593,16 @@ int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const
         PM_HIP(hipMemcpyAsync(h.data(), hist.p, sizeof(unsigned long long) * (size_t)hl,
                               hipMemcpyDeviceToHost, c->stream));
         PM_HIP(hipStreamSynchronize(c->stream));
-        hist.release();
         c->label_freq.assign(h.begin(), h.end());
+        // degree sums per label (scratch bounds of pm_workspace_size)
+        PM_HIP(hipMemsetAsync(hist.p, 0, sizeof(unsigned long long) * (size_t)hl, c->stream));
+        launch_label_degsum(c->stream, n, c->rp, c->labels, label_bytes,
+                            hist.as<unsigned long long>(), hl);
+        PM_HIP(hipMemcpyAsync(h.data(), hist.p, sizeof(unsigned long long) * (size_t)hl,
+                              hipMemcpyDeviceToHost, c->stream));
+        PM_HIP(hipStreamSynchronize(c->stream));
+        c->label_degsum.assign(h.begin(), h.end());
+        hist.release();
         // neighbour-label count index for the first LCC sweep
         int maxl = -1;
         for (int64_t L = 0; L < hl; ++L)
@@ -1177,131 +1696,102 @@ int pm_prune(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask, ui
              const pm_options *opt, pm_stats *stats) {
     return guarded([&] {
         if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
+        if (!role_mask || !edge_bits) throw Error(PM_ERR_INVALID_ARG, "null output");
+        prune_impl(c, first_id, count, role_mask, edge_bits, opt, stats, nullptr);
+    });
+}
+
+int pm_export_state(pm_ctx *c, int32_t id, int32_t stop_after, const pm_options *opt,
+                    uint64_t *state, uint64_t *done_mask) {
+    return guarded([&] {
+        if (!c || !state || !done_mask) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        pm_options o = opt ? *opt : pm_options{};
+        if (!opt) o.stop_after = -1;
+        o.stop_after = stop_after < 0 ? PM_MAX_CONSTRAINTS : stop_after;
+        o.mode = PM_MODE_FULL;
+        o.known_roles = nullptr;
+        o.known_edges = nullptr;
+        pm_stats st{};
+        prune_impl(c, id, 1, state, nullptr, &o, &st, nullptr);
+        *done_mask = st.done_mask;
+    });
+}
+
+int pm_import_state(pm_ctx *c, int32_t id, const uint64_t *state, uint64_t done_mask,
+                    uint64_t *role_mask, uint64_t *edge_bits, const pm_options *opt,
+                    pm_stats *stats) {
+    return guarded([&] {
+        if (!c || !state || !role_mask || !edge_bits) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        pm_options o = opt ? *opt : pm_options{};
+        if (!opt) o.stop_after = -1;
+        o.mode = PM_MODE_FULL;
+        o.init_state = state;
+        o.skip_mask = done_mask;
+        prune_impl(c, id, 1, role_mask, edge_bits, &o, stats, nullptr);
+    });
+}
+
+int pm_workspace_size(pm_ctx *c, int32_t first_id, int32_t count, const pm_options *opt,
+                      size_t *bytes) {
+    return guarded([&] {
+        if (!c || !bytes) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
         if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
         if (count <= 0 || first_id < 0 || first_id + count > (int32_t)c->templates.size())
             throw Error(PM_ERR_NOT_FOUND, "template id range out of bounds");
-        if (!role_mask || !edge_bits) throw Error(PM_ERR_INVALID_ARG, "null output");
-        if (opt && (opt->order_mode < PM_ORDER_FIXED || opt->order_mode > PM_ORDER_LEARNED))
-            throw Error(PM_ERR_INVALID_ARG, "unknown order mode");
-        if (opt && opt->order_mode == PM_ORDER_LEARNED && !c->has_model)
-            throw Error(PM_ERR_MODEL, "learned order without a loaded model");
-        if (opt && opt->trace && opt->trace_cap > 0 && count != 1)
-            throw Error(PM_ERR_INVALID_ARG, "a trace records one template: count must be 1");
+        const int nw = workers_for(opt, count);
+        size_t worst = 0;
+        for (int32_t i = 0; i < count; ++i)
+            worst = std::max(worst, workspace_bound(c, *c->templates[(size_t)(first_id + i)],
+                                                    c->exp_log2, c->split_cap));
+        *bytes = worst * (size_t)nw;
+    });
+}
+
+int pm_set_workspace(pm_ctx *c, void *ws, size_t bytes) {
+    return guarded([&] {
+        if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
+        if (ws && ((uintptr_t)ws & 255u))
+            throw Error(PM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+        if (ws && bytes < 4096) throw Error(PM_ERR_WORKSPACE, "workspace smaller than 4 KiB");
         set_device(c);
-        const int64_t words = (c->m + 63) / 64;
-        // workers: each prunes whole templates on its own stream with its own
-        // scratch; worker 0 uses the context stream
-        int nw = 1;
-        if (opt && opt->batch_streams > 1 && count > 1)
-            nw = std::min<int>(std::min<int>(opt->batch_streams, 16), count);
-        while ((int)c->scratch.size() < nw) {
-            auto sc = std::make_unique<Scratch>();
-            if (c->scratch.empty()) {
-                sc->stream = c->stream;
-            } else {
-                PM_HIP(hipStreamCreateWithFlags(&sc->stream, hipStreamNonBlocking));
-                sc->own_stream = true;
-            }
-            c->scratch.push_back(std::move(sc));
-        }
-        if (nw > 1) {
-            // the caller's pending work on its stream precedes the workers
-            PM_HIP(hipStreamSynchronize(c->stream));
-        }
-        std::vector<pm_stats> per((size_t)count);
-        auto run_one = [&](Scratch *w, int32_t i) {
-            const CompiledTemplate &T = *c->templates[(size_t)(first_id + i)];
-            uint64_t *ro = role_mask + (size_t)i * (size_t)c->n;
-            uint64_t *eo = edge_bits + (size_t)i * (size_t)words;
-            switch (T.mask_bytes) {
-            case 1: { Pruner<uint8_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
-            case 2: { Pruner<uint16_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
-            case 4: { Pruner<uint32_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
-            default: { Pruner<uint64_t> p(c, w, T); p.run(ro, eo, opt); per[(size_t)i] = p.st; break; }
-            }
-        };
-        if (nw == 1) {
-            for (int32_t i = 0; i < count; ++i) run_one(c->scratch[0].get(), i);
-        } else {
-            // the templates likely to take longest go first (more
-            // independent cycles, then more edges and vertices), so the
-            // long ones overlap each other and the short ones fill in at
-            // the end instead of one long template running alone
-            std::vector<int32_t> deal((size_t)count);
-            for (int32_t i = 0; i < count; ++i) deal[(size_t)i] = i;
-            auto cost = [&](int32_t i) {
-                const CompiledTemplate &T = *c->templates[(size_t)(first_id + i)];
-                return std::make_tuple(T.m0 - T.n0 + 1, T.m0, T.n0);
-            };
-            std::stable_sort(deal.begin(), deal.end(),
-                             [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
-            std::atomic<int32_t> next{0};
-            std::vector<std::string> errs((size_t)nw);
-            std::vector<int> codes((size_t)nw, PM_OK);
-            std::vector<std::thread> th;
-            for (int k = 0; k < nw; ++k)
-                th.emplace_back([&, k] {
-                    try {
-                        PM_HIP(hipSetDevice(c->device));
-                        for (;;) {
-                            const int32_t j = next.fetch_add(1);
-                            if (j >= count) break;
-                            run_one(c->scratch[(size_t)k].get(), deal[(size_t)j]);
-                        }
-                        PM_HIP(hipStreamSynchronize(c->scratch[(size_t)k]->stream));
-                    } catch (const Error &e) {
-                        errs[(size_t)k] = e.what();
-                        codes[(size_t)k] = e.code;
-                        next.store(count);
-                    } catch (const std::exception &e) {
-                        errs[(size_t)k] = e.what();
-                        codes[(size_t)k] = PM_ERR_HIP;
-                        next.store(count);
-                    }
-                });
-            for (auto &t : th) t.join();
-            for (int k = 0; k < nw; ++k)
-                if (codes[(size_t)k] != PM_OK) throw Error(codes[(size_t)k], errs[(size_t)k]);
-        }
-        pm_stats total{};
-        for (const pm_stats &st : per) {
-            total.ms_total += st.ms_total;
-            total.ms_init += st.ms_init;
-            total.ms_lcc += st.ms_lcc;
-            total.ms_compact += st.ms_compact;
-            total.ms_nlcc += st.ms_nlcc;
-            total.ms_exact += st.ms_exact;
-            total.ms_first_sweep += st.ms_first_sweep;
-            total.ms_sweep_kernel += st.ms_sweep_kernel;
-            total.lcc_sweeps += st.lcc_sweeps;
-            total.constraints += st.constraints;
-            total.first_sweep_vertices += st.first_sweep_vertices;
-            total.first_sweep_entries += st.first_sweep_entries;
-            total.candidate_entries += st.candidate_entries;
-            total.vertex_queries += st.vertex_queries;
-            total.edge_queries += st.edge_queries;
-            total.result_vertices += st.result_vertices;
-            total.edge_candidates += st.edge_candidates;
-            total.vq_pos += st.vq_pos;
-            total.vq_neg += st.vq_neg;
-            total.eq_pos += st.eq_pos;
-            total.eq_neg += st.eq_neg;
-            total.wave_ms_vq_pos += st.wave_ms_vq_pos;
-            total.wave_ms_vq_neg += st.wave_ms_vq_neg;
-            total.wave_ms_eq_pos += st.wave_ms_eq_pos;
-            total.wave_ms_eq_neg += st.wave_ms_eq_neg;
-            total.wave_ms_certify += st.wave_ms_certify;
-            total.wave_ms_expand += st.wave_ms_expand;
-            total.expand_scans += st.expand_scans;
-            total.expand_candidates += st.expand_candidates;
-            total.expand_valid += st.expand_valid;
-            total.first_sweep_bytes += st.first_sweep_bytes;
-            total.witness_edges += st.witness_edges;
-            total.split_tasks += st.split_tasks;
-            total.trace_entries += st.trace_entries;
-        }
         PM_HIP(hipStreamSynchronize(c->stream));
-        if (stats) *stats = total;
+        for (auto &sc : c->scratch) {
+            if (sc->stream) PM_HIP(hipStreamSynchronize(sc->stream));
+            sc->use_arena(nullptr, 0);
+        }
+        c->ws = ws ? static_cast<char *>(ws) : nullptr;
+        c->ws_bytes = ws ? bytes : 0;
+    });
+}
+
+int pm_count_matches(pm_ctx *c, int32_t id, const uint64_t *state, int32_t *maps_out,
+                     int64_t cap, pm_match_count *out) {
+    return guarded([&] {
+        if (!c || !out) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
+        if (id < 0 || id >= (int32_t)c->templates.size()) throw Error(PM_ERR_NOT_FOUND, "unknown template id");
+        if (cap < 0 || (cap > 0 && !maps_out)) throw Error(PM_ERR_INVALID_ARG, "bad map output");
+        set_device(c);
+        ensure_workers(c, 1);
+        Scratch *w = c->scratch[0].get();
+        if (c->ws) {
+            w->use_arena(c->ws, c->ws_bytes);
+            w->reset_arena();
+        } else if (w->in_arena) {
+            w->use_arena(nullptr, 0);
+        }
+        const CompiledTemplate &T = *c->templates[(size_t)id];
+        pm_match_count r{};
+        switch (T.mask_bytes) {
+        case 1: { Pruner<uint8_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
+        case 2: { Pruner<uint16_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
+        case 4: { Pruner<uint32_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
+        default: { Pruner<uint64_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
+        }
+        r.automorphisms = count_automorphisms(T);
+        r.subgraphs = r.automorphisms ? r.maps / r.automorphisms : 0;
+        PM_HIP(hipStreamSynchronize(c->stream));
+        *out = r;
     });
 }
 

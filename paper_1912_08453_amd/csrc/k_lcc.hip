@@ -33,6 +33,12 @@ template <bool CNT>
 __device__ __forceinline__ uint64_t evaluate(uint64_t w, uint64_t cover, const int *cnt,
                                              const LccTable &tab) {
     uint64_t nw = w;
+    if (tab.any) {
+        // candidate-set rule: some template neighbour of q is covered
+        for (int q = 0; q < tab.n0; ++q)
+            if (((w >> q) & 1ull) && !(tab.adj[q] & cover)) nw &= ~(1ull << q);
+        return nw;
+    }
     for (int q = 0; q < tab.n0; ++q)
         if (((w >> q) & 1ull) && (tab.adj[q] & ~cover)) nw &= ~(1ull << q);
     if constexpr (CNT) {
@@ -625,6 +631,15 @@ __device__ __forceinline__ uint64_t omega_filtered(const M *__restrict__ omega,
     return may_be_active(f, x) ? (uint64_t)omega[x] : 0ull;
 }
 
+// Is entry u -> x kept (reach: the roles adjacent to omega(u))?  With the
+// edge elimination ablated every entry of an active row is kept.
+template <typename M>
+__device__ __forceinline__ bool keeps(const M *__restrict__ omega,
+                                      const uint32_t *__restrict__ f, int32_t x, uint64_t reach,
+                                      const LccTable &tab) {
+    return tab.keep_all || (omega_filtered(omega, f, x) & reach) != 0ull;
+}
+
 // One thread per vertex over ceil(n / 256) * 256 threads: a wavefront's
 // ballot of non-empty role sets (64 vertices) folds to 8 filter bits, one
 // byte of the filter, so every byte is written and no clearing is needed.
@@ -677,9 +692,9 @@ __global__ __launch_bounds__(kBlock) void compact_count_group(const int64_t *__r
             for (int u = 0; u < kUnroll; ++u) cc[u] = col[k + (int64_t)u * G];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
-                c += (omega_filtered(omega, filt, cc[u]) & reach) != 0ull;
+                c += keeps(omega, filt, cc[u], reach, tab);
         }
-        for (; k < e; k += G) c += (omega_filtered(omega, filt, col[k]) & reach) != 0ull;
+        for (; k < e; k += G) c += keeps(omega, filt, col[k], reach, tab);
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, G);
@@ -717,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
             for (int u = 0; u < kUnroll; ++u) cc[u] = col[k0 + (int64_t)u * kWave + lane];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t m = ballot64((omega_filtered(omega, filt, cc[u]) & reach) != 0ull);
+                const uint64_t m = ballot64(keeps(omega, filt, cc[u], reach, tab));
                 if (lane == 0) bits[chunk + u] = m;
                 c += __popcll(m);
             }
@@ -726,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
         for (; k0 < e; k0 += kWave, ++chunk) {
             const int64_t k = k0 + lane;
             const uint64_t m =
-                ballot64(k < e && (omega_filtered(omega, filt, col[k]) & reach) != 0ull);
+                ballot64(k < e && keeps(omega, filt, col[k], reach, tab));
             if (lane == 0) bits[chunk] = m;
             c += __popcll(m);
         }
@@ -772,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_group(
         int32_t x = 0;
         if (k < e) {
             x = col[k];
-            keep = (omega_filtered(omega, filt, x) & reach) != 0ull;
+            keep = keeps(omega, filt, x, reach, tab);
         }
         const uint64_t m = ballot64(keep) & gmask;
         if (keep) {

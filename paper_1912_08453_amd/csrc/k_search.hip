@@ -221,13 +221,44 @@ __device__ __forceinline__ int64_t rl_end(const SearchArgs &a, int32_t y, int q)
 // with the rest.  The handed-on pieces and what the search keeps partition
 // its tree, so together they find a match if there is one; a miss here
 // only says that this search's own part holds none.
+//
+// Counting mode (kCount, match counting and enumeration): the search does
+// not stop at a match.  At the last level every candidate that passes the
+// checks completes a match; their number is added to cs->n (and their maps
+// written to cs->maps while room is left) instead of descending into them,
+// and the search ends when its tree is exhausted.  Splitting partitions the
+// tree in this mode too, so every map is counted exactly once.
 enum { kSearchMiss = 0, kSearchFound = 1 };
 
-template <typename M>
+struct CountSink {
+    unsigned long long n = 0;           // maps counted by this wavefront
+    int32_t *maps = nullptr;            // [cap][n0] or null
+    int64_t cap = 0;
+    unsigned long long *written = nullptr;
+};
+
+// Write the maps completed at the last level: the placed images, with
+// template vertex q at each passing candidate x.
+__device__ __forceinline__ void emit_maps(const SearchArgs &a, CountSink *cs, int32_t img_r,
+                                          int q, int32_t x, bool ok, uint64_t b) {
+    const int lane = lane_id();
+    unsigned long long at = 0;
+    if (lane == 0) at = atomicAdd(cs->written, (unsigned long long)__popcll(b));
+    at = __shfl(at, 0);
+    if ((int64_t)at >= cs->cap) return;
+    const int64_t o = (int64_t)at + __popcll(b & lanemask_lt());
+    const bool w = ok && o < cs->cap;
+    for (int p = 0; p < a.n0; ++p) {
+        const int32_t y = read_lane32(img_r, p);
+        if (w) cs->maps[o * a.n0 + p] = p == q ? x : y;
+    }
+}
+
+template <typename M, bool kCount = false>
 __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
                           const M *__restrict__ om, int32_t v0, int32_t v1,
                           const SplitTask *__restrict__ rt, int64_t task, int plan, bool split,
-                          int32_t &img_r, int32_t &rb_r) {
+                          int32_t &img_r, int32_t &rb_r, CountSink *cs = nullptr) {
     const int lane = lane_id();
     const int k = P->k;
     const int npin = P->npin;
@@ -243,7 +274,13 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
     }
     rb_r = img_r >= 0 ? a.rl_pos[img_r] * a.n0 : 0;
     const int base_lvl = npin + rt_np;
-    if (!rt && k <= npin) return kSearchFound;
+    if (!rt && k <= npin) {
+        if constexpr (kCount) {
+            cs->n += 1;
+            if (cs->maps) emit_maps(a, cs, img_r, -1, 0, lane == 0, 1ull);
+        }
+        return kSearchFound;
+    }
     const int32_t *__restrict__ rlc = a.rl_col;
     const int64_t *__restrict__ rlo = a.rl_off;
     // role-list positions fit in 32 bits (checked when the lists are built)
@@ -397,6 +434,15 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
                 ok = wave_find(rlc, rlo[rbj + q], rlo[rbj + q + 1], x, ok) >= 0;
             }
             const uint64_t b = ballot64(ok);
+            if constexpr (kCount) {
+                if (lvl == k - 1) {
+                    // every passing candidate completes a map
+                    cs->n += (unsigned long long)__popcll(b);
+                    if (cs->maps && b) emit_maps(a, cs, img_r, q, x, ok, b);
+                    if (lane == lvl) cur_r = cur + kWave;
+                    continue;
+                }
+            }
             if (lane == lvl) {
                 pend_r = b;
                 base_r = cur;
@@ -421,12 +467,15 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
     }
 }
 
-// Certify the head roles of a found embedding (NLCC).
+// Certify the head roles of a found embedding (NLCC); with work aggregation
+// off, only the root's role.
 template <typename M>
-__device__ void certify_roles(const SearchPlan *__restrict__ P, int32_t img_r, M *sat) {
+__device__ void certify_roles(const SearchArgs &a, const SearchPlan *__restrict__ P,
+                              int32_t img_r, M *sat) {
     const int lane = lane_id();
-    if (((P->vmask >> lane) & 1ull) && ((P->certify >> lane) & 1ull))
-        atomic_or_elem<M>(sat, img_r, 1ull << lane);
+    const bool mine = a.aggregate ? (((P->vmask >> lane) & 1ull) && ((P->certify >> lane) & 1ull))
+                                  : lane == P->pin[0];
+    if (mine) atomic_or_elem<M>(sat, img_r, 1ull << lane);
 }
 
 // An edge is certified through the bit of either of its two compacted
@@ -671,7 +720,9 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                 if (found) {
                     ++npos;
                     tpos += c1 - c0;
-                    if (a.mode == 1) {
+                    if (a.mode == 1 && !a.aggregate) {
+                        if (lane == h) atomic_or_elem<M>(sat, img, 1ull << h);
+                    } else if (a.mode == 1) {
                         certify_match<M>(a, P, img, sat);
                         if (a.expand) {
                             const uint64_t c2 = wall_clock64();
@@ -679,7 +730,7 @@ __global__ __launch_bounds__(kSearchBlock) void vertex_search_kernel(const int32
                             texp += wall_clock64() - c2;
                         }
                     } else {
-                        certify_roles<M>(P, img, sat);
+                        certify_roles<M>(a, P, img, sat);
                     }
                     tcert += wall_clock64() - c1;
                 } else {
@@ -872,6 +923,12 @@ __device__ bool edge_query(const SearchArgs &a, const SearchPlan *__restrict__ P
     }
     ++qc.npos;
     qc.tpos += c1 - c0;
+    if (!a.aggregate) {
+        // only the edge this query was asked about
+        if (lane_id() == 0) certify_pair(a, u, P->pin[0], w, P->pin[1]);
+        qc.tcert += wall_clock64() - c1;
+        return true;
+    }
     certify_match<M>(a, P, img, cert);
     if (a.expand) {
         const uint64_t c2 = wall_clock64();
@@ -1063,6 +1120,128 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                        tasks, n_tasks, c_rp, c_col, c_off, rp, omega, tab, edge_bits);
 }
 
+// ---------------------------------------------- match counting/enumeration
+// Count tasks: compacted entries u -> w whose ends hold the pinned roles
+// (qa at u, qb at w).  Every map puts its template edge (qa, qb) on exactly
+// one such entry, so counting from each task once counts every map once.
+template <typename M>
+__global__ __launch_bounds__(kSearchBlock) void count_tasks_kernel(
+    int64_t c_m, const int32_t *__restrict__ c_own, const int32_t *__restrict__ c_col,
+    const M *__restrict__ om, int qa, int qb, int32_t *eu, int32_t *ew, int32_t *n_out,
+    int64_t cap) {
+    const int lane = lane_id();
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < c_m;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = base + threadIdx.x;
+        bool p = false;
+        int32_t u = 0, w = 0;
+        if (k < c_m) {
+            u = c_own[k];
+            w = c_col[k];
+            p = (((uint64_t)om[u] >> qa) & 1ull) && (((uint64_t)om[w] >> qb) & 1ull);
+        }
+        const uint64_t m = ballot64(p);
+        if (!m) continue;
+        int pos = 0;
+        if (lane == 0) pos = atomicAdd(n_out, __popcll(m));
+        pos = __shfl(pos, 0);
+        if (p) {
+            const int64_t o = pos + __popcll(m & lanemask_lt());
+            if (o < cap) {
+                eu[o] = u;
+                ew[o] = w;
+            }
+        }
+    }
+}
+
+template <typename M>
+void launch_count_tasks(hipStream_t s, int64_t c_m, const int32_t *c_own, const int32_t *c_col,
+                        const M *omega, int qa, int qb, int32_t *eu, int32_t *ew, int32_t *n_out,
+                        int64_t cap) {
+    if (c_m <= 0) return;
+    int64_t grid = (c_m + kSearchBlock - 1) / kSearchBlock;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL(count_tasks_kernel<M>, dim3((unsigned)grid), dim3(kSearchBlock), 0, s, c_m,
+                       c_own, c_col, omega, qa, qb, eu, ew, n_out, cap);
+}
+
+// One wavefront per task (chunks of a.task_chunk per fetch), the full
+// template pinned at the task's entry; searches past the step budget hand
+// on parts of their tree as split tasks (a.split_out).
+template <typename M>
+__global__ __launch_bounds__(kSearchBlock) void count_search_kernel(
+    const int32_t *eu, const int32_t *ew, int64_t n_tasks, const M *om, const int32_t *plan_id,
+    SearchArgs a, int32_t *maps, int64_t cap, unsigned long long *written,
+    unsigned long long *total) {
+    const int lane = lane_id();
+    CountSink cs;
+    cs.maps = maps;
+    cs.cap = cap;
+    cs.written = written;
+    const SearchPlan *P = a.plans + plan_id[0];
+    for (;;) {
+        int t0 = 0;
+        if (lane == 0) t0 = atomicAdd(a.task_counter, a.task_chunk);
+        t0 = __shfl(t0, 0);
+        if ((int64_t)t0 >= n_tasks) break;
+        const int64_t t1 =
+            (int64_t)t0 + a.task_chunk < n_tasks ? (int64_t)t0 + a.task_chunk : n_tasks;
+        for (int64_t t = t0; t < t1; ++t) {
+            int32_t img = 0, rb = 0;
+            dfs_search<M, true>(a, P, om, eu[t], ew[t], nullptr, t, 0, a.split_budget > 0, img,
+                                rb, &cs);
+        }
+    }
+    if (lane == 0 && cs.n) atomicAdd(total, cs.n);
+}
+
+template <typename M>
+__global__ __launch_bounds__(kSearchBlock) void count_split_kernel(
+    const SplitTask *tasks, int64_t n_tasks, const int32_t *eu, const int32_t *ew, const M *om,
+    const int32_t *plan_id, SearchArgs a, int32_t *maps, int64_t cap,
+    unsigned long long *written, unsigned long long *total) {
+    const int lane = lane_id();
+    CountSink cs;
+    cs.maps = maps;
+    cs.cap = cap;
+    cs.written = written;
+    const SearchPlan *P = a.plans + plan_id[0];
+    for (;;) {
+        int i = 0;
+        if (lane == 0) i = atomicAdd(a.task_counter, 1);
+        i = __shfl(i, 0);
+        if ((int64_t)i >= n_tasks) break;
+        const SplitTask *rt = tasks + i;
+        const int64_t t = rt->t;
+        int32_t img = 0, rb = 0;
+        dfs_search<M, true>(a, P, om, eu[t], ew[t], rt, t, 0, a.split_budget > 0, img, rb, &cs);
+    }
+    if (lane == 0 && cs.n) atomicAdd(total, cs.n);
+}
+
+template <typename M>
+void launch_count_search(hipStream_t s, const int32_t *eu, const int32_t *ew, int64_t n_tasks,
+                         const M *omega, const int32_t *plan_id, const SearchArgs &a,
+                         int32_t *maps, int64_t cap, unsigned long long *written,
+                         unsigned long long *total, int grid) {
+    if (n_tasks <= 0) return;
+    hipLaunchKernelGGL(count_search_kernel<M>, dim3(grid), dim3(kSearchBlock), 0, s, eu, ew,
+                       n_tasks, omega, plan_id, a, maps, cap, written, total);
+}
+
+template <typename M>
+void launch_count_split(hipStream_t s, const SplitTask *tasks, int64_t n_tasks, const int32_t *eu,
+                        const int32_t *ew, const M *omega, const int32_t *plan_id,
+                        const SearchArgs &a, int32_t *maps, int64_t cap,
+                        unsigned long long *written, unsigned long long *total, int grid) {
+    if (n_tasks <= 0) return;
+    int64_t g = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
+    if (g > grid) g = grid;
+    hipLaunchKernelGGL(count_split_kernel<M>, dim3((unsigned)g), dim3(kSearchBlock), 0, s, tasks,
+                       n_tasks, eu, ew, omega, plan_id, a, maps, cap, written, total);
+}
+
 #define PM_INSTANTIATE_SEARCH(M)                                                                  \
     template void launch_role_count<M>(hipStream_t, const int32_t *, int64_t, const int64_t *,    \
                                        const int32_t *, const M *, int, int64_t *, int32_t *);    \
@@ -1087,7 +1266,18 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
                                         const int32_t *, int32_t, const SearchArgs &, int);       \
     template void launch_active_edges<M>(hipStream_t, const int32_t *, int64_t, const int64_t *,  \
                                          const int32_t *, const int32_t *, const int64_t *,       \
-                                         const M *, const LccTable &, uint64_t *);
+                                         const M *, const LccTable &, uint64_t *);                \
+    template void launch_count_tasks<M>(hipStream_t, int64_t, const int32_t *, const int32_t *,   \
+                                        const M *, int, int, int32_t *, int32_t *, int32_t *,     \
+                                        int64_t);                                                 \
+    template void launch_count_search<M>(hipStream_t, const int32_t *, const int32_t *, int64_t, \
+                                         const M *, const int32_t *, const SearchArgs &,          \
+                                         int32_t *, int64_t, unsigned long long *,                \
+                                         unsigned long long *, int);                              \
+    template void launch_count_split<M>(hipStream_t, const SplitTask *, int64_t, const int32_t *, \
+                                        const int32_t *, const M *, const int32_t *,              \
+                                        const SearchArgs &, int32_t *, int64_t,                   \
+                                        unsigned long long *, unsigned long long *, int);
 
 PM_INSTANTIATE_SEARCH(uint8_t)
 PM_INSTANTIATE_SEARCH(uint16_t)

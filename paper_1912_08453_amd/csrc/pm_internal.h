@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include "pm.h"
+
 namespace pm {
 
 constexpr int kWave = 64;            // CDNA wavefront width
@@ -27,6 +29,10 @@ constexpr int kNumBins = 4;          // small, mid, wave, hub
 struct LccTable {
     int32_t n0;
     int32_t ncount;
+    int32_t any;                    // candidate-set rule: q stays while SOME
+                                    // template neighbour of q is covered
+    int32_t keep_all;               // compaction keeps every entry of an
+                                    // active row (edge elimination ablated)
     uint64_t adj[kMaxK];            // adj(q)
     uint64_t cmask[kMaxCount];      // adj(q) restricted to one label L
     int32_t cq[kMaxCount];          // q of the rule
@@ -281,6 +287,8 @@ struct SearchArgs {
     SplitTask *split_out;
     int32_t *split_n;
     int64_t split_cap;
+    int32_t aggregate;              // 0: a found embedding certifies only the
+                                    // query it answers (work aggregation off)
 };
 
 // Role lists of the vertices in tasks over the compacted subgraph: pass 1
@@ -379,6 +387,39 @@ void launch_mlp_grad(hipStream_t s, const float *w, const float *x, const float 
                      float *partial, float *partial_loss, float *grad, float *loss);
 void launch_adam(hipStream_t s, float *w, const float *grad, float *m, float *v, float lr,
                  float bc1, float bc2);
+
+// ---- state import, reuse, no-allocation scratch -------------------------------
+template <typename M>
+void launch_and_state(hipStream_t s, int64_t n, M *omega, const uint64_t *state);
+template <typename M>
+void launch_known_roles(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const M *omega,
+                        const uint64_t *known, M *cert);
+void launch_known_edges(hipStream_t s, int64_t c_m, const int32_t *c_own, const int32_t *c_off,
+                        const int64_t *rp, const uint64_t *known, uint64_t *c_cert);
+void launch_label_degsum(hipStream_t s, int64_t n, const int64_t *rp, const void *labels,
+                         int label_bytes, unsigned long long *sum, int64_t hist_len);
+
+// ---- match counting ----------------------------------------------------------
+// Count tasks: compacted entries u -> w with qa in omega(u) and qb in
+// omega(w), appended to eu/ew via *n_out (zeroed by the caller; at most cap
+// written).
+template <typename M>
+void launch_count_tasks(hipStream_t s, int64_t c_m, const int32_t *c_own, const int32_t *c_col,
+                        const M *omega, int qa, int qb, int32_t *eu, int32_t *ew, int32_t *n_out,
+                        int64_t cap);
+// Every map of the full template with plan *plan_id's pins at (eu[t],
+// ew[t]) (or within split task ranges) is counted into *total; up to cap
+// of them are written to maps[cap][n0] through *written.
+template <typename M>
+void launch_count_search(hipStream_t s, const int32_t *eu, const int32_t *ew, int64_t n_tasks,
+                         const M *omega, const int32_t *plan_id, const SearchArgs &a,
+                         int32_t *maps, int64_t cap, unsigned long long *written,
+                         unsigned long long *total, int grid);
+template <typename M>
+void launch_count_split(hipStream_t s, const SplitTask *tasks, int64_t n_tasks, const int32_t *eu,
+                        const int32_t *ew, const M *omega, const int32_t *plan_id,
+                        const SearchArgs &a, int32_t *maps, int64_t cap,
+                        unsigned long long *written, unsigned long long *total, int grid);
 
 void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t n, uint64_t v);
 void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);

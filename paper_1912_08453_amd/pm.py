@@ -23,6 +23,10 @@ PM_VALIDATE = 2
 PM_ORDER_FIXED = 0
 PM_ORDER_GIVEN = 1
 PM_ORDER_LEARNED = 2
+PM_MODE_FULL = 0
+PM_MODE_CANDIDATE = 1
+PM_ABLATE_EDGE_ELIMINATION = 1
+PM_ABLATE_WORK_AGGREGATION = 2
 MAX_CONSTRAINTS = 64
 MLP_FEATURES = 12
 MLP_OUTPUTS = 2
@@ -31,14 +35,15 @@ MLP_PARAMS = 5122
 ERRORS = {
     -1: "PM_ERR_INVALID_ARG", -2: "PM_ERR_HIP", -3: "PM_ERR_GRAPH", -4: "PM_ERR_TEMPLATE",
     -5: "PM_ERR_NO_GRAPH", -6: "PM_ERR_CAPACITY", -7: "PM_ERR_OOM", -8: "PM_ERR_NOT_FOUND",
-    -9: "PM_ERR_MODEL",
+    -9: "PM_ERR_MODEL", -10: "PM_ERR_WORKSPACE",
 }
 
 # exported symbols declared in include/pm.h
 SYMBOLS = ["pm_last_error", "pm_version", "pm_create", "pm_destroy", "pm_load_graph",
            "pm_unload_graph", "pm_load_templates", "pm_template_constraints",
            "pm_inspect_template", "pm_prune", "pm_load_model", "pm_mlp_forward", "pm_mlp_grad",
-           "pm_mlp_train", "pm_set_param", "pm_get_param"]
+           "pm_mlp_train", "pm_set_param", "pm_get_param", "pm_export_state",
+           "pm_import_state", "pm_workspace_size", "pm_set_workspace", "pm_count_matches"]
 
 
 class PMError(RuntimeError):
@@ -72,7 +77,10 @@ class pm_options(ctypes.Structure):
                 ("order", ctypes.c_int32 * MAX_CONSTRAINTS), ("stop_after", ctypes.c_int32),
                 ("batch_streams", ctypes.c_int32), ("learned_min_score", ctypes.c_float),
                 ("learned_stop", ctypes.c_int32), ("trace_cap", ctypes.c_int32),
-                ("trace", ctypes.POINTER(pm_trace_entry)), ("reserved", ctypes.c_int32 * 4)]
+                ("trace", ctypes.POINTER(pm_trace_entry)), ("mode", ctypes.c_int32),
+                ("ablate", ctypes.c_uint32), ("init_state", ctypes.c_void_p),
+                ("skip_mask", ctypes.c_uint64), ("known_roles", ctypes.c_void_p),
+                ("known_edges", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 4)]
 
 
 class pm_stats(ctypes.Structure):
@@ -85,23 +93,32 @@ class pm_stats(ctypes.Structure):
                  "candidate_entries", "vertex_queries", "edge_queries", "result_vertices",
                  "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries", "expand_scans",
                  "expand_candidates", "expand_valid", "first_sweep_bytes", "witness_edges",
-                 "split_tasks")]
+                 "split_tasks")] + \
+               [("done_mask", ctypes.c_uint64), ("workspace_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class pm_match_count(ctypes.Structure):
+    _fields_ = [("maps", ctypes.c_uint64), ("automorphisms", ctypes.c_uint64),
+                ("subgraphs", ctypes.c_uint64), ("written", ctypes.c_int64),
+                ("roots", ctypes.c_int64), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
-def load_library(path: str = None):
-    """Load libpm.so (or the build named by PM_LIBRARY); raises if it is
-    missing (no CPU fallback exists)."""
+def load_library():
+    """Load the in-tree libpm.so; raises if it is missing (no CPU fallback
+    exists)."""
     global _lib
     if _lib is not None:
         return _lib
-    if path is None:
-        path = os.environ.get("PM_LIBRARY", LIB_PATH)
+    path = LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"libpm.so not built at {path}; run __graft_entry__.build()")
     # torch ships its own HIP runtime; loading it first makes libpm bind to
@@ -128,6 +145,14 @@ def load_library(path: str = None):
     lib.pm_mlp_forward.argtypes = [P, P, P, I64, P]
     lib.pm_mlp_grad.argtypes = [P, P, P, P, I64, P, P]
     lib.pm_mlp_train.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, P]
+    lib.pm_export_state.argtypes = [P, I32, I32, ctypes.POINTER(pm_options), P,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    lib.pm_import_state.argtypes = [P, I32, P, ctypes.c_uint64, P, P, ctypes.POINTER(pm_options),
+                                    ctypes.POINTER(pm_stats)]
+    lib.pm_workspace_size.argtypes = [P, I32, I32, ctypes.POINTER(pm_options),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    lib.pm_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+    lib.pm_count_matches.argtypes = [P, I32, P, P, I64, ctypes.POINTER(pm_match_count)]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -236,22 +261,14 @@ class PM:
         return _unpack_constraints(cnt.value, kinds, ne, heads, edges)
 
     # ------------------------------------------------------------- prune
-    def prune(self, first_id: int, count: int = 1, order=None,
-              stop_after: int = -1, role_mask=None, edge_bits=None, batch_streams: int = 0,
-              learned_min_score: Optional[float] = None, trace: bool = False):
-        """Returns (role_mask uint64-as-int64 tensor [count, n], edge_bits
-        [count, ceil(m/64)], stats dict); with trace=True the stats dict also
-        holds "trace", the list of per-step records.  order: None (fixed),
-        "learned" (greedy by the loaded model), or a permutation."""
-        torch = self.torch
-        words = (self.m + 63) // 64
-        if role_mask is None:
-            role_mask = torch.empty((count, max(self.n, 1)), dtype=torch.int64, device=self.device)
-        if edge_bits is None:
-            edge_bits = torch.empty((count, max(words, 1)), dtype=torch.int64, device=self.device)
+    def _options(self, order=None, stop_after=-1, batch_streams=0, learned_min_score=None,
+                 mode=PM_MODE_FULL, ablate=0, init_state=None, skip_mask=0, known_roles=None,
+                 known_edges=None):
         opt = pm_options()
         opt.stop_after = stop_after
         opt.batch_streams = batch_streams
+        opt.mode = int(mode)
+        opt.ablate = int(ablate)
         if isinstance(order, str):
             if order != "learned":
                 raise ValueError("order must be None, 'learned' or a permutation")
@@ -264,6 +281,40 @@ class PM:
         if learned_min_score is not None:
             opt.learned_stop = 1
             opt.learned_min_score = float(learned_min_score)
+        for name, t in (("init_state", init_state), ("known_roles", known_roles),
+                        ("known_edges", known_edges)):
+            if t is not None:
+                self._check_device_i64(t, name)
+                setattr(opt, name, t.data_ptr())
+        opt.skip_mask = int(skip_mask) & 0xFFFFFFFFFFFFFFFF
+        return opt
+
+    def _check_device_i64(self, t, name):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.int64 and t.is_contiguous()
+                and t.device == self.device):
+            raise ValueError(f"{name} must be a contiguous int64 tensor on {self.device}")
+
+    def prune(self, first_id: int, count: int = 1, order=None,
+              stop_after: int = -1, role_mask=None, edge_bits=None, batch_streams: int = 0,
+              learned_min_score: Optional[float] = None, trace: bool = False,
+              mode: int = PM_MODE_FULL, ablate: int = 0, init_state=None, skip_mask: int = 0,
+              known_roles=None, known_edges=None):
+        """Returns (role_mask uint64-as-int64 tensor [count, n], edge_bits
+        [count, ceil(m/64)], stats dict); with trace=True the stats dict also
+        holds "trace", the list of per-step records.  order: None (fixed),
+        "learned" (greedy by the loaded model), or a permutation.  mode:
+        PM_MODE_FULL or PM_MODE_CANDIDATE; ablate: PM_ABLATE_* bits;
+        init_state / known_roles [count, n] and known_edges [count, words]:
+        device int64 tensors (see pm.h)."""
+        torch = self.torch
+        words = (self.m + 63) // 64
+        if role_mask is None:
+            role_mask = torch.empty((count, max(self.n, 1)), dtype=torch.int64, device=self.device)
+        if edge_bits is None:
+            edge_bits = torch.empty((count, max(words, 1)), dtype=torch.int64, device=self.device)
+        opt = self._options(order, stop_after, batch_streams, learned_min_score, mode, ablate,
+                            init_state, skip_mask, known_roles, known_edges)
         tr = None
         if trace:
             tr = (pm_trace_entry * (MAX_CONSTRAINTS + 1))()
@@ -278,6 +329,82 @@ class PM:
         if tr is not None:
             out["trace"] = [tr[i].as_dict() for i in range(int(st.trace_entries))]
         return role_mask[:, :self.n], edge_bits[:, :words], out
+
+    # ------------------------------------------------------ state, counting
+    def export_state(self, tid: int, stop_after: int = -1, order=None, learned_min_score=None,
+                     state=None):
+        """(state int64 tensor [n] on the device, done_mask) after the first
+        LCC fixpoint and stop_after constraints (< 0: all)."""
+        torch = self.torch
+        if state is None:
+            state = torch.empty(max(self.n, 1), dtype=torch.int64, device=self.device)
+        opt = self._options(order, stop_after, 0, learned_min_score)
+        done = ctypes.c_uint64()
+        _check(self.lib, self.lib.pm_export_state(self.h, tid, int(stop_after), ctypes.byref(opt),
+                                                  ctypes.c_void_p(state.data_ptr()),
+                                                  ctypes.byref(done)))
+        return state[:self.n], int(done.value)
+
+    def import_state(self, tid: int, state, done_mask: int, order=None, stop_after: int = -1,
+                     learned_min_score=None, role_mask=None, edge_bits=None):
+        """Resume from an exported state; returns (role_mask [1, n],
+        edge_bits [1, words], stats)."""
+        torch = self.torch
+        words = (self.m + 63) // 64
+        self._check_device_i64(state, "state")
+        if role_mask is None:
+            role_mask = torch.empty((1, max(self.n, 1)), dtype=torch.int64, device=self.device)
+        if edge_bits is None:
+            edge_bits = torch.empty((1, max(words, 1)), dtype=torch.int64, device=self.device)
+        opt = self._options(order, stop_after, 0, learned_min_score)
+        st = pm_stats()
+        _check(self.lib, self.lib.pm_import_state(
+            self.h, tid, ctypes.c_void_p(state.data_ptr()), ctypes.c_uint64(done_mask & 0xFFFFFFFFFFFFFFFF),
+            ctypes.c_void_p(role_mask.data_ptr()), ctypes.c_void_p(edge_bits.data_ptr()),
+            ctypes.byref(opt), ctypes.byref(st)))
+        return role_mask[:, :self.n], edge_bits[:, :words], st.as_dict()
+
+    def workspace_size(self, first_id: int, count: int = 1, batch_streams: int = 0) -> int:
+        opt = self._options(batch_streams=batch_streams)
+        b = ctypes.c_size_t()
+        _check(self.lib, self.lib.pm_workspace_size(self.h, first_id, count, ctypes.byref(opt),
+                                                    ctypes.byref(b)))
+        return int(b.value)
+
+    def set_workspace(self, ws) -> None:
+        """Use the device tensor ws (any dtype, contiguous; kept alive by
+        this object) for all scratch; None returns to library-owned
+        scratch."""
+        if ws is None:
+            _check(self.lib, self.lib.pm_set_workspace(self.h, None, 0))
+            self._ws = None
+            return
+        _check(self.lib, self.lib.pm_set_workspace(self.h, ctypes.c_void_p(ws.data_ptr()),
+                                                   ws.numel() * ws.element_size()))
+        self._ws = ws
+
+    def count_matches(self, tid: int, state=None, cap: int = 0):
+        """Match count of template tid within state ([n] or [1, n] device
+        int64 role masks, None: label roles).  With cap > 0 also returns up
+        to cap maps as an int32 tensor [k, n0]."""
+        torch = self.torch
+        n0 = len(self.templates[tid].labels)
+        sp = None
+        if state is not None:
+            st_t = state.reshape(-1)
+            self._check_device_i64(st_t, "state")
+            sp = ctypes.c_void_p(st_t.data_ptr())
+        maps = None
+        mp = None
+        if cap > 0:
+            maps = torch.empty((cap, n0), dtype=torch.int32, device=self.device)
+            mp = ctypes.c_void_p(maps.data_ptr())
+        out = pm_match_count()
+        _check(self.lib, self.lib.pm_count_matches(self.h, tid, sp, mp, int(cap), ctypes.byref(out)))
+        res = out.as_dict()
+        if maps is not None:
+            res["maps_out"] = maps[:out.written]
+        return res
 
     # ------------------------------------------------------------ tuning
     TUNING = ("expand", "expand_max", "witness", "relist", "edge_chunk", "edge_stripes",

@@ -125,10 +125,16 @@ int main(void) {
     printf("pm_template %zu\n", sizeof(pm_template));
     F(pm_options, stop_after); F(pm_options, batch_streams); F(pm_options, learned_min_score);
     F(pm_options, learned_stop); F(pm_options, trace_cap); F(pm_options, trace);
+    F(pm_options, mode); F(pm_options, ablate); F(pm_options, init_state);
+    F(pm_options, skip_mask); F(pm_options, known_roles); F(pm_options, known_edges);
     F(pm_options, reserved);
     F(pm_trace_entry, roles_before); F(pm_trace_entry, ms); F(pm_trace_entry, score);
     F(pm_trace_entry, predicted); F(pm_trace_entry, features);
     F(pm_stats, lcc_sweeps); F(pm_stats, trace_entries); F(pm_stats, split_tasks);
+    F(pm_stats, done_mask); F(pm_stats, workspace_bytes);
+    printf("pm_match_count %zu\n", sizeof(pm_match_count));
+    F(pm_match_count, maps); F(pm_match_count, automorphisms); F(pm_match_count, subgraphs);
+    F(pm_match_count, written); F(pm_match_count, roots); F(pm_match_count, ms_total);
     return 0;
 }
 ''')
@@ -145,6 +151,7 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
     assert c["pm_trace_entry"] == ctypes.sizeof(pm.pm_trace_entry)
     assert c["pm_stats"] == ctypes.sizeof(pm.pm_stats)
     assert c["pm_template"] == ctypes.sizeof(pm.pm_template)
+    assert c["pm_match_count"] == ctypes.sizeof(pm.pm_match_count)
     for key, v in c.items():
         if "." in key:
             struct, field = key.split(".")
