@@ -419,6 +419,23 @@ int pm_workspace_size(pm_ctx *ctx, int32_t first_id, int32_t count, const pm_opt
    runs. */
 int pm_set_workspace(pm_ctx *ctx, void *ws, size_t bytes);
 
+/* ---- prune without allocation ---------------------------------------------------
+   For callers that cannot allocate device memory (code under stream
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   prune as pm_prune with count = 1, with all scratch taken from a static
+   device array of PM_NOALLOC_SCRATCH_BYTES bytes that the library holds on
+   every device it runs on until the process ends.  No hipMalloc, hipFree or
+   other allocating call is made.  The swap-scan table and the split-task
+   lists use smaller sizes here (work-saving settings; results are the
+   same).  PM_ERR_WORKSPACE when pm_workspace_size for this template exceeds
+   the array.  All calls on one device share the array: calls that overlap
+   on one device (two host threads, or two contexts on different streams)
+   race and give undefined results; serialise them.  The array keeps the
+   last call's contents; every call initialises what it reads. */
+#define PM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int pm_prune_noalloc(pm_ctx *ctx, int32_t id, uint64_t *role_mask, uint64_t *edge_bits,
+                     const pm_options *opt, pm_stats *stats);
+
 /* ---- match counting and enumeration on the pruned graph --------------------
    Match enumeration and counting run on the reduced graph that pruning
    leaves (termination and output section): a full-template walk with

@@ -205,6 +205,7 @@ struct pm_ctx {
     // caller-owned workspace (pm_set_workspace); null: library-owned scratch
     char *ws = nullptr;
     size_t ws_bytes = 0;
+    void *noalloc = nullptr;             // this device's static scratch array
     // learned-order model and the workspace of its training kernels
     DevBuf model;
     bool has_model = false;
@@ -1472,6 +1473,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
         c->stream = (hipStream_t)hip_stream;
         try {
             set_device(c);
+            // the no-allocation prune's static scratch of this device
+            PM_HIP(noalloc_scratch(device, &c->noalloc));
             hipDeviceProp_t prop;
             PM_HIP(hipGetDeviceProperties(&prop, device));
             c->grid_search = std::max(256, prop.multiProcessorCount * 8);
@@ -1761,6 +1764,19 @@ int pm_set_workspace(pm_ctx *c, void *ws, size_t bytes) {
         }
         c->ws = ws ? static_cast<char *>(ws) : nullptr;
         c->ws_bytes = ws ? bytes : 0;
+    });
+}
+
+int pm_prune_noalloc(pm_ctx *c, int32_t id, uint64_t *role_mask, uint64_t *edge_bits,
+                     const pm_options *opt, pm_stats *stats) {
+    return guarded([&] {
+        if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
+        if (!role_mask || !edge_bits) throw Error(PM_ERR_INVALID_ARG, "null output");
+        if (!c->noalloc) throw Error(PM_ERR_HIP, "no static scratch on this device");
+        NoAlloc na;
+        na.base = static_cast<char *>(c->noalloc);
+        na.bytes = kNoAllocBytes;
+        prune_impl(c, id, 1, role_mask, edge_bits, opt, stats, &na);
     });
 }
 

@@ -1,4 +1,5 @@
-// State import and reuse kernels for gfx950.
+// State import and reuse kernels for gfx950, and the static scratch array of
+// the no-allocation prune.
 //
 // The pruning state is the role-set array omega; the edge state is derived
 // from it.  Any state that still holds the complete set is a valid place to
@@ -8,6 +9,8 @@
 // state in (omega &= state), seed the final search with roles and edges
 // already known to be in the complete set, and give the per-label degree
 // sums that bound scratch sizes.
+#include <mutex>
+
 #include "device_util.h"
 #include "pm_internal.h"
 
@@ -109,6 +112,36 @@ void launch_label_degsum(hipStream_t s, int64_t n, const int64_t *rp, const void
     if (n <= 0) return;
     hipLaunchKernelGGL(label_degsum_kernel, dim3((unsigned)grid_for(n, 4096)), dim3(kStateBlock),
                        0, s, n, rp, labels, label_bytes, sum, hist_len);
+}
+
+// ---- static scratch of the no-allocation prune -------------------------------
+// One array per device, held until the process ends.  Host code never uses
+// the array's name as an address: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 #define PM_INSTANTIATE_STATE(M)                                                                 \

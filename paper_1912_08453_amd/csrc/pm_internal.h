@@ -398,6 +398,10 @@ void launch_known_edges(hipStream_t s, int64_t c_m, const int32_t *c_own, const 
                         const int64_t *rp, const uint64_t *known, uint64_t *c_cert);
 void launch_label_degsum(hipStream_t s, int64_t n, const int64_t *rp, const void *labels,
                          int label_bytes, unsigned long long *sum, int64_t hist_len);
+constexpr size_t kNoAllocBytes = PM_NOALLOC_SCRATCH_BYTES;
+// Device address of this device's static no-allocation scratch array
+// (kNoAllocBytes bytes); the device must be current.
+hipError_t noalloc_scratch(int device, void **ptr);
 
 // ---- match counting ----------------------------------------------------------
 // Count tasks: compacted entries u -> w with qa in omega(u) and qb in

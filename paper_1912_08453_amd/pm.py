@@ -27,6 +27,7 @@ PM_MODE_FULL = 0
 PM_MODE_CANDIDATE = 1
 PM_ABLATE_EDGE_ELIMINATION = 1
 PM_ABLATE_WORK_AGGREGATION = 2
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MAX_CONSTRAINTS = 64
 MLP_FEATURES = 12
 MLP_OUTPUTS = 2
@@ -43,7 +44,8 @@ SYMBOLS = ["pm_last_error", "pm_version", "pm_create", "pm_destroy", "pm_load_gr
            "pm_unload_graph", "pm_load_templates", "pm_template_constraints",
            "pm_inspect_template", "pm_prune", "pm_load_model", "pm_mlp_forward", "pm_mlp_grad",
            "pm_mlp_train", "pm_set_param", "pm_get_param", "pm_export_state",
-           "pm_import_state", "pm_workspace_size", "pm_set_workspace", "pm_count_matches"]
+           "pm_import_state", "pm_workspace_size", "pm_set_workspace", "pm_prune_noalloc",
+           "pm_count_matches"]
 
 
 class PMError(RuntimeError):
@@ -152,6 +154,8 @@ def load_library():
     lib.pm_workspace_size.argtypes = [P, I32, I32, ctypes.POINTER(pm_options),
                                       ctypes.POINTER(ctypes.c_size_t)]
     lib.pm_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+    lib.pm_prune_noalloc.argtypes = [P, I32, P, P, ctypes.POINTER(pm_options),
+                                     ctypes.POINTER(pm_stats)]
     lib.pm_count_matches.argtypes = [P, I32, P, P, I64, ctypes.POINTER(pm_match_count)]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = ctypes.c_int
@@ -382,6 +386,18 @@ class PM:
         _check(self.lib, self.lib.pm_set_workspace(self.h, ctypes.c_void_p(ws.data_ptr()),
                                                    ws.numel() * ws.element_size()))
         self._ws = ws
+
+    def prune_noalloc(self, tid: int, role_mask, edge_bits, order=None, stop_after: int = -1,
+                      learned_min_score=None):
+        """pm_prune_noalloc: outputs are caller-owned device tensors
+        [1, n] / [1, words]; returns the stats dict."""
+        opt = self._options(order, stop_after, 0, learned_min_score)
+        st = pm_stats()
+        _check(self.lib, self.lib.pm_prune_noalloc(self.h, tid,
+                                                   ctypes.c_void_p(role_mask.data_ptr()),
+                                                   ctypes.c_void_p(edge_bits.data_ptr()),
+                                                   ctypes.byref(opt), ctypes.byref(st)))
+        return st.as_dict()
 
     def count_matches(self, tid: int, state=None, cap: int = 0):
         """Match count of template tid within state ([n] or [1, n] device

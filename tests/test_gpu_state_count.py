@@ -189,7 +189,10 @@ def automorphisms(t):
 def test_match_count_and_enumeration(pmmod, torch_dev, kind, s):
     torch, dev = torch_dev
     g, t = get_case(kind, s)
-    cnt, maps = oracle.enumerate_maps(g.row_ptr, g.col, g.labels, t.labels, t.edges)
+    cnt, _ = oracle.enumerate_maps(g.row_ptr, g.col, g.labels, t.labels, t.edges, cap=1)
+    cnt, maps = oracle.enumerate_maps(g.row_ptr, g.col, g.labels, t.labels, t.edges,
+                                      cap=max(cnt, 1))
+    log(f"count {kind} {s}: {cnt} maps")
     ctx = load(pmmod, torch_dev, g)
     tid = ctx.load_templates([t])
     r, _, _ = ctx.prune(tid)
