@@ -1,18 +1,31 @@
 #!/usr/bin/env python3
-"""Benchmark of the complete-set prune on one MI355X.
+"""Benchmark of complete-set pruning (constraint checking) on one MI355X.
 
-Workload (one step): prune an R-MAT scale-22 graph (Graph500 parameters,
-edge factor 16, undirected, log2-degree labels) to the complete set of a
-6-vertex template (triangle and 4-cycle sharing an edge, a pendant, one
-repeated label), through the C ABI: first LCC sweep, candidate-subgraph
-compaction, LCC fixpoint, every non-local constraint, and the exact
-full-template step.  Inputs are resident in HBM before timing starts.
+Default workload (one step): R-MAT scale 26 (Graph500 parameters, edge
+factor 16, 67.1 M vertices, 2.1 G directed CSR entries, log2-degree uint8
+labels), the 8-vertex two-cycle template with a repeated-label pair four
+hops apart and all its connected 1- and 2-edge-deletion relaxations (28
+templates in all), pruned to their complete sets through the C ABI:
 
-Prints one JSON line: metric GTEPS = directed CSR entries / time-to-fixpoint,
-with time-to-fixpoint, per-phase device times, a roofline entry for the
-first LCC sweep kernel and the CPU oracle's rate on a bounded sample.
+  * the neighbour-label count index (one streaming pass over the CSR; the
+    first LCC sweep of every template reads it), then
+  * one batched pm_prune call for all 28 templates on 4 concurrent streams
+    with the learned constraint order: first LCC sweep, compaction, LCC
+    fixpoint, every non-local constraint, the exact final search.
+
+Inputs are resident in HBM before timing starts.  The plain path -- the
+same index pass, then one pm_prune call per template with the fixed order
+-- is timed beside it, and every template's output must be identical.
+
+Prints one JSON line: metric GTEPS = directed CSR entries x templates /
+time-to-fixpoint of the step, the roofline of the CSR-streaming kernel (the
+count-index pass), the CPU oracle's rate on a bounded sample, and legs on a
+resident scale-22 graph (single template, 64-template batch, learned order
+with ablations, incremental search, match counting, exploratory search,
+topology sweep and design ablations).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +35,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+GRAPH500 = (0.57, 0.19, 0.19)
+CHAKRABARTI = (0.45, 0.15, 0.15)
+UNIFORM = (0.25, 0.25, 0.25)
 
 
 def log(msg):
@@ -33,40 +49,26 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--graph-seed", type=int, default=22)
-    ap.add_argument("--template-seed", type=int, default=0)
+    ap.add_argument("--workload", default="theta8-s26", choices=["theta8-s26", "tri-square-s22"],
+                    help="theta8-s26 (default): the scale-26 batch of a base template and its "
+                         "relaxations; tri-square-s22: one template at scale 22")
+    ap.add_argument("--legs",
+                    default="single,batched,learned,incremental,count,explore,topology",
+                    help="comma-separated legs on a resident scale-22 graph; '' for none")
+    ap.add_argument("--batch-streams", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-s", type=float, default=20.0)
-    ap.add_argument("--legs", default="batched,learned,autotune",
-                    help="extra legs on the same resident graph: batched (64 mixed templates, "
-                         "one call per template vs concurrent streams), learned (64 multi-cycle "
-                         "templates, fixed vs learned constraint order), autotune (coordinate "
-                         "search of the tuning settings on the timed template; the timed "
-                         "steps above use the defaults), explore (opt-in: exploratory search "
-                         "from the 6-clique on the timed template's labels, relaxed level "
-                         "by level until a variant matches); '' for none")
-    ap.add_argument("--batch-streams", type=int, default=4)
-    ap.add_argument("--workload", default="tri-square-s22", choices=["tri-square-s22", "theta8-s26"],
-                    help="tri-square-s22: one template at scale 22 (default); theta8-s26: scale-26 base template "
-                         "and its 1-2 edge-deletion relaxations, one call per variant vs one "
-                         "batched call with the learned order")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path, so --gpus must be 1 "
+              "(templates would shard across GPUs with no communication; see the design notes)",
+              file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_1912_08453_amd import inputs as I
-    from paper_1912_08453_amd import pm
-
     if args.copy_calibration:
-        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
         x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
         x.fill_(1)
         y = torch.empty_like(x)
@@ -78,153 +80,78 @@ def main():
                           "launches": 3}))
         return
 
-    if args.workload == "theta8-s26":
-        return exploratory(args)
-
-    t0 = time.time()
-    rp, col = I.rmat_csr(args.scale, seed=args.graph_seed)
-    labels = I.labels_log2deg(rp)
-    g = I.Graph(rp, col, labels)
-    tmpl = I.template_tri_square(g, args.template_seed)
-    n, m = g.n, g.m
-    log(f"graph scale {args.scale}: n={n} m={m} (directed entries), built in "
-        f"{time.time() - t0:.1f}s; template labels {tmpl.labels}")
-
-    dev = torch.device("cuda", 0)
-    d_rp = torch.from_numpy(rp).to(dev)
-    d_col = torch.from_numpy(col).to(dev)
-    d_lab = torch.from_numpy(labels).to(dev)
-    ctx = pm.PM(0)
-    torch.cuda.synchronize()
-    t_load = time.perf_counter()
-    ctx.load_graph(d_rp, d_col, d_lab)
-    torch.cuda.synchronize()
-    load_ms = 1e3 * (time.perf_counter() - t_load)
-    tid = ctx.load_templates([tmpl])
-    words = (m + 63) // 64
-    role = torch.empty((1, n), dtype=torch.int64, device=dev)
-    edge = torch.empty((1, words), dtype=torch.int64, device=dev)
-
-    for i in range(args.warmup):
-        _, _, st = ctx.prune(tid, role_mask=role, edge_bits=edge)
-        log(f"warmup {i}: {st['ms_total']:.2f} ms")
-    torch.cuda.synchronize()
-    stats = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        _, _, st = ctx.prune(tid, role_mask=role, edge_bits=edge)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t_el = time.perf_counter() - t_start
-    ms_per_step = 1e3 * t_el / args.steps
-    gteps = m / (ms_per_step / 1e3) / 1e9
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {gteps:.3f} GTEPS")
-
-    def avg(k):
-        return sum(s[k] for s in stats) / len(stats)
-
-    # roofline of the first LCC sweep kernel (HBM-bound).  From the
-    # neighbour-label count index: compulsory bytes = labels (1 B per
-    # vertex) + the count bytes each vertex's initial roles need + omega
-    # written (s B per vertex), computed by the library.  Without the index
-    # (gather sweep over the CSR): 4 B worklist id + 16 B row_ptr pair per
-    # active vertex, 4 B col per entry, omega read once and written once per
-    # active vertex.
-    s_bytes = 1 if tmpl.n0 <= 8 else 2 if tmpl.n0 <= 16 else 4 if tmpl.n0 <= 32 else 8
-    if stats[-1]["first_sweep_bytes"] > 0:
-        alg_bytes = stats[-1]["first_sweep_bytes"]
-        kname = "first_sweep_counts_kernel (first LCC sweep from the neighbour-label count index)"
-    else:
-        na = stats[-1]["first_sweep_vertices"]
-        ma = stats[-1]["first_sweep_entries"]
-        alg_bytes = 20 * na + 4 * ma + s_bytes * (n + na)
-        kname = "lcc_sweep_kernel (first LCC sweep over the CSR)"
-    k_ms = avg("ms_sweep_kernel")
-    achieved = alg_bytes / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
-    traffic = None
-    if stats[-1]["first_sweep_bytes"] > 0:
-        traffic = recorded_traffic("first_sweep_counts_kernel", args.scale, args.graph_seed,
-                                   args.template_seed)
-    roofline = {"bound": "hbm", "kernel": kname,
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": int(alg_bytes), "ms_per_launch": round(k_ms, 5)}
-
-    phases = {k: round(avg(k), 4) for k in stats[-1] if k.startswith("ms_")}
-    search = {k: round(avg(k), 3) for k in stats[-1] if k.startswith("wave_ms_")}
-    counts = {k: stats[-1][k] for k in stats[-1]
-              if not k.startswith("ms_") and not k.startswith("wave_ms_")}
-    r = pm.to_u64(role[0])
-    counts["result_vertices"] = int((r != 0).sum())
-    counts["result_entries"] = int(np.unpackbits(pm.to_u64(edge[0]).view(np.uint8)).sum())
-
     legs = [x for x in args.legs.split(",") if x]
-    batched = learned = tuned = None
-    if "autotune" in legs:
-        tuned = autotune_leg(ctx, tid, role, edge)
-        log(f"autotune: {json.dumps(tuned)}")
-    explored = None
-    if "explore" in legs:
-        explored = explore_leg(ctx, tmpl)
-        log(f"explore: {json.dumps(explored)}")
-    if "batched" in legs:
-        batched = batched_leg(ctx, g, args.batch_streams)
-        log(f"batched: {json.dumps(batched)}")
-    if "learned" in legs:
-        learned = learned_leg(ctx, g)
-        log(f"learned: {json.dumps(learned)}")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, tmpl, args.cpu_sample_s)
-
-    out = {
-        "metric": "GTEPS (directed CSR entries / time-to-fixpoint, bit-exact complete set)",
-        "value": round(gteps, 4),
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": f"R-MAT scale {args.scale} (a,b,c)=(0.57,0.19,0.19) ef16, "
-                               f"log2-degree uint8 labels; 6-vertex triangle+4-cycle+pendant "
-                               f"template, repeated label (seed {args.template_seed})",
-                   "n": n, "m_directed": m, "template_labels": tmpl.labels,
-                   "parallelism": "single GPU"},
-        "time_to_fixpoint_ms": round(ms_per_step, 4),
-        "graph_load_ms": round(load_ms, 2),
-        "phases_ms": phases,
-        "counts": counts,
-        "search_wave_ms": search,
-        "roofline": roofline,
-        "dominant_phase": {"phase": "exact step (edge_search_kernel, vertex_search_kernel)",
-                           "share_of_step": round(avg("ms_exact") / max(avg("ms_total"), 1e-9), 4),
-                           "bound": "search latency / random gathers (no roofline claim)"},
-        "cpu_baseline": cpu,
-        "batched": batched,
-        "autotune": tuned,
-        "explore": explored,
-        "learned_order": learned,
-    }
+    if args.workload == "theta8-s26":
+        out = theta8_s26(args)
+    else:
+        out = None
+    ctx22 = g22 = None
+    leg_out = {}
+    if legs or out is None:
+        g22 = build_graph(22, 22)
+        ctx22 = load(g22)
+    if out is None:
+        out = single_leg(ctx22, g22, args, primary=True)
+    else:
+        if "single" in legs:
+            leg_out["single_template_s22"] = single_leg(ctx22, g22, args, primary=False)
+    for name, fn in (("batched", batched_leg), ("learned", learned_leg),
+                     ("incremental", incremental_leg), ("count", count_leg),
+                     ("explore", explore_leg), ("topology", topology_leg)):
+        if name in legs:
+            t0 = time.time()
+            leg_out[name] = fn(ctx22, g22, args)
+            log(f"leg {name} ({time.time() - t0:.0f}s): {json.dumps(leg_out[name])[:400]}")
+    out["legs"] = leg_out
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
-def recorded_traffic(kernel, scale, graph_seed, template_seed):
-    """HBM bytes per launch of `kernel` from the counter record under
-    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
-    None when there is no record for this workload or the kernel's source has
-    changed since the counters were taken."""
-    import hashlib
-    if graph_seed != 22:
-        return None
-    path = os.path.join(ROOT, "profiles",
-                        f"first_sweep_counts_tri_square_scale{scale}_seed{template_seed}.txt")
+# ------------------------------------------------------------------ helpers
+def build_graph(scale, seed, abc=GRAPH500):
+    import numpy as np  # noqa: F401
+    from paper_1912_08453_amd import inputs as I
+    t0 = time.time()
+    rp, col = I.rmat_csr(scale, seed=seed, abc=abc)
+    g = I.Graph(rp, col, I.labels_log2deg(rp))
+    log(f"graph scale {scale} abc={abc}: n={g.n} m={g.m} built in {time.time() - t0:.1f}s")
+    return g
+
+
+def load(g):
+    import torch
+    from paper_1912_08453_amd import pm
+    dev = torch.device("cuda", 0)
+    ctx = pm.PM(0)
+    ctx.load_graph(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                   torch.from_numpy(g.labels).to(dev))
+    torch.cuda.synchronize()
+    return ctx
+
+
+def wall(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0), r
+
+
+def index_bytes(ctx):
+    """Algorithmic bytes of one count-index pass (the first LCC sweep's
+    input for every template): row_ptr (8(n+1)), col (4m), every vertex's
+    label once (n, the compulsory part of the label gather) and the index
+    written (labels x padded n)."""
+    gi = ctx.graph_info()
+    n, m = gi["n"], gi["m"]
+    return 8 * (n + 1) + 4 * m + n + gi["index_bytes"]
+
+
+def recorded_traffic(kernel_file):
+    """HBM bytes per launch from a counter record under profiles/
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when
+    there is none or the kernel's source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", kernel_file)
     if not os.path.exists(path):
         return None
     rec = {}
@@ -232,236 +159,255 @@ def recorded_traffic(kernel, scale, graph_seed, template_seed):
         line = line.strip()
         if line and not line.startswith("#") and "=" in line:
             k, v = line.split("=", 1)
-            rec[k] = v
-    if rec.get("kernel") != kernel:
-        return None
+            rec[k.strip()] = v.strip()
     src = os.path.join(ROOT, rec.get("source", ""))
-    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != rec.get("source_sha1"):
+    if not os.path.exists(src) or \
+            hashlib.sha1(open(src, "rb").read()).hexdigest() != rec.get("source_sha1"):
         return None
-    return int(float(rec["fetch_kib_per_dispatch"]) * 1024 * float(rec["fetch_scale"]) +
-               float(rec["write_kib_per_dispatch"]) * 1024 * float(rec["write_scale"]))
+    try:
+        return int(float(rec["fetch_kib_per_dispatch"]) * 1024 * float(rec["fetch_scale"]) +
+                   float(rec["write_kib_per_dispatch"]) * 1024 * float(rec["write_scale"]))
+    except (KeyError, ValueError):
+        return None
 
 
-def exploratory(args, scale=26, graph_seed=26, template_seed=0):
-    """Scale-26 exploratory workload: the 8-vertex two-cycle base template
-    (repeated-label pair 4 hops apart) and its connected 1- and 2-edge
-    deletion relaxations, deduplicated up to labelled isomorphism.  Plain:
-    one pm_prune call per variant, fixed order.  Batched: one call for all
-    variants on concurrent streams with the learned order.  Value: directed
-    entries x variants / batched wall time."""
+def roofline_of_index(ctx, ms_list, workload_key):
+    b = index_bytes(ctx)
+    k_ms = sum(ms_list) / len(ms_list)
+    achieved = b / (k_ms / 1e3) / 1e9
+    return {"bound": "hbm",
+            "kernel": "label_count_tiles_kernel + label_count_hub_kernel (neighbour-label count "
+                      "index: one pass over row_ptr and col, labels gathered, index written)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(f"label_count_{workload_key}.txt"),
+            "bytes_per_launch": int(b), "ms_per_launch": round(k_ms, 4),
+            "launches_timed": len(ms_list)}
+
+
+# ------------------------------------------------------ config 5 (default)
+def theta8_s26(args, scale=26, seed=26, template_seed=0):
     import numpy as np
     import torch
     from paper_1912_08453_amd import inputs as I
     from paper_1912_08453_amd import order_training as OT
-    from paper_1912_08453_amd import pm
-    t0 = time.time()
-    rp, col = I.rmat_csr(scale, seed=graph_seed)
-    labels = I.labels_log2deg(rp)
-    g = I.Graph(rp, col, labels)
+    g = build_graph(scale, seed)
     base = I.template_theta8(g, template_seed)
     ts = I.relaxations(base)
-    log(f"graph scale {scale}: n={g.n} m={g.m} built in {time.time() - t0:.1f}s; "
-        f"{len(ts)} variants of {base.labels}")
-    dev = torch.device("cuda", 0)
-    ctx = pm.PM(0)
-    ctx.load_graph(torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev),
-                   torch.from_numpy(labels).to(dev))
+    T = len(ts)
+    log(f"{T} templates: base labels {base.labels}")
+    ms_load, ctx = wall(lambda: load(g))
     first = ctx.load_templates(ts)
     ctx.load_model(OT.load_model())
     thr = OT.load_threshold()
-    T = len(ts)
+    dev = torch.device("cuda", 0)
     n, words = g.n, (g.m + 63) // 64
     rb = torch.empty((T, n), dtype=torch.int64, device=dev)
     eb = torch.empty((T, words), dtype=torch.int64, device=dev)
-    r1 = torch.empty((1, n), dtype=torch.int64, device=dev)
-    e1 = torch.empty((1, words), dtype=torch.int64, device=dev)
-    ctx.prune(first, role_mask=r1, edge_bits=e1)      # warm-up
-    plain_ms, batched_ms = [], []
-    per = []
-    for step in range(args.steps):
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
+
+    def step(order="learned", min_score=None):
+        k_ms = ctx.build_count_index()
+        _, _, st = ctx.prune(first, count=T, role_mask=rb, edge_bits=eb,
+                             batch_streams=args.batch_streams, order=order,
+                             learned_min_score=min_score)
+        return k_ms, st
+
+    for i in range(args.warmup):
+        ms, _ = wall(step)
+        log(f"warmup {i}: {ms:.1f} ms")
+    times, k_ms_list, stats = [], [], []
+    for i in range(args.steps):
+        ms, (k_ms, st) = wall(step)
+        times.append(ms)
+        k_ms_list.append(k_ms)
+        stats.append(st)
+        log(f"step {i}: {ms:.1f} ms (count index {k_ms:.2f} ms)")
+    ms_step = float(np.mean(times))
+    value = g.m * T / (ms_step / 1e3) / 1e9
+
+    # the plain path: the same index pass, one call per template, fixed order
+    r1 = torch.empty((T, n), dtype=torch.int64, device=dev)
+    e1 = torch.empty((T, words), dtype=torch.int64, device=dev)
+
+    def plain():
+        ctx.build_count_index()
+        per = []
         for i in range(T):
-            _, _, st = ctx.prune(first + i, role_mask=r1, edge_bits=e1)
-            if step == 0:
-                per.append({"edges": len(ts[i].edges), "ms": round(st["ms_total"], 2),
-                            "ms_exact": round(st["ms_exact"], 2),
-                            "result_vertices": st["result_vertices"]})
-        torch.cuda.synchronize()
-        plain_ms.append(1e3 * (time.perf_counter() - ta))
-        ta = time.perf_counter()
-        _, _, stb = ctx.prune(first, count=T, role_mask=rb, edge_bits=eb,
-                              batch_streams=args.batch_streams, order="learned",
-                              learned_min_score=thr)
-        torch.cuda.synchronize()
-        batched_ms.append(1e3 * (time.perf_counter() - ta))
-        log(f"step {step}: one per call {plain_ms[-1]:.1f} ms, batched+learned {batched_ms[-1]:.1f} ms")
-    # the last variant of the plain pass is still in r1/e1: same output
-    same = bool(torch.equal(r1[0], rb[T - 1]) and torch.equal(e1[0], eb[T - 1]))
-    bm = float(np.median(batched_ms))
-    pmed = float(np.median(plain_ms))
+            _, _, st = ctx.prune(first + i, role_mask=r1[i:i + 1], edge_bits=e1[i:i + 1])
+            per.append(st)
+        return per
+    plain_ms = []
+    per_plain = None
+    for _ in range(min(args.steps, 3)):
+        ms, per_plain = wall(plain)
+        plain_ms.append(ms)
+    identical = bool(torch.equal(r1, rb) and torch.equal(e1, eb))
+    log(f"plain {np.mean(plain_ms):.1f} ms, batched+learned {ms_step:.1f} ms, identical {identical}")
+    if not identical:
+        raise SystemExit("batched output differs from the one-template-per-call output")
+    # other batched modes (one timing each), same outputs
+    alt = {}
+    for name, order, ms_thr in (("batched_fixed", None, None),
+                                ("batched_learned_stop", "learned", thr)):
+        ms, _ = wall(lambda: step(order, ms_thr))
+        same = bool(torch.equal(r1, rb) and torch.equal(e1, eb))
+        alt[name] = {"ms": round(ms, 2), "identical": same}
+        if not same:
+            raise SystemExit(f"{name} output differs")
+    del r1, e1
+    roof = roofline_of_index(ctx, k_ms_list, "rmat26_log2deg")
+    phases = {k: round(float(np.mean([s[k] for s in stats])), 3) for k in stats[-1]
+              if k.startswith("ms_")}
+    per_variant = [{"edges": len(ts[i].edges), "ms": round(p["ms_total"], 2),
+                    "ms_exact": round(p["ms_exact"], 2),
+                    "result_vertices": p["result_vertices"]} for i, p in enumerate(per_plain)]
     out = {
-        "metric": "GTEPS (directed CSR entries x variants / time-to-fixpoint, bit-exact complete "
-                  "sets)",
-        "value": round(g.m * T / (bm / 1e3) / 1e9, 4), "unit": "GTEPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": round(bm, 2),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": f"R-MAT scale {scale} ef16 log2-degree labels; 8-vertex two-cycle "
-                               f"template with a repeated-label pair 4 hops apart and its "
-                               f"{T - 1} connected 1-2 edge-deletion relaxations",
-                   "n": n, "m_directed": g.m, "variants": T, "base_labels": base.labels,
-                   "parallelism": "single GPU"},
-        "one_variant_per_call_fixed_order_ms": round(pmed, 2),
-        "batched_learned_ms": round(bm, 2), "batch_streams": args.batch_streams,
-        "speedup": round(pmed / bm, 4), "last_variant_identical": same,
-        "batched_stats": {k: round(v, 2) if isinstance(v, float) else v
-                          for k, v in stb.items() if k.startswith("ms_") or k in
-                          ("constraints", "result_vertices", "edge_queries")},
-        "per_variant_plain": per,
+        "metric": "GTEPS (directed CSR entries x templates / time-to-fixpoint, bit-exact "
+                  "complete sets; batched + learned order vs one template per call, fixed "
+                  "order)",
+        "value": round(value, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {scale} (a,b,c)=(0.57,0.19,0.19) ef16, "
+                               f"log2-degree uint8 labels; 8-vertex two-cycle template with a "
+                               f"repeated-label pair 4 hops apart and its {T - 1} connected "
+                               f"1-2 edge-deletion relaxations ({T} templates), one batch",
+                   "n": n, "m_directed": g.m, "templates": T, "base_labels": base.labels,
+                   "batch_streams": args.batch_streams, "order": "learned (every constraint "
+                   "checked)", "parallelism": "single GPU"},
+        "time_to_fixpoint_ms": round(ms_step, 3),
+        "plain_one_template_per_call_ms": round(float(np.mean(plain_ms)), 2),
+        "speedup_vs_plain": round(float(np.mean(plain_ms)) / ms_step, 4),
+        "outputs_identical": identical,
+        "other_batched_modes": alt,
+        "count_index_ms": round(float(np.mean(k_ms_list)), 3),
+        "graph_load_ms": round(ms_load, 1),
+        "phases_ms_sum_over_templates": phases,
+        "per_template_plain": per_variant,
+        "roofline": roof,
+        "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_sweep_baseline(g, ts, T)
     ctx.close()
-
-
-def explore_leg(ctx, tmpl, max_deletions=4):
-    """Exploratory search (the paper's 6-clique scenario): the complete
-    graph on the timed template's vertex labels, relaxed level by level
-    (connected variants, one per isomorphism class) until a variant has a
-    match; per-level variant counts, matches and wall time."""
-    from paper_1912_08453_amd import explore
-    n0 = len(tmpl.labels)
-    clique = [(a, b) for a in range(n0) for b in range(a + 1, n0)]
-    t0 = time.perf_counter()
-    res = explore.explore(ctx, tmpl.labels, clique, max_deletions=max_deletions, log=log)
-    total = 1e3 * (time.perf_counter() - t0)
-    out = {"workload": f"K{n0} on labels {list(tmpl.labels)}, up to {max_deletions} edges "
-                       f"removed", "levels": res.levels, "stop_level": res.level,
-           "total_ms": round(total, 1)}
-    if res.level >= 0:
-        out["union_vertices"] = int((res.role_union != 0).sum().item())
+    del rb, eb
+    torch.cuda.empty_cache()
     return out
 
 
-def autotune_leg(ctx, tid, role, edge):
-    """Coordinate search of the tuning settings on the timed template (best
-    of 3 prunes per candidate), the tuned time against the defaults' on the
-    same timer, and the output with the tuned settings against the timed
-    steps' output.  The defaults are restored afterwards."""
-    import torch
-    from paper_1912_08453_amd import autotune
-    start = ctx.params()
-    best, table = autotune.autotune(ctx, [tid], reps=3)
-    timer = autotune.prune_timer(ctx, [tid], reps=5)
-    tuned_ms = timer()
-    r2, e2, _ = ctx.prune(tid)
-    same = bool(torch.equal(r2, role) and torch.equal(e2, edge))
-    for k, v in start.items():
-        ctx.set_param(k, v)
-    default_ms = timer()
-    return {"defaults": start, "tuned": {k: v for k, v in best.items() if v != start[k]},
-            "candidates_timed": len(table) - 1, "default_ms": round(default_ms, 2),
-            "tuned_ms": round(tuned_ms, 2), "outputs_identical": same}
+def cpu_sweep_baseline(g, ts, T, sample=1 << 20, sample_1t=1 << 16):
+    """The oracle's local rule (one LCC sweep from the label roles) on a
+    uniform vertex sample of the same graph for the base template, scaled to
+    entries x templates per second.  Every template's prune needs at least
+    this sweep over the whole graph, and the oracle's later steps (LCC
+    fixpoint, constraints, exact step) only add time, so this bounds its
+    rate from above.  Also timed on one thread."""
+    import numpy as np
+    import oracle
+    gg = oracle._G(g.row_ptr, g.col, g.labels)
+    t = ts[0]
+    tt = oracle._T(t.labels, t.edges)
+    om = oracle.init_roles(gg, tt)
+    rng = np.random.Generator(np.random.Philox(7))
+    verts = np.sort(rng.choice(g.n, size=min(sample, g.n), replace=False)).astype(np.int32)
+    cores = oracle.num_threads()
+    t0 = time.perf_counter()
+    _, ent = oracle.lcc_sample(gg, tt, om, verts)
+    dt = time.perf_counter() - t0
+    rate = ent / dt                     # entries per second
+    oracle.set_threads(1)
+    v1 = verts[:sample_1t]
+    t0 = time.perf_counter()
+    _, ent1 = oracle.lcc_sample(gg, tt, om, v1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    return {"value": round(rate / 1e9, 6), "unit": "GTEPS", "cores": cores, "kind": "oracle",
+            "sample": f"oracle's LCC rule, one sweep from the label roles of the base template "
+                      f"on {verts.size} uniformly sampled vertices of the same scale-26 graph "
+                      f"({ent} CSR entries, {dt:.1f}s); entries/s, which bounds the oracle's "
+                      f"rate in entries x templates/s from above (each of the {T} templates "
+                      f"needs at least this sweep over all 2.1 G entries)",
+            "one_thread": {"value": round(ent1 / dt1 / 1e9, 6), "unit": "GTEPS", "cores": 1,
+                           "sample": f"same rule on {v1.size} of those vertices ({ent1} "
+                                     f"entries, {dt1:.1f}s)"}}
 
 
-def batched_leg(ctx, g, streams, seed=3, count=64):
-    """64 mixed templates (paths/trees, one- and two-cycle, K4; some with a
-    repeated label) against the resident graph: one pm_prune call per
-    template in the fixed order, then one call for all of them on `streams`
-    concurrent streams.  Outputs must be identical."""
+# ------------------------------------------------- config 2 (single template)
+def single_leg(ctx, g, args, primary):
+    """The triangle + 4-cycle + pendant template (repeated label) on the
+    scale-22 graph: time-to-fixpoint of one prune, with the count-index pass
+    in the step."""
+    import numpy as np
     import torch
     from paper_1912_08453_amd import inputs as I
-    ts = I.templates_batch(g, seed, count=count)
-    first = ctx.load_templates(ts)
-    n, words = g.n, (g.m + 63) // 64
+    t = I.template_tri_square(g, 0)
+    tid = ctx.load_templates([t])
     dev = torch.device("cuda", 0)
-    r1 = torch.empty((count, n), dtype=torch.int64, device=dev)
-    e1 = torch.empty((count, words), dtype=torch.int64, device=dev)
-    r2 = torch.empty_like(r1)
-    e2 = torch.empty_like(e1)
-    ctx.prune(first, count=count, role_mask=r2, edge_bits=e2, batch_streams=streams)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    phase = {"ms_exact": 0.0, "ms_nlcc": 0.0, "ms_lcc": 0.0}
-    for i in range(count):
-        _, _, st = ctx.prune(first + i, role_mask=r1[i:i + 1], edge_bits=e1[i:i + 1])
-        for k in phase:
-            phase[k] += st[k]
-    torch.cuda.synchronize()
-    seq_ms = 1e3 * (time.perf_counter() - t0)
-    t0 = time.perf_counter()
-    ctx.prune(first, count=count, role_mask=r2, edge_bits=e2, batch_streams=streams)
-    torch.cuda.synchronize()
-    bat_ms = 1e3 * (time.perf_counter() - t0)
-    same = bool(torch.equal(r1, r2) and torch.equal(e1, e2))
-    del r1, e1, r2, e2
-    return {"workload": f"{count} templates (3-8 vertices; trees, one/two cycles, K4; "
-                        f"seed {seed}) on the same graph",
-            "one_template_per_call_ms": round(seq_ms, 2),
-            "batched_ms": round(bat_ms, 2), "batch_streams": streams,
-            "speedup": round(seq_ms / bat_ms, 4), "outputs_identical": same,
-            "one_per_call_phase_ms": {k: round(v, 2) for k, v in phase.items()}}
+    role = torch.empty((1, g.n), dtype=torch.int64, device=dev)
+    edge = torch.empty((1, (g.m + 63) // 64), dtype=torch.int64, device=dev)
+
+    def step():
+        k_ms = ctx.build_count_index()
+        _, _, st = ctx.prune(tid, role_mask=role, edge_bits=edge)
+        return k_ms, st
+    steps = args.steps if primary else max(args.steps, 5)
+    for _ in range(args.warmup):
+        wall(step)
+    times, kms, stats = [], [], []
+    for _ in range(steps):
+        ms, (k, st) = wall(step)
+        times.append(ms)
+        kms.append(k)
+        stats.append(st)
+    ms_step = float(np.mean(times))
+    prune_ms = float(np.mean([s["ms_total"] for s in stats]))
+    phases = {k: round(float(np.mean([s[k] for s in stats])), 4) for k in stats[-1]
+              if k.startswith("ms_")}
+    search = {k: round(float(np.mean([s[k] for s in stats])), 3) for k in stats[-1]
+              if k.startswith("wave_ms_")}
+    r = role[0].cpu().numpy().view(np.uint64)
+    res = {"workload": f"R-MAT scale 22 ef16 log2-degree labels; 6-vertex triangle+4-cycle+"
+                       f"pendant template {t.labels} (repeated label)",
+           "value": round(g.m / (ms_step / 1e3) / 1e9, 4), "unit": "GTEPS",
+           "ms_per_step": round(ms_step, 3), "steps": steps,
+           "prune_device_ms": round(prune_ms, 3),
+           "value_prune_only": round(g.m / (prune_ms / 1e3) / 1e9, 4),
+           "count_index_ms": round(float(np.mean(kms)), 4),
+           "phases_ms": phases, "search_wave_ms": search,
+           "result_vertices": int((r != 0).sum()),
+           "roofline": roofline_of_index(ctx, kms, "rmat22_log2deg"),
+           "dominant_phase": {"phase": "exact step (edge_search_kernel, vertex_search_kernel)",
+                              "share_of_prune": round(phases["ms_exact"] /
+                                                      max(phases["ms_total"], 1e-9), 4),
+                              "bound": "search latency / random gathers (no byte roofline)"}}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_oracle_prune_baseline(g, t)
+    if primary:
+        res.update({"metric": "GTEPS (directed CSR entries / time-to-fixpoint, bit-exact "
+                              "complete set)", "n_gpus": 1, "warmup": args.warmup,
+                    "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                    "dtype": "u8", "data": "synthetic",
+                    "config": {"workload": res["workload"], "n": g.n, "m_directed": g.m,
+                               "parallelism": "single GPU"},
+                    "cpu_baseline": res.get("cpu_baseline")})
+    return res
 
 
-def learned_leg(ctx, g, seed=4, count=64):
-    """64 seeded 7-8 vertex templates with cyclomatic number >= 2 (seeds
-    disjoint from the model's training templates): whole prune with the
-    fixed order and with the learned order (model and stopping threshold
-    shipped with the package).  Outputs must be identical."""
-    import torch
-    from paper_1912_08453_amd import inputs as I
-    from paper_1912_08453_amd import order_training as OT
-    ts = I.templates_multicycle(g, seed, count=count)
-    first = ctx.load_templates(ts)
-    ctx.load_model(OT.load_model())
-    thr = OT.load_threshold()
-    n, words = g.n, (g.m + 63) // 64
-    dev = torch.device("cuda", 0)
-    ra = torch.empty((1, n), dtype=torch.int64, device=dev)
-    ea = torch.empty((1, words), dtype=torch.int64, device=dev)
-    rb = torch.empty_like(ra)
-    eb = torch.empty_like(ea)
-    keys = ("ms_total", "ms_nlcc", "ms_lcc", "ms_exact", "constraints")
-    tot = {"fixed": dict.fromkeys(keys, 0.0), "learned": dict.fromkeys(keys, 0.0)}
-    same = True
-    ctx.prune(first, role_mask=ra, edge_bits=ea)   # warm-up
-    for i in range(count):
-        _, _, sf = ctx.prune(first + i, role_mask=ra, edge_bits=ea)
-        _, _, sl = ctx.prune(first + i, order="learned", learned_min_score=thr,
-                             role_mask=rb, edge_bits=eb)
-        same = same and bool(torch.equal(ra, rb) and torch.equal(ea, eb))
-        for k in keys:
-            tot["fixed"][k] += sf[k]
-            tot["learned"][k] += sl[k]
-    out = {"workload": f"{count} multi-cycle templates (7-8 vertices, cyclomatic >= 2, "
-                       f"seed {seed}) on the same graph",
-           "min_score": thr, "outputs_identical": same}
-    for mode in ("fixed", "learned"):
-        out[mode] = {k: round(v, 2) for k, v in tot[mode].items()}
-    out["speedup_total"] = round(tot["fixed"]["ms_total"] / tot["learned"]["ms_total"], 4)
-    cl_f = tot["fixed"]["ms_nlcc"] + tot["fixed"]["ms_lcc"]
-    cl_l = tot["learned"]["ms_nlcc"] + tot["learned"]["ms_lcc"]
-    out["speedup_nlcc_plus_lcc"] = round(cl_f / cl_l, 4) if cl_l > 0 else None
-    return out
-
-
-def cpu_baseline(g, tmpl, budget_s):
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    init, LCC fixpoint and every non-local constraint on the full graph,
-    then the exact final step's searches for a uniform random sample of the
-    surviving vertices, scaled to all of them.  Rate = directed entries per
-    second of the estimated whole prune."""
+def cpu_oracle_prune_baseline(g, t, budget_s=20.0, sample=2000):
+    """The oracle on the same graph and template: init, LCC fixpoint and
+    every non-local constraint in full, then the exact step for a uniform
+    sample of the surviving vertices, scaled to all of them."""
     import numpy as np
     import oracle
     from oracle import constraints as C
     cores = oracle.num_threads()
     gg = oracle._G(g.row_ptr, g.col, g.labels)
-    tt = oracle._T(tmpl.labels, tmpl.edges)
+    tt = oracle._T(t.labels, t.edges)
     t0 = time.perf_counter()
     om = oracle.init_roles(gg, tt)
     oracle.lcc(gg, tt, om)
     t_lcc = time.perf_counter() - t0
-    K0 = C.non_local_constraints(tmpl.labels, tmpl.edges)
+    K0 = C.non_local_constraints(t.labels, t.edges)
     done = 0
     for c in K0:
         if time.perf_counter() - t0 > budget_s:
@@ -472,21 +418,241 @@ def cpu_baseline(g, tmpl, budget_s):
     t_nlcc = time.perf_counter() - t0 - t_lcc
     active = np.nonzero(om)[0].astype(np.int32)
     rng = np.random.Generator(np.random.Philox(7))
-    sample = np.sort(rng.permutation(active)[:min(2000, active.shape[0])]) if active.size else active
+    smp = np.sort(rng.permutation(active)[:min(sample, active.shape[0])]) if active.size else active
     t1 = time.perf_counter()
-    oracle.exact_subset(gg, tt, om, sample)
+    oracle.exact_subset(gg, tt, om, smp)
     t_s = time.perf_counter() - t1
-    t_exact = t_s * (active.shape[0] / max(sample.shape[0], 1))
+    t_exact = t_s * (active.shape[0] / max(smp.shape[0], 1))
     total = t_lcc + t_nlcc + t_exact
-    complete = done == len(K0)
     return {"value": round(g.m / total / 1e9, 6), "unit": "GTEPS", "cores": cores,
             "kind": "oracle",
-            "sample": f"oracle on the same graph and template: init + LCC fixpoint "
-                      f"({t_lcc:.2f}s) + {done}/{len(K0)} non-local constraints ({t_nlcc:.2f}s) "
-                      f"measured in full; exact step timed on {sample.shape[0]} of "
-                      f"{active.shape[0]} surviving vertices ({t_s:.2f}s) and scaled to all "
-                      f"(est. {t_exact:.1f}s)" + ("" if complete else "; constraint list cut "
-                      "by the time budget")}
+            "sample": f"init + LCC fixpoint ({t_lcc:.2f}s) + {done}/{len(K0)} non-local "
+                      f"constraints ({t_nlcc:.2f}s) in full; exact step on {smp.shape[0]} of "
+                      f"{active.shape[0]} surviving vertices ({t_s:.2f}s) scaled to all "
+                      f"(est. {t_exact:.1f}s)"}
+
+
+# ----------------------------------------------------------- config 3 batch
+def batched_leg(ctx, g, args, seed=3, count=64):
+    import torch
+    from paper_1912_08453_amd import inputs as I
+    ts = I.templates_batch(g, seed, count=count)
+    first = ctx.load_templates(ts)
+    n, words = g.n, (g.m + 63) // 64
+    dev = torch.device("cuda", 0)
+    r1 = torch.empty((count, n), dtype=torch.int64, device=dev)
+    e1 = torch.empty((count, words), dtype=torch.int64, device=dev)
+    r2 = torch.empty_like(r1)
+    e2 = torch.empty_like(e1)
+    ctx.prune(first, count=count, role_mask=r2, edge_bits=e2, batch_streams=args.batch_streams)
+
+    def one_by_one():
+        for i in range(count):
+            ctx.prune(first + i, role_mask=r1[i:i + 1], edge_bits=e1[i:i + 1])
+    seq_ms, _ = wall(one_by_one)
+    bat_ms, _ = wall(lambda: ctx.prune(first, count=count, role_mask=r2, edge_bits=e2,
+                                       batch_streams=args.batch_streams))
+    same = bool(torch.equal(r1, r2) and torch.equal(e1, e2))
+    # the same batch drawing all scratch from one caller-owned workspace
+    ws_bytes = ctx.workspace_size(first, count, batch_streams=args.batch_streams)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ctx.set_workspace(ws)
+    ws_ms, _ = wall(lambda: ctx.prune(first, count=count, role_mask=r2, edge_bits=e2,
+                                      batch_streams=args.batch_streams))
+    same_ws = bool(torch.equal(r1, r2) and torch.equal(e1, e2))
+    ctx.set_workspace(None)
+    del ws, r1, e1, r2, e2
+    torch.cuda.empty_cache()
+    return {"workload": f"{count} templates (3-8 vertices; trees, one/two cycles, K4; seed {seed})"
+                        f" on the scale-22 graph",
+            "one_template_per_call_ms": round(seq_ms, 2), "batched_ms": round(bat_ms, 2),
+            "batch_streams": args.batch_streams, "speedup": round(seq_ms / bat_ms, 4),
+            "outputs_identical": same,
+            "caller_workspace": {"bytes": ws_bytes, "batched_ms": round(ws_ms, 2),
+                                 "outputs_identical": same_ws}}
+
+
+# ------------------------------------------------------ config 4 learned
+def learned_leg(ctx, g, args, seed=4, count=64):
+    """Multi-cycle templates: fixed order; learned order with every
+    constraint checked; learned order with the stopping threshold; and, to
+    separate ordering from skipping, the fixed order stopped after as many
+    constraints as the learned run checked, and no non-local constraint at
+    all (stop_after = 0, then the exact step).  All outputs identical."""
+    import torch
+    from paper_1912_08453_amd import inputs as I
+    from paper_1912_08453_amd import order_training as OT
+    ts = I.templates_multicycle(g, seed, count=count)
+    first = ctx.load_templates(ts)
+    ctx.load_model(OT.load_model())
+    thr = OT.load_threshold()
+    keys = ("ms_total", "ms_nlcc", "ms_lcc", "ms_exact", "constraints")
+    modes = ("fixed", "learned_all", "learned_stop", "fixed_stop_same_count", "no_nonlocal")
+    tot = {m: dict.fromkeys(keys, 0.0) for m in modes}
+    same = True
+    ra = None
+    ctx.prune(first)   # warm-up
+    for i in range(count):
+        outs = {}
+        _, _, s_l = ctx.prune(first + i, order="learned", learned_min_score=thr)
+        k_stop = int(s_l["constraints"])
+        for m, kw in (("fixed", {}), ("learned_all", {"order": "learned"}),
+                      ("learned_stop", {"order": "learned", "learned_min_score": thr}),
+                      ("fixed_stop_same_count", {}), ("no_nonlocal", {})):
+            if m == "fixed_stop_same_count":
+                r, e, st = ctx.prune(first + i, max_checks=k_stop)
+            elif m == "no_nonlocal":
+                r, e, st = ctx.prune(first + i, max_checks=0)
+            else:
+                r, e, st = ctx.prune(first + i, **kw)
+            outs[m] = (r.clone(), e.clone())
+            for k in keys:
+                tot[m][k] += st[k]
+        ra, ea = outs["fixed"]
+        for m in modes:
+            same = same and bool(torch.equal(ra, outs[m][0]) and torch.equal(ea, outs[m][1]))
+    res = {"workload": f"{count} multi-cycle templates (7-8 vertices, cyclomatic >= 2, "
+                       f"seed {seed}) on the scale-22 graph", "min_score": thr,
+           "outputs_identical": same}
+    for m in modes:
+        res[m] = {k: round(v, 2) for k, v in tot[m].items()}
+    f = tot["fixed"]["ms_total"]
+    res["speedup_vs_fixed"] = {m: round(f / tot[m]["ms_total"], 4) for m in modes}
+    return res
+
+
+# ----------------------------------------------------- incremental (f2)
+def incremental_leg(ctx, g, args):
+    """Interactive incremental search: the triangle + 4-cycle + pendant
+    template reached from a spanning tree by adding its two other edges,
+    then relaxed again by deleting them; each revision reuses the previous
+    complete set (additions) or the candidate set with the previous complete
+    set pre-certified (deletions), timed against a full prune."""
+    from paper_1912_08453_amd import incremental
+    from paper_1912_08453_amd import inputs as I
+    t = I.template_tri_square(g, 0)
+    edges = sorted(tuple(sorted(e)) for e in t.edges)
+    tree = [(0, 1), (0, 2), (0, 4), (1, 3), (3, 5)]
+    extra = [e for e in edges if e not in tree]
+    s = incremental.Session(ctx, t.labels, tree, compare=True)
+    for e in extra:
+        s.add_edge(*e)
+    for e in extra[::-1]:
+        s.delete_edge(*e)
+    recs = s.history[1:]
+    inc = sum(r["ms"] + r.get("candidate_ms", 0.0) for r in recs)
+    naive = sum(r["naive_ms"] for r in recs)
+    return {"workload": f"scale-22 graph, template labels {t.labels}: start from the tree "
+                        f"{tree}, add {extra}, delete them again",
+            "steps": [{k: (list(v) if isinstance(v, tuple) else v) for k, v in r.items()}
+                      for r in recs],
+            "incremental_ms": round(inc, 2), "naive_ms": round(naive, 2),
+            "speedup": round(naive / inc, 4) if inc > 0 else None,
+            "outputs_identical": all(r["identical"] for r in recs)}
+
+
+# --------------------------------------------------------- counting (f3)
+def count_leg(ctx, g, args):
+    """Match counting on the pruned graph: every match of the config-2
+    template and of three batch templates, counted within their complete
+    sets (the pruning time beside the counting time)."""
+    from paper_1912_08453_amd import inputs as I
+    t = I.template_tri_square(g, 0)
+    ts = [t] + I.templates_batch(g, 3, count=64)[:3]
+    first = ctx.load_templates(ts)
+    out = []
+    for i, tt in enumerate(ts):
+        prune_ms, (r, _, _) = wall(lambda: ctx.prune(first + i))
+        r = r.clone()
+        cnt_ms, res = wall(lambda: ctx.count_matches(first + i, state=r))
+        rec = {"labels": list(tt.labels), "edges": len(tt.edges), "maps": res["maps"],
+               "automorphisms": res["automorphisms"], "matches": res["subgraphs"],
+               "roots": res["roots"], "prune_ms": round(prune_ms, 2),
+               "count_ms": round(cnt_ms, 2)}
+        out.append(rec)
+    return {"workload": "scale-22 graph: triangle+4-cycle+pendant and three batch templates",
+            "templates": out}
+
+
+# ------------------------------------------------------- exploratory (f1)
+def explore_leg(ctx, g, args, max_deletions=4):
+    """The 6-clique on the config-2 template's labels, relaxed level by
+    level until a variant matches, with and without the candidate set."""
+    from paper_1912_08453_amd import explore
+    from paper_1912_08453_amd import inputs as I
+    t = I.template_tri_square(g, 0)
+    n0 = len(t.labels)
+    clique = [(a, b) for a in range(n0) for b in range(a + 1, n0)]
+    res = {}
+    for cand in (True, False):
+        ms, r = wall(lambda: explore.explore(ctx, t.labels, clique, max_deletions=max_deletions,
+                                             use_candidate_set=cand))
+        res["with_candidate_set" if cand else "from_label_roles"] = {
+            "levels": r.levels, "stop_level": r.level, "total_ms": round(ms, 1),
+            "union_vertices": int((r.role_union != 0).sum().item()) if r.level >= 0 else 0}
+    return {"workload": f"K{n0} on labels {list(t.labels)}, up to {max_deletions} edges removed",
+            **res}
+
+
+# ------------------------------------------------- topology + ablations (f4)
+def topology_leg(ctx22, g22, args, scale=20, seed=20):
+    """R-MAT graphs of one scale with the paper's three parameter sets
+    (Graph500, Chakrabarti et al., uniform), log2-degree labels, the
+    triangle + 4-cycle + pendant shape with labels from an occurrence in
+    each graph: complete-set size, match count and time; then the design
+    ablations (edge elimination off, work aggregation off) on the scale-22
+    graph, same output."""
+    import numpy as np
+    import torch
+    from paper_1912_08453_amd import inputs as I
+    from paper_1912_08453_amd import pm
+    rows = []
+    for name, abc in (("graph500", GRAPH500), ("chakrabarti", CHAKRABARTI),
+                      ("uniform", UNIFORM)):
+        g = build_graph(scale, seed, abc)
+        ctx = load(g)
+        try:
+            t = I.template_tri_square(g, 0)
+        except RuntimeError:
+            rows.append({"graph": name, "abc": abc, "n": g.n, "m": g.m,
+                         "template": "no occurrence of the shape found"})
+            ctx.close()
+            continue
+        tid = ctx.load_templates([t])
+        ctx.prune(tid)
+        ms, (r, e, st) = wall(lambda: ctx.prune(tid))
+        r = r.clone()
+        bits = int(np.unpackbits(e[0].cpu().numpy().view(np.uint8)).sum())
+        cms, cnt = wall(lambda: ctx.count_matches(tid, state=r))
+        rows.append({"graph": name, "abc": abc, "n": g.n, "m": g.m,
+                     "d_max": int(np.diff(g.row_ptr).max()), "labels": int(g.labels.max()) + 1,
+                     "template_labels": list(t.labels),
+                     "result_vertices": int((r[0] != 0).sum().item()),
+                     "result_entries": bits, "maps": cnt["maps"], "matches": cnt["subgraphs"],
+                     "prune_ms": round(ms, 2), "count_ms": round(cms, 2),
+                     "phases_ms": {k: round(v, 3) for k, v in st.items()
+                                   if k.startswith("ms_")}})
+        ctx.close()
+        del g
+    t = I.template_tri_square(g22, 0)
+    tid = ctx22.load_templates([t])
+    abl = {}
+    ref = None
+    for name, bits in (("default", 0), ("no_edge_elimination", pm.PM_ABLATE_EDGE_ELIMINATION),
+                       ("no_work_aggregation", pm.PM_ABLATE_WORK_AGGREGATION)):
+        ctx22.prune(tid, ablate=bits)
+        ms, (r, e, st) = wall(lambda: ctx22.prune(tid, ablate=bits))
+        if ref is None:
+            ref = (r.clone(), e.clone())
+        abl[name] = {"ms": round(ms, 2), "ms_lcc": round(st["ms_lcc"], 3),
+                     "ms_compact": round(st["ms_compact"], 3), "ms_nlcc": round(st["ms_nlcc"], 3),
+                     "ms_exact": round(st["ms_exact"], 3),
+                     "candidate_entries": st["candidate_entries"],
+                     "edge_queries": st["edge_queries"], "vertex_queries": st["vertex_queries"],
+                     "identical": bool(torch.equal(ref[0], r) and torch.equal(ref[1], e))}
+    return {"topology": {"workload": f"R-MAT scale {scale} ef16, log2-degree labels",
+                         "graphs": rows},
+            "ablations": {"workload": f"scale-22 graph, template {t.labels}", **abl}}
 
 
 if __name__ == "__main__":

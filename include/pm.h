@@ -139,6 +139,8 @@ typedef struct {
                                           its root edge); no single-vertex
                                           swap expansion                     */
 
+typedef struct pm_stats pm_stats;
+
 /* One step of the constraint loop, recorded when options.trace is set. */
 typedef struct {
     int32_t constraint;            /* generation index; -1: the learned loop
@@ -200,11 +202,29 @@ typedef struct {
     const uint64_t *known_edges;   /* device uint64[count][ceil(m/64)] or
                                       NULL: edge bits known to belong to the
                                       complete set (same conditions)          */
+    int32_t shared_inputs;         /* nonzero: init_state, known_roles and
+                                      known_edges are ONE array ([n] or
+                                      [ceil(m/64)]) used for every template of
+                                      the call                                */
+    int32_t pad_;
+    uint64_t *union_roles;         /* device uint64[n] or NULL: every
+                                      template's role masks are ORed into it
+                                      (caller-initialised; atomic, so
+                                      concurrent templates may share it)      */
+    uint64_t *union_edges;         /* device uint64[ceil(m/64)] or NULL: the
+                                      same for the edge bits                  */
+    pm_stats *per_template;        /* host pm_stats[count] or NULL: each
+                                      template's own statistics               */
+    int32_t limit_checks;          /* nonzero: check at most max_checks
+                                      non-local constraints (in the selected
+                                      order), then run the final search as
+                                      usual -- the output does not change     */
+    int32_t max_checks;
     int32_t reserved[4];
 } pm_options;
 
 /* Per-call statistics (valid when pm_prune returns PM_OK). */
-typedef struct {
+struct pm_stats {
     double ms_total;               /* whole prune, device time                */
     double ms_init;                /* role initialisation                     */
     double ms_lcc;                 /* all LCC sweeps                          */
@@ -249,7 +269,7 @@ typedef struct {
                                       templates when count > 1               */
     int64_t workspace_bytes;       /* peak device scratch of one template's
                                       prune (largest over the templates)      */
-} pm_stats;
+};
 
 /* Returns the message for the last error on this thread ("" if none). */
 const char *pm_last_error(void);
@@ -279,6 +299,28 @@ int pm_destroy(pm_ctx *ctx);
    first LCC sweep without reading the adjacency lists. */
 int pm_load_graph(pm_ctx *ctx, int64_t n, int64_t m, const int64_t *row_ptr,
                   const int32_t *col, const void *labels, int label_bytes, uint32_t flags);
+
+/* (Re)build the neighbour-label count index of the loaded graph: one
+   streaming pass over row_ptr and col that gathers every neighbour's label
+   and writes cnt[L][v] (the counts the first LCC sweep of every template
+   reads; vertex state and initialisation plus the LCC rule).  pm_load_graph
+   builds it once; this call rebuilds it, e.g. to time the pass.  *ms (may
+   be NULL) receives its device time (events on the context stream).
+   PM_ERR_INVALID_ARG when the graph is not eligible (labels not uint8 below
+   64, or m >= 2^32). */
+int pm_build_count_index(pm_ctx *ctx, double *ms);
+
+/* Facts about the loaded graph. */
+typedef struct {
+    int64_t n, m;
+    int32_t label_bytes;
+    int32_t index_labels;      /* labels covered by the count index (0: none) */
+    int64_t index_bytes;       /* bytes of the count index                    */
+    int64_t hubs;              /* rows longer than 4096 entries               */
+    int64_t hub_segments;      /* their 4096-entry segments                   */
+    double ms_count_index;     /* device time of the last index build         */
+} pm_graph_info_t;
+int pm_graph_info(pm_ctx *ctx, pm_graph_info_t *out);
 
 /* Forget the loaded graph (and free copies made under PM_HOST_PTRS). */
 int pm_unload_graph(pm_ctx *ctx);

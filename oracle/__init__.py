@@ -74,6 +74,8 @@ def _load():
     lib.orc_exact_sample.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64, P, P, P]
     lib.orc_enumerate.restype = I64
     lib.orc_enumerate.argtypes = [I64, P, P, P, I32, I32, P, P, P, I64]
+    lib.orc_lcc_sample.restype = I64
+    lib.orc_lcc_sample.argtypes = [I64, P, P, P, I32, I32, P, P, P, P, I64, P]
     lib.orc_num_threads.restype = I32
     lib.orc_set_threads.restype = None
     lib.orc_set_threads.argtypes = [I32]
@@ -154,6 +156,19 @@ def exact(g: _G, t: _T, omega: np.ndarray):
     if rc:
         raise ValueError("bad template")
     return role[:g.n], edge[:nwords(g.m)]
+
+
+def lcc_sample(g: _G, t: _T, omega: np.ndarray, verts: np.ndarray):
+    """One LCC sweep evaluated for the given vertices only: (new role masks
+    of those vertices, CSR entries their rows hold).  Timing samples."""
+    vs = np.ascontiguousarray(verts, dtype=np.int32)
+    out = np.zeros(max(vs.shape[0], 1), dtype=np.uint64)
+    om = np.ascontiguousarray(omega, dtype=np.uint64)
+    e = _load().orc_lcc_sample(g.n, _p(g.row_ptr), _p(g.col), _p(g.labels), t.n0, t.m0,
+                               _p(t.labels), _p(t.edges), _p(om), _p(vs), vs.shape[0], _p(out))
+    if e < 0:
+        raise ValueError("bad template")
+    return out[:vs.shape[0]], int(e)
 
 
 def exact_subset(g: _G, t: _T, omega: np.ndarray, verts: np.ndarray) -> int:

@@ -42,6 +42,8 @@
  *                       enumerate every injective, label-preserving map of V0
  *                       that maps E0 into E, and take the union of their
  *                       vertices (with roles) and edges.
+ *   orc_lcc_sample   -- one LCC sweep (the rule above) evaluated for chosen
+ *                       vertices only: timing samples of the CPU baseline.
  *   orc_enumerate    -- the same enumeration, writing every map phi out
  *                       (match enumeration and counting on the reduced
  *                       graph, termination and output section).
@@ -611,4 +613,35 @@ int64_t orc_enumerate(int64_t n, const int64_t *row_ptr, const int32_t *col,
     }
     free(role); free(edge);
     return total;
+}
+
+/* ---- one LCC sweep on sampled vertices ------------------------------------ */
+/* out[i] = the roles of verts[i] that survive one application of the local
+   rule to the state `omega` (the vertex's own roles filtered by
+   role_survives).  Returns the CSR entries the sampled rows hold, or -1. */
+int64_t orc_lcc_sample(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                       const int32_t *vlabel, int n0, int m0, const int32_t *tl,
+                       const int32_t *te, const uint64_t *omega, const int32_t *verts,
+                       int64_t nv, uint64_t *out) {
+    tmpl_t T;
+    if (load_tmpl(&T, n0, m0, tl, te)) return -1;
+    graph_t G = {n, row_ptr, col, vlabel};
+    int nlab = 0;
+    for (int q = 0; q < n0; ++q) if (T.label[q] + 1 > nlab) nlab = T.label[q] + 1;
+    uint64_t *labmask = (uint64_t *)calloc((size_t)nlab + 1, sizeof(uint64_t));
+    for (int q = 0; q < n0; ++q) labmask[T.label[q]] |= 1ull << q;
+    int64_t entries = 0;
+    #pragma omp parallel for schedule(dynamic, 256) reduction(+:entries)
+    for (int64_t i = 0; i < nv; ++i) {
+        const int64_t v = verts[i];
+        const uint64_t w = omega[v];
+        uint64_t nw = 0;
+        for (int q = 0; q < T.n0; ++q)
+            if (((w >> q) & 1) && role_survives(&G, &T, omega, v, q, labmask, nlab))
+                nw |= 1ull << q;
+        out[i] = nw;
+        entries += row_ptr[v + 1] - row_ptr[v];
+    }
+    free(labmask);
+    return entries;
 }

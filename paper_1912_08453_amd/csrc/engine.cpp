@@ -182,6 +182,9 @@ struct pm_ctx {
     // of neighbours of v with label L at lab_cnt[L * n + v]; nlab = 0: none
     DevBuf lab_cnt;
     int nlab = 0;
+    int index_nlab = 0;                  // labels the index would cover (0: not eligible)
+    DevBuf idx_hub_v, idx_seg_slot, idx_seg_b, idx_seg_e, idx_hub_cnt;
+    int64_t idx_hubs = 0, idx_segs = 0;
     int64_t cnt_stride = 0;
     double ms_count_index = 0.0;
     int64_t hub_cap = 0, seg_cap = 0;
@@ -797,8 +800,11 @@ struct Pruner {
         int done = __builtin_popcountll(skipped);
         size_t pos = 0;
         int64_t pending_after = -1;   // trace entry waiting for roles_after
+        int checked = 0;
+        const int limit = opt && opt->limit_checks ? std::max(0, opt->max_checks) : K + 1;
         while (done < K) {
             if (stop_after >= 0 && done >= stop_after) break;
+            if (checked >= limit) break;
             if (nA == 0) break;
             OrderPick pk{};
             int k = -1;
@@ -842,6 +848,7 @@ struct Pruner {
             remaining &= ~(1ull << k);
             done_mask |= 1ull << k;
             ++done;
+            ++checked;
             if (trace && n_trace < cap) {
                 pm_trace_entry &e = trace[n_trace];
                 e = pm_trace_entry{};
@@ -1164,6 +1171,39 @@ int guarded(F &&f) {
     }
 }
 
+// (Re)build the neighbour-label count index of the loaded graph (one pass
+// over the CSR), timed with events on the context stream.
+void build_count_index(pm_ctx *c) {
+    const int nlab = c->index_nlab;
+    const int64_t n = c->n;
+    const int64_t np = (n + 255) / 256 * 256;
+    c->lab_cnt.ensure((size_t)np * (size_t)nlab);
+    c->cnt_stride = np;
+    CountIndexHubs h;
+    h.n_hubs = c->idx_hubs;
+    h.n_segs = c->idx_segs;
+    h.hub_v = c->idx_hub_v.as<int32_t>();
+    h.seg_slot = c->idx_seg_slot.as<int32_t>();
+    h.seg_b = c->idx_seg_b.as<int64_t>();
+    h.seg_e = c->idx_seg_e.as<int64_t>();
+    h.hub_cnt = c->idx_hub_cnt.as<uint32_t>();
+    hipEvent_t a, b;
+    PM_HIP(hipEventCreate(&a));
+    PM_HIP(hipEventCreate(&b));
+    PM_HIP(hipEventRecord(a, c->stream));
+    launch_label_count(c->stream, n, np, c->rp, c->col, (const uint8_t *)c->labels, nlab,
+                       c->lab_cnt.as<uint8_t>(), h);
+    PM_HIP(hipGetLastError());
+    PM_HIP(hipEventRecord(b, c->stream));
+    PM_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    PM_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    c->ms_count_index = ms;
+    c->nlab = nlab;
+}
+
 int workers_for(const pm_options *opt, int32_t count) {
     int nw = 1;
     if (opt && opt->batch_streams > 1 && count > 1)
@@ -1348,9 +1388,11 @@ void prune_impl(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask,
         uint64_t *eo = edge_bits ? edge_bits + (size_t)i * (size_t)words : nullptr;
         pm_options o = opt ? *opt : pm_options{};
         if (!opt) o.stop_after = -1;
-        if (o.init_state) o.init_state += (size_t)i * (size_t)c->n;
-        if (o.known_roles) o.known_roles += (size_t)i * (size_t)c->n;
-        if (o.known_edges) o.known_edges += (size_t)i * (size_t)words;
+        if (!o.shared_inputs) {
+            if (o.init_state) o.init_state += (size_t)i * (size_t)c->n;
+            if (o.known_roles) o.known_roles += (size_t)i * (size_t)c->n;
+            if (o.known_edges) o.known_edges += (size_t)i * (size_t)words;
+        }
         w->reset_arena();
         auto go = [&](auto &p) {
             if (na) {
@@ -1359,6 +1401,8 @@ void prune_impl(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask,
             }
             p.run(ro, eo);
             per[(size_t)i] = p.st;
+            if (o.union_roles) launch_or_into(w->stream, c->n, ro, o.union_roles);
+            if (o.union_edges && eo) launch_or_into(w->stream, words, eo, o.union_edges);
         };
         switch (T.mask_bytes) {
         case 1: { Pruner<uint8_t> p(c, w, T, &o); go(p); break; }
@@ -1452,6 +1496,8 @@ void prune_impl(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask,
     PM_HIP(hipStreamSynchronize(c->stream));
     if (na) c->scratch[0]->use_arena(nullptr, 0);
     if (stats) *stats = total;
+    if (opt && opt->per_template)
+        for (int32_t i = 0; i < count; ++i) opt->per_template[i] = per[(size_t)i];
 }
 
 }  // namespace
@@ -1514,7 +1560,9 @@ int pm_destroy(pm_ctx *c) {
         if (!c) return;
         (void)hipSetDevice(c->device);
         for (auto &t : c->templates) free_template_device(*t);
-        for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->lab_cnt}) b->release();
+        for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->lab_cnt, &c->idx_hub_v,
+                          &c->idx_seg_slot, &c->idx_seg_b, &c->idx_seg_e, &c->idx_hub_cnt})
+            b->release();
         c->scratch.clear();
         for (DevBuf *b : {&c->model, &c->mlp_partial, &c->mlp_ploss, &c->mlp_grad, &c->mlp_m,
                           &c->mlp_v, &c->mlp_loss})
@@ -1556,7 +1604,11 @@ int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const
         c->own_col.release();
         c->own_labels.release();
         c->lab_cnt.release();
+        for (DevBuf *b : {&c->idx_hub_v, &c->idx_seg_slot, &c->idx_seg_b, &c->idx_seg_e, &c->idx_hub_cnt})
+            b->release();
         c->nlab = 0;
+        c->index_nlab = 0;
+        c->idx_hubs = c->idx_segs = 0;
         if (host) {
             c->own_rp.ensure(sizeof(int64_t) * (size_t)(n + 1));
             c->own_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1));
@@ -1606,34 +1658,75 @@ int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const
         PM_HIP(hipStreamSynchronize(c->stream));
         c->label_degsum.assign(h.begin(), h.end());
         hist.release();
-        // neighbour-label count index for the first LCC sweep
+        // neighbour-label count index for the first LCC sweep (uint8 labels
+        // below kCountLabels; tile offsets are 32-bit, so m < 2^32)
         int maxl = -1;
         for (int64_t L = 0; L < hl; ++L)
             if (h[(size_t)L]) maxl = (int)L;
-        const char *noidx = getenv("PM_NO_COUNT_INDEX");
+        c->index_nlab = 0;
         if (label_bytes == 1 && maxl >= 0 && maxl < kCountLabels && n > 0 &&
-            !(noidx && atoi(noidx))) {
-            const int nlab = maxl + 1;
-            const int64_t np = (n + 255) / 256 * 256;
-            c->lab_cnt.ensure((size_t)np * (size_t)nlab);
-            c->cnt_stride = np;
-            hipEvent_t a, b;
-            PM_HIP(hipEventCreate(&a));
-            PM_HIP(hipEventCreate(&b));
-            PM_HIP(hipEventRecord(a, c->stream));
-            launch_label_count(c->stream, n, np, c->rp, c->col, (const uint8_t *)c->labels, nlab,
-                               c->lab_cnt.as<uint8_t>());
-            PM_HIP(hipGetLastError());
-            PM_HIP(hipEventRecord(b, c->stream));
-            PM_HIP(hipEventSynchronize(b));
-            float ms = 0;
-            PM_HIP(hipEventElapsedTime(&ms, a, b));
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-            c->ms_count_index = ms;
-            c->nlab = nlab;
+            m < ((int64_t)1 << 32)) {
+            c->index_nlab = maxl + 1;
+            // hub rows and their segments, for the index's hub pass
+            std::vector<int32_t> hv, ss;
+            std::vector<int64_t> sb, se;
+            for (int64_t v = 0; v < n; ++v) {
+                const int64_t d = h_rp[(size_t)v + 1] - h_rp[(size_t)v];
+                if (d <= kBinWaveMaxDeg) continue;
+                for (int64_t b = h_rp[(size_t)v]; b < h_rp[(size_t)v + 1]; b += kHubSegment) {
+                    ss.push_back((int32_t)hv.size());
+                    sb.push_back(b);
+                    se.push_back(std::min<int64_t>(b + kHubSegment, h_rp[(size_t)v + 1]));
+                }
+                hv.push_back((int32_t)v);
+            }
+            c->idx_hubs = (int64_t)hv.size();
+            c->idx_segs = (int64_t)ss.size();
+            if (!hv.empty()) {
+                c->idx_hub_v.ensure(sizeof(int32_t) * hv.size());
+                c->idx_seg_slot.ensure(sizeof(int32_t) * ss.size());
+                c->idx_seg_b.ensure(sizeof(int64_t) * sb.size());
+                c->idx_seg_e.ensure(sizeof(int64_t) * se.size());
+                c->idx_hub_cnt.ensure(sizeof(uint32_t) * hv.size() * kCountLabels);
+                PM_HIP(hipMemcpy(c->idx_hub_v.p, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice));
+                PM_HIP(hipMemcpy(c->idx_seg_slot.p, ss.data(), sizeof(int32_t) * ss.size(), hipMemcpyHostToDevice));
+                PM_HIP(hipMemcpy(c->idx_seg_b.p, sb.data(), sizeof(int64_t) * sb.size(), hipMemcpyHostToDevice));
+                PM_HIP(hipMemcpy(c->idx_seg_e.p, se.data(), sizeof(int64_t) * se.size(), hipMemcpyHostToDevice));
+            }
         }
+        const char *noidx = getenv("PM_NO_COUNT_INDEX");
+        if (c->index_nlab > 0 && !(noidx && atoi(noidx))) build_count_index(c);
         c->has_graph = true;
+    });
+}
+
+int pm_build_count_index(pm_ctx *c, double *ms) {
+    return guarded([&] {
+        if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
+        if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
+        if (c->index_nlab <= 0)
+            throw Error(PM_ERR_INVALID_ARG, "graph not eligible for the count index "
+                                            "(needs uint8 labels below 64 and m < 2^32)");
+        set_device(c);
+        build_count_index(c);
+        if (ms) *ms = c->ms_count_index;
+    });
+}
+
+int pm_graph_info(pm_ctx *c, pm_graph_info_t *out) {
+    return guarded([&] {
+        if (!c || !out) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
+        pm_graph_info_t g{};
+        g.n = c->n;
+        g.m = c->m;
+        g.label_bytes = c->label_bytes;
+        g.index_labels = c->nlab;
+        g.index_bytes = c->nlab > 0 ? c->cnt_stride * (int64_t)c->nlab : 0;
+        g.hubs = c->idx_hubs;
+        g.hub_segments = c->idx_segs;
+        g.ms_count_index = c->ms_count_index;
+        *out = g;
     });
 }
 

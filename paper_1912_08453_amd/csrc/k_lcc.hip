@@ -236,56 +236,6 @@ static unsigned stage_grid(int64_t n_in) {
 }
 
 // ---------------------------------------- first LCC sweep from label counts
-// Neighbour-label counts of the loaded graph (an index built once per
-// graph, for uint8 labels below kCountLabels): cnt[L * np + v] = number of
-// neighbours of v with label L, saturated at 255 (np = n rounded up to a
-// multiple of kBlock; the padding holds zeros).  A block takes tiles of
-// kBlock consecutive vertices; its wavefronts count one vertex at a time
-// with an LDS histogram, the saturated counts gather in an LDS tile, and
-// the block writes each label's counts for the tile as one contiguous run.
-__global__ __launch_bounds__(kBlock) void label_count_kernel(int64_t n, int64_t np,
-                                                             const int64_t *rp,
-                                                             const int32_t *col,
-                                                             const uint8_t *labels, int nlab,
-                                                             uint8_t *cnt) {
-    __shared__ unsigned int acc[kBlock / kWave][kWave];
-    __shared__ uint8_t tile[kCountLabels][kBlock];
-    const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < n; t0 += (int64_t)gridDim.x * kBlock) {
-        for (int j = wib; j < kBlock; j += kBlock / kWave) {
-            const int64_t v = t0 + j;
-            acc[wib][lane] = 0;
-            __builtin_amdgcn_wave_barrier();
-            if (v < n) {
-                const int64_t e1 = rp[v + 1];
-                for (int64_t e = rp[v] + lane; e < e1; e += kWave) {
-                    const int L = labels[col[e]];
-                    if (L < nlab) atomicAdd(&acc[wib][L], 1u);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane < nlab) {
-                const unsigned int c = acc[wib][lane];
-                tile[lane][j] = (uint8_t)(c > 255u ? 255u : c);
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        __syncthreads();
-        for (int L = 0; L < nlab; ++L) cnt[(int64_t)L * np + t0 + threadIdx.x] = tile[L][threadIdx.x];
-        __syncthreads();
-    }
-}
-
-void launch_label_count(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
-                        const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt) {
-    if (n <= 0) return;
-    int64_t grid = (n + kBlock - 1) / kBlock;
-    if (grid > 16384) grid = 16384;
-    hipLaunchKernelGGL(label_count_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, n, np, rp,
-                       col, labels, nlab, cnt);
-}
-
 // The first LCC sweep evaluated from the initial role sets alone: with
 // omega0(u) = roles of u's label, a neighbour u covers template neighbour
 // q' of q iff label(u) = label(q'), and the distinct-count rule for label L
@@ -896,6 +846,8 @@ void launch_compact_fill(hipStream_t s, const int64_t *rp, const int32_t *col, c
 }
 
 // --------------------------------------------------------- exclusive scan
+__global__ void fill_from_kernel(const int64_t *src, int64_t *dst) { *dst = *src; }
+
 // out[i] = in[0] + ... + in[i-1] for i in [0, n]; three passes over tiles of
 // kScanTile elements.
 constexpr int kScanPer = 16;
@@ -920,69 +872,113 @@ __global__ __launch_bounds__(kBlock) void scan_tile_sums(const int64_t *in, int6
     }
 }
 
-__global__ __launch_bounds__(1024) void scan_sums_kernel(int64_t *sums, int64_t nb, int64_t *total) {
-    __shared__ int64_t sc[1024];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < nb; base += 1024) {
-        int64_t i = base + threadIdx.x;
-        int64_t x = i < nb ? sums[i] : 0;
-        sc[threadIdx.x] = x;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int64_t t = threadIdx.x >= (unsigned)off ? sc[threadIdx.x - off] : 0;
-            __syncthreads();
-            sc[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nb) sums[i] = carry + sc[threadIdx.x] - x;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += sc[1023];
-        __syncthreads();
+// Block-wide exclusive scan of one value per thread (kBlock threads): wave
+// scans by shuffles, then the wave totals through LDS.  Returns the
+// exclusive prefix; *total receives the block's sum.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t *wsum,
+                                                        int64_t *total) {
+    const int lane = lane_id();
+    const int w = threadIdx.x / kWave;
+    int64_t inc = x;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t t = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += t;
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) {
+        const int64_t v = wsum[i];
+        if (i < w) before += v;
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
+// One tile of kScanTile elements, coalesced: staged through LDS (rows of
+// kScanPer elements padded by one, so a thread's row reads hit distinct
+// banks), each thread sums its row, the block scans the row sums, and the
+// exclusive prefixes go back through LDS to coalesced stores.  in may equal
+// out.  base_add is added to every output.
+__device__ __forceinline__ void scan_tile(const int64_t *in, int64_t *out, int64_t n,
+                                          int64_t tile0, int64_t base_add, int64_t *stage,
+                                          int64_t *wsum, int64_t *tile_total) {
+    constexpr int kPad = kScanPer + 1;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int e = j * kBlock + threadIdx.x;          // element within the tile
+        const int64_t i = tile0 + e;
+        stage[(e / kScanPer) * kPad + (e % kScanPer)] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    int64_t row = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) row += stage[threadIdx.x * kPad + j];
+    int64_t total = 0;
+    int64_t run = block_exclusive_scan(row, wsum, &total) + base_add;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int64_t v = stage[threadIdx.x * kPad + j];
+        stage[threadIdx.x * kPad + j] = run;
+        run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int e = j * kBlock + threadIdx.x;
+        const int64_t i = tile0 + e;
+        if (i < n) out[i] = stage[(e / kScanPer) * kPad + (e % kScanPer)];
+    }
+    __syncthreads();
+    *tile_total = total;
+}
+
+// Exclusive scan of at most kScanTile values in place; *total_out receives
+// their sum.
+__global__ __launch_bounds__(kBlock) void scan_small_kernel(int64_t *a, int64_t n,
+                                                            int64_t *total_out) {
+    __shared__ int64_t stage[kBlock * (kScanPer + 1)];
+    __shared__ int64_t wsum[kBlock / kWave];
+    int64_t total = 0;
+    scan_tile(a, a, n, 0, 0, stage, wsum, &total);
+    if (threadIdx.x == 0) *total_out = total;
 }
 
 __global__ __launch_bounds__(kBlock) void scan_apply(const int64_t *in, int64_t n,
                                                      const int64_t *sums, int64_t *out) {
-    __shared__ int64_t ts[kBlock];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-    int64_t v[kScanPer];
-    int64_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
-        int64_t i = base + j;
-        v[j] = i < n ? in[i] : 0;
-        acc += v[j];
-    }
-    ts[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        int64_t t = threadIdx.x >= (unsigned)off ? ts[threadIdx.x - off] : 0;
-        __syncthreads();
-        ts[threadIdx.x] += t;
-        __syncthreads();
-    }
-    int64_t run = sums[blockIdx.x] + ts[threadIdx.x] - acc;
-#pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
-        int64_t i = base + j;
-        if (i < n) out[i] = run;
-        run += v[j];
-    }
+    __shared__ int64_t stage[kBlock * (kScanPer + 1)];
+    __shared__ int64_t wsum[kBlock / kWave];
+    int64_t total = 0;
+    scan_tile(in, out, n, (int64_t)blockIdx.x * kScanTile, sums[blockIdx.x], stage, wsum, &total);
 }
 
+// Tile sums, an exclusive scan of the tile sums (in one block when there
+// are at most kScanTile of them, else recursively), then every tile scanned
+// with its offset.  scratch holds scan_scratch_len(n) values.
 void launch_exclusive_scan(hipStream_t s, const int64_t *in, int64_t *out, int64_t n,
-                           int64_t *scratch, int64_t) {
+                           int64_t *scratch, int64_t len) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, scratch, nb, out + n);
+    if (nb <= kScanTile) {
+        hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kBlock), 0, s, scratch, nb, out + n);
+    } else {
+        // scratch[0, nb) scanned in place; its total to out[n]
+        launch_exclusive_scan(s, scratch, scratch, nb, scratch + nb + 1, len - nb - 1);
+        hipLaunchKernelGGL(fill_from_kernel, dim3(1), dim3(1), 0, s, scratch + nb, out + n);
+    }
     hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch, out);
 }
 
-int64_t scan_scratch_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+int64_t scan_scratch_len(int64_t n) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1) nb = 1;
+    return nb + 1 + (nb > kScanTile ? scan_scratch_len(nb) : 0);
+}
 
 // ---------------------------------------------------------------- fills
 __global__ void fill_u64_kernel(uint64_t *p, int64_t n, uint64_t v) {

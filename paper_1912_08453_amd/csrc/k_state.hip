@@ -91,19 +91,52 @@ void launch_known_edges(hipStream_t s, int64_t c_m, const int32_t *c_own, const 
                        dim3(kStateBlock), 0, s, c_m, c_own, c_off, rp, known, c_cert);
 }
 
+// Unions over the templates of one call: dst |= src, word by word.  Atomic,
+// since templates pruned on concurrent streams share dst; a word whose src
+// is zero is not touched.
+__global__ __launch_bounds__(kStateBlock) void or_into_kernel(int64_t n, const uint64_t *src,
+                                                              uint64_t *dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = src[i];
+        if (x) atomicOr((unsigned long long *)(dst + i), (unsigned long long)x);
+    }
+}
+
+void launch_or_into(hipStream_t s, int64_t n, const uint64_t *src, uint64_t *dst) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(or_into_kernel, dim3((unsigned)grid_for(n)), dim3(kStateBlock), 0, s, n,
+                       src, dst);
+}
+
 // Sum of degrees per label (labels below hist_len): bounds the entries of
-// the candidate subgraph of a template from its labels alone.
+// the candidate subgraph of a template from its labels alone.  8-bit labels
+// accumulate in LDS, one global atomic per label and block.
 __global__ __launch_bounds__(kStateBlock) void label_degsum_kernel(int64_t n, const int64_t *rp,
                                                                    const void *labels,
                                                                    int label_bytes,
                                                                    unsigned long long *sum,
                                                                    int64_t hist_len) {
+    __shared__ unsigned long long local[256];
+    const bool small = label_bytes == 1 && hist_len <= 256;
+    if (small) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) local[i] = 0;
+        __syncthreads();
+    }
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t L = label_bytes == 1 ? (int64_t)((const uint8_t *)labels)[v]
                                            : (int64_t)((const uint16_t *)labels)[v];
         const int64_t d = rp[v + 1] - rp[v];
-        if (L < hist_len && d) atomicAdd(&sum[L], (unsigned long long)d);
+        if (L < hist_len && d) {
+            if (small) atomicAdd(&local[L], (unsigned long long)d);
+            else atomicAdd(&sum[L], (unsigned long long)d);
+        }
+    }
+    if (small) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 256; i += blockDim.x)
+            if (local[i]) atomicAdd(&sum[i], local[i]);
     }
 }
 

@@ -360,8 +360,20 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst);
 // up to a multiple of 256 (labels and omega must allow 4-byte accesses at
 // multiples of 4: device allocations are aligned).
 constexpr int kCountLabels = 64;
+// Hub rows (more than kBinWaveMaxDeg entries) of the count index, counted by
+// segments of kHubSegment entries: segment s covers entries [seg_b, seg_e)
+// of hub slot seg_slot[s], whose vertex is hub_v[slot]; hub_cnt holds
+// [n_hubs][kCountLabels] 32-bit counts (cleared by the launcher).
+struct CountIndexHubs {
+    int64_t n_hubs = 0, n_segs = 0;
+    const int32_t *hub_v = nullptr;
+    const int32_t *seg_slot = nullptr;
+    const int64_t *seg_b = nullptr, *seg_e = nullptr;
+    uint32_t *hub_cnt = nullptr;
+};
 void launch_label_count(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
-                        const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt);
+                        const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt,
+                        const CountIndexHubs &h);
 
 // First LCC sweep from the count index: omega(v) = roles q of label(v) with
 // cnt[L][v] >= need for every (L, need) of q (need_off[q] .. need_off[q+1]
@@ -396,6 +408,8 @@ void launch_known_roles(hipStream_t s, const int32_t *tasks, int64_t n_tasks, co
                         const uint64_t *known, M *cert);
 void launch_known_edges(hipStream_t s, int64_t c_m, const int32_t *c_own, const int32_t *c_off,
                         const int64_t *rp, const uint64_t *known, uint64_t *c_cert);
+// dst[i] |= src[i] (atomic OR per 64-bit word), i < n.
+void launch_or_into(hipStream_t s, int64_t n, const uint64_t *src, uint64_t *dst);
 void launch_label_degsum(hipStream_t s, int64_t n, const int64_t *rp, const void *labels,
                          int label_bytes, unsigned long long *sum, int64_t hist_len);
 constexpr size_t kNoAllocBytes = PM_NOALLOC_SCRATCH_BYTES;

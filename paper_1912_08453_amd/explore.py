@@ -8,16 +8,24 @@ that level.  Here a variant keeps all template vertices and must stay
 connected (as in the incremental scenario), variants that are the same up
 to a label-preserving relabelling are searched once (they have the same
 matches as vertex and edge sets), and each level is pruned by batched
-pm_prune calls on the resident graph.  The union is taken over the complete
-sets the library returns: a vertex is in it if it holds a role in some
-variant's complete set, an edge if it is in some variant's edge set.
+pm_prune calls on the resident graph.
+
+Candidate set (the key enabler the paper names for this scenario): before
+level 0 the base template is pruned in PM_MODE_CANDIDATE -- local checks
+only, with the rule relaxed so that the result holds the complete set of
+every connected variant obtained by deleting edges -- and every variant of
+every level then starts from that set (one shared init_state) instead of
+from the label roles of the whole graph.  The library ORs the complete sets
+of a level into its union buffers (a vertex is in the union iff it holds a
+role in some variant's complete set; its bits are the roles it holds in the
+class representatives searched, not in every isomorphic copy).
 
     from paper_1912_08453_amd import explore
     res = explore.explore(ctx, labels, edges, max_deletions=3)
 
-The paper further restricts later searches to a candidate set and reuses
-non-local constraint results across variants; neither is done here, every
-variant is pruned from the full graph.
+Non-local constraint results are not carried from one variant to the next:
+each variant's checks run against its own state, which is sound only for
+that variant.
 """
 from __future__ import annotations
 
@@ -124,17 +132,30 @@ class ExploreResult:
 
 def explore(ctx, labels: Sequence[int], edges: Sequence[Tuple[int, int]],
             max_deletions: Optional[int] = None, batch: int = 32, batch_streams: int = 4,
-            log=None) -> ExploreResult:
+            use_candidate_set: bool = True, log=None) -> ExploreResult:
     """Search levels 0, 1, ... (at most max_deletions, default: as long as
     variants remain) until a level has a variant with a match; see the
     module docstring."""
     import torch
+    from . import pm as _pm
     labels = [int(x) for x in labels]
     edges = [tuple(int(v) for v in e) for e in edges]
     top = len(edges) if max_deletions is None else min(max_deletions, len(edges))
     dev = ctx.device
     n, words = ctx.n, (ctx.m + 63) // 64
     res = ExploreResult(level=-1)
+    cand = None
+    if use_candidate_set:
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        base = ctx.load_templates([_Variant(labels, edges)])
+        role, _, _ = ctx.prune(base, mode=_pm.PM_MODE_CANDIDATE)
+        cand = role[0].contiguous()
+        torch.cuda.synchronize(dev)
+        ms = 1e3 * (time.perf_counter() - t0)
+        res.levels.append({"level": "candidate set", "ms": round(ms, 2)})
+        if log:
+            log(f"candidate set: {ms:.1f} ms")
     for k in range(top + 1):
         vs = variants(labels, edges, k)
         if not vs:
@@ -147,12 +168,10 @@ def explore(ctx, labels: Sequence[int], edges: Sequence[Tuple[int, int]],
         for s in range(0, len(vs), batch):
             chunk = vs[s:s + batch]
             first = ctx.load_templates([_Variant(labels, es) for es in chunk])
-            role, edge, _ = ctx.prune(first, count=len(chunk), batch_streams=batch_streams)
-            for i in range(len(chunk)):
-                matched.append(bool(role[i].any().item()))
-                r_un |= role[i]
-                e_un |= edge[i]
-            del role, edge
+            _, _, st = ctx.prune(first, count=len(chunk), batch_streams=batch_streams,
+                                 init_state=cand, shared_inputs=True, union_roles=r_un,
+                                 union_edges=e_un, per_template=True)
+            matched += [p["result_vertices"] > 0 for p in st["per_template"]]
         torch.cuda.synchronize(dev)
         ms = 1e3 * (time.perf_counter() - t0)
         res.levels.append({"level": k, "variants": len(vs), "matched": int(sum(matched)),

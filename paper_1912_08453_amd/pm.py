@@ -45,7 +45,7 @@ SYMBOLS = ["pm_last_error", "pm_version", "pm_create", "pm_destroy", "pm_load_gr
            "pm_inspect_template", "pm_prune", "pm_load_model", "pm_mlp_forward", "pm_mlp_grad",
            "pm_mlp_train", "pm_set_param", "pm_get_param", "pm_export_state",
            "pm_import_state", "pm_workspace_size", "pm_set_workspace", "pm_prune_noalloc",
-           "pm_count_matches"]
+           "pm_count_matches", "pm_build_count_index", "pm_graph_info"]
 
 
 class PMError(RuntimeError):
@@ -74,17 +74,6 @@ class pm_trace_entry(ctypes.Structure):
                 "predicted": list(self.predicted), "features": list(self.features)}
 
 
-class pm_options(ctypes.Structure):
-    _fields_ = [("order_mode", ctypes.c_int32), ("n_order", ctypes.c_int32),
-                ("order", ctypes.c_int32 * MAX_CONSTRAINTS), ("stop_after", ctypes.c_int32),
-                ("batch_streams", ctypes.c_int32), ("learned_min_score", ctypes.c_float),
-                ("learned_stop", ctypes.c_int32), ("trace_cap", ctypes.c_int32),
-                ("trace", ctypes.POINTER(pm_trace_entry)), ("mode", ctypes.c_int32),
-                ("ablate", ctypes.c_uint32), ("init_state", ctypes.c_void_p),
-                ("skip_mask", ctypes.c_uint64), ("known_roles", ctypes.c_void_p),
-                ("known_edges", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 4)]
-
-
 class pm_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("ms_total", "ms_init", "ms_lcc", "ms_compact", "ms_nlcc", "ms_exact",
@@ -100,6 +89,31 @@ class pm_stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class pm_options(ctypes.Structure):
+    _fields_ = [("order_mode", ctypes.c_int32), ("n_order", ctypes.c_int32),
+                ("order", ctypes.c_int32 * MAX_CONSTRAINTS), ("stop_after", ctypes.c_int32),
+                ("batch_streams", ctypes.c_int32), ("learned_min_score", ctypes.c_float),
+                ("learned_stop", ctypes.c_int32), ("trace_cap", ctypes.c_int32),
+                ("trace", ctypes.POINTER(pm_trace_entry)), ("mode", ctypes.c_int32),
+                ("ablate", ctypes.c_uint32), ("init_state", ctypes.c_void_p),
+                ("skip_mask", ctypes.c_uint64), ("known_roles", ctypes.c_void_p),
+                ("known_edges", ctypes.c_void_p), ("shared_inputs", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("union_roles", ctypes.c_void_p),
+                ("union_edges", ctypes.c_void_p),
+                ("per_template", ctypes.POINTER(pm_stats)), ("limit_checks", ctypes.c_int32),
+                ("max_checks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class pm_graph_info_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("label_bytes", ctypes.c_int32),
+                ("index_labels", ctypes.c_int32), ("index_bytes", ctypes.c_int64),
+                ("hubs", ctypes.c_int64), ("hub_segments", ctypes.c_int64),
+                ("ms_count_index", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class pm_match_count(ctypes.Structure):
@@ -157,6 +171,8 @@ def load_library():
     lib.pm_prune_noalloc.argtypes = [P, I32, P, P, ctypes.POINTER(pm_options),
                                      ctypes.POINTER(pm_stats)]
     lib.pm_count_matches.argtypes = [P, I32, P, P, I64, ctypes.POINTER(pm_match_count)]
+    lib.pm_build_count_index.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    lib.pm_graph_info.argtypes = [P, ctypes.POINTER(pm_graph_info_t)]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -229,6 +245,17 @@ class PM:
         self.n, self.m = n, m
         self._graph_refs = refs if not (flags & PM_HOST_PTRS) else None
 
+    def build_count_index(self) -> float:
+        """Rebuild the neighbour-label count index; returns its device ms."""
+        ms = ctypes.c_double()
+        _check(self.lib, self.lib.pm_build_count_index(self.h, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def graph_info(self) -> dict:
+        g = pm_graph_info_t()
+        _check(self.lib, self.lib.pm_graph_info(self.h, ctypes.byref(g)))
+        return g.as_dict()
+
     # --------------------------------------------------------- templates
     def load_templates(self, templates: Sequence) -> int:
         """templates: objects with .labels (list[int]) and .edges (list of
@@ -267,7 +294,8 @@ class PM:
     # ------------------------------------------------------------- prune
     def _options(self, order=None, stop_after=-1, batch_streams=0, learned_min_score=None,
                  mode=PM_MODE_FULL, ablate=0, init_state=None, skip_mask=0, known_roles=None,
-                 known_edges=None):
+                 known_edges=None, shared_inputs=False, union_roles=None, union_edges=None,
+                 max_checks=None):
         opt = pm_options()
         opt.stop_after = stop_after
         opt.batch_streams = batch_streams
@@ -285,8 +313,13 @@ class PM:
         if learned_min_score is not None:
             opt.learned_stop = 1
             opt.learned_min_score = float(learned_min_score)
+        opt.shared_inputs = 1 if shared_inputs else 0
+        if max_checks is not None:
+            opt.limit_checks = 1
+            opt.max_checks = int(max_checks)
         for name, t in (("init_state", init_state), ("known_roles", known_roles),
-                        ("known_edges", known_edges)):
+                        ("known_edges", known_edges), ("union_roles", union_roles),
+                        ("union_edges", union_edges)):
             if t is not None:
                 self._check_device_i64(t, name)
                 setattr(opt, name, t.data_ptr())
@@ -303,14 +336,21 @@ class PM:
               stop_after: int = -1, role_mask=None, edge_bits=None, batch_streams: int = 0,
               learned_min_score: Optional[float] = None, trace: bool = False,
               mode: int = PM_MODE_FULL, ablate: int = 0, init_state=None, skip_mask: int = 0,
-              known_roles=None, known_edges=None):
+              known_roles=None, known_edges=None, shared_inputs: bool = False,
+              union_roles=None, union_edges=None, per_template: bool = False,
+              max_checks: Optional[int] = None):
         """Returns (role_mask uint64-as-int64 tensor [count, n], edge_bits
         [count, ceil(m/64)], stats dict); with trace=True the stats dict also
         holds "trace", the list of per-step records.  order: None (fixed),
         "learned" (greedy by the loaded model), or a permutation.  mode:
         PM_MODE_FULL or PM_MODE_CANDIDATE; ablate: PM_ABLATE_* bits;
         init_state / known_roles [count, n] and known_edges [count, words]:
-        device int64 tensors (see pm.h)."""
+        device int64 tensors (one [n] / [words] array for all templates with
+        shared_inputs); union_roles [n] / union_edges [words]: device int64
+        tensors every template's output is ORed into (see pm.h).  With
+        per_template the stats dict holds "per_template", one dict per
+        template.  max_checks: check at most that many non-local constraints
+        before the final search (output unchanged)."""
         torch = self.torch
         words = (self.m + 63) // 64
         if role_mask is None:
@@ -318,7 +358,12 @@ class PM:
         if edge_bits is None:
             edge_bits = torch.empty((count, max(words, 1)), dtype=torch.int64, device=self.device)
         opt = self._options(order, stop_after, batch_streams, learned_min_score, mode, ablate,
-                            init_state, skip_mask, known_roles, known_edges)
+                            init_state, skip_mask, known_roles, known_edges, shared_inputs,
+                            union_roles, union_edges, max_checks)
+        per = None
+        if per_template:
+            per = (pm_stats * count)()
+            opt.per_template = ctypes.cast(per, ctypes.POINTER(pm_stats))
         tr = None
         if trace:
             tr = (pm_trace_entry * (MAX_CONSTRAINTS + 1))()
@@ -330,6 +375,8 @@ class PM:
                                            ctypes.c_void_p(edge_bits.data_ptr()),
                                            ctypes.byref(opt), ctypes.byref(st)))
         out = st.as_dict()
+        if per is not None:
+            out["per_template"] = [per[i].as_dict() for i in range(count)]
         if tr is not None:
             out["trace"] = [tr[i].as_dict() for i in range(int(st.trace_entries))]
         return role_mask[:, :self.n], edge_bits[:, :words], out

@@ -77,8 +77,8 @@ def main():
     g = I.Graph(rp, col, labels)
     # the workers are spawned (an OpenMP runtime does not survive fork) and
     # map the graph from files
-    import tempfile
-    tmpdir = tempfile.mkdtemp(prefix="pm_golden_")
+    tmpdir = os.path.join(os.path.dirname(OUT), ".graph_tmp")
+    os.makedirs(tmpdir, exist_ok=True)
     paths = []
     for name, arr in (("rp", rp), ("col", col), ("labels", labels)):
         paths.append(os.path.join(tmpdir, name + ".npy"))

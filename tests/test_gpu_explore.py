@@ -3,7 +3,8 @@ the one it stops at have no match in any variant, and at that level the
 union of the complete sets (vertices with a role, role bits, edges) equals
 the union of the oracle's complete sets of the same level's variants (the
 variants enumerated independently, with the input generator's relaxation
-list)."""
+list).  With and without the candidate set of the base template as every
+variant's starting state."""
 import sys
 
 import numpy as np
@@ -37,19 +38,21 @@ def pmmod():
 K4 = [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2), (1, 3)]
 
 
+@pytest.mark.parametrize("cand", [True, False])
 @pytest.mark.parametrize("seed,labels,max_del", [
     (1, [0, 1, 2, 3], None),
     (2, [0, 1, 0, 1], None),
     (3, [0, 1, 2, 3], 0),
 ])
-def test_explore_against_oracle(pmmod, torch_dev, seed, labels, max_del):
+def test_explore_against_oracle(pmmod, torch_dev, seed, labels, max_del, cand):
     from paper_1912_08453_amd import explore
     torch, dev = torch_dev
     g = I.random_graph(300, 0.03, 4, seed)
     ctx = pmmod.PM(0)
     ctx.load_graph(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
                    torch.from_numpy(np.ascontiguousarray(g.labels)).to(dev))
-    res = explore.explore(ctx, labels, K4, max_deletions=max_del, log=log)
+    res = explore.explore(ctx, labels, K4, max_deletions=max_del, use_candidate_set=cand,
+                          log=log)
     base = I.Template(list(labels), list(K4))
     rel = I.relaxations(base, max_deletions=len(K4))
     by_level = {}

@@ -127,12 +127,16 @@ int main(void) {
     F(pm_options, learned_stop); F(pm_options, trace_cap); F(pm_options, trace);
     F(pm_options, mode); F(pm_options, ablate); F(pm_options, init_state);
     F(pm_options, skip_mask); F(pm_options, known_roles); F(pm_options, known_edges);
+    F(pm_options, shared_inputs); F(pm_options, union_roles); F(pm_options, union_edges);
+    F(pm_options, per_template); F(pm_options, limit_checks); F(pm_options, max_checks);
     F(pm_options, reserved);
     F(pm_trace_entry, roles_before); F(pm_trace_entry, ms); F(pm_trace_entry, score);
     F(pm_trace_entry, predicted); F(pm_trace_entry, features);
     F(pm_stats, lcc_sweeps); F(pm_stats, trace_entries); F(pm_stats, split_tasks);
     F(pm_stats, done_mask); F(pm_stats, workspace_bytes);
     printf("pm_match_count %zu\n", sizeof(pm_match_count));
+    printf("pm_graph_info_t %zu\n", sizeof(pm_graph_info_t));
+    F(pm_graph_info_t, index_labels); F(pm_graph_info_t, index_bytes); F(pm_graph_info_t, ms_count_index);
     F(pm_match_count, maps); F(pm_match_count, automorphisms); F(pm_match_count, subgraphs);
     F(pm_match_count, written); F(pm_match_count, roots); F(pm_match_count, ms_total);
     return 0;
@@ -152,6 +156,7 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
     assert c["pm_stats"] == ctypes.sizeof(pm.pm_stats)
     assert c["pm_template"] == ctypes.sizeof(pm.pm_template)
     assert c["pm_match_count"] == ctypes.sizeof(pm.pm_match_count)
+    assert c["pm_graph_info_t"] == ctypes.sizeof(pm.pm_graph_info_t)
     for key, v in c.items():
         if "." in key:
             struct, field = key.split(".")

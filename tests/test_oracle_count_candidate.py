@@ -128,3 +128,17 @@ def test_candidate_set_by_hand():
     rp, col = I.csr_from_edges(6, np.array([(0, 1), (2, 3), (4, 5)]))
     cand, _ = oracle.candidate_set(rp, col, labels, [0, 1, 2], [(0, 1), (1, 2)])
     assert cand.tolist() == [1, 2, 0, 0, 4, 2]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_sampled_sweep_equals_one_jacobi_sweep(seed):
+    """The timing sampler applies the same local rule: on every vertex it
+    gives exactly one synchronous sweep of the oracle's LCC."""
+    g, t = _random(seed)
+    gg, tt = oracle._G(g.row_ptr, g.col, g.labels), oracle._T(t.labels, t.edges)
+    om = oracle.init_roles(gg, tt)
+    one = om.copy()
+    oracle.lcc(gg, tt, one, max_sweeps=1)
+    got, entries = oracle.lcc_sample(gg, tt, om, np.arange(g.n))
+    assert np.array_equal(got, one)
+    assert entries == g.m
