@@ -288,7 +288,9 @@ def theta8_s26(args, scale=26, seed=26, template_seed=0):
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
+        log("cpu baseline: oracle sweep on a vertex sample")
         out["cpu_baseline"] = cpu_sweep_baseline(g, ts, T)
+        log(f"cpu baseline: {out['cpu_baseline']['value']} GTEPS")
     ctx.close()
     del rb, eb
     torch.cuda.empty_cache()
@@ -380,7 +382,9 @@ def single_leg(ctx, g, args, primary):
                               "share_of_prune": round(phases["ms_exact"] /
                                                       max(phases["ms_total"], 1e-9), 4),
                               "bound": "search latency / random gathers (no byte roofline)"}}
+    log(f"single template: {ms_step:.2f} ms/step")
     if not args.no_cpu_baseline:
+        log("cpu baseline: oracle prune of the single template (bounded sample)")
         res["cpu_baseline"] = cpu_oracle_prune_baseline(g, t)
     if primary:
         res.update({"metric": "GTEPS (directed CSR entries / time-to-fixpoint, bit-exact "
@@ -508,6 +512,8 @@ def learned_leg(ctx, g, args, seed=4, count=64):
             outs[m] = (r.clone(), e.clone())
             for k in keys:
                 tot[m][k] += st[k]
+        if i % 16 == 15:
+            log(f"learned leg: {i + 1}/{count} templates")
         ra, ea = outs["fixed"]
         for m in modes:
             same = same and bool(torch.equal(ra, outs[m][0]) and torch.equal(ea, outs[m][1]))
@@ -552,10 +558,11 @@ def incremental_leg(ctx, g, args):
 
 
 # --------------------------------------------------------- counting (f3)
-def count_leg(ctx, g, args):
+def count_leg(ctx, g, args, max_maps=1 << 34):
     """Match counting on the pruned graph: every match of the config-2
-    template and of three batch templates, counted within their complete
-    sets (the pruning time beside the counting time)."""
+    template and of the scale-22 batch's first templates, counted within
+    their complete sets (each count stops past 2^34 maps; "complete" says
+    whether it did), with the pruning time beside the counting time."""
     from paper_1912_08453_amd import inputs as I
     t = I.template_tri_square(g, 0)
     ts = [t] + I.templates_batch(g, 3, count=64)[:3]
@@ -564,11 +571,13 @@ def count_leg(ctx, g, args):
     for i, tt in enumerate(ts):
         prune_ms, (r, _, _) = wall(lambda: ctx.prune(first + i))
         r = r.clone()
-        cnt_ms, res = wall(lambda: ctx.count_matches(first + i, state=r))
+        cnt_ms, res = wall(lambda: ctx.count_matches(first + i, state=r, max_maps=max_maps))
         rec = {"labels": list(tt.labels), "edges": len(tt.edges), "maps": res["maps"],
-               "automorphisms": res["automorphisms"], "matches": res["subgraphs"],
+               "complete": bool(res["complete"]), "automorphisms": res["automorphisms"],
+               "matches": res["subgraphs"] if res["complete"] else None,
                "roots": res["roots"], "prune_ms": round(prune_ms, 2),
                "count_ms": round(cnt_ms, 2)}
+        log(f"count: {rec}")
         out.append(rec)
     return {"workload": "scale-22 graph: triangle+4-cycle+pendant and three batch templates",
             "templates": out}
@@ -584,7 +593,9 @@ def explore_leg(ctx, g, args, max_deletions=4):
     n0 = len(t.labels)
     clique = [(a, b) for a in range(n0) for b in range(a + 1, n0)]
     res = {}
-    for cand in (True, False):
+    # one untimed run of each mode first (scratch growth), then the timed ones
+    for cand in (False, True, False, True):
+        log(f"explore: candidate set {cand}")
         ms, r = wall(lambda: explore.explore(ctx, t.labels, clique, max_deletions=max_deletions,
                                              use_candidate_set=cand))
         res["with_candidate_set" if cand else "from_label_roles"] = {
@@ -607,31 +618,40 @@ def topology_leg(ctx22, g22, args, scale=20, seed=20):
     from paper_1912_08453_amd import inputs as I
     from paper_1912_08453_amd import pm
     rows = []
+    shapes = (("tri+square+pendant", I.TRI_SQUARE_EDGES),
+              ("square+pendant", [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4)]))
     for name, abc in (("graph500", GRAPH500), ("chakrabarti", CHAKRABARTI),
                       ("uniform", UNIFORM)):
         g = build_graph(scale, seed, abc)
         ctx = load(g)
-        try:
-            t = I.template_tri_square(g, 0)
-        except RuntimeError:
+        log(f"topology: {name}")
+        for sname, edges in shapes:
+            n0 = max(max(e) for e in edges) + 1
+            try:
+                # labels of an occurrence, repeats allowed: a log2-degree
+                # labelling of the uniform graph has too few labels for
+                # pairwise distinct ones
+                t = I.extract_template(g, n0, edges, 11, distinct=False, name=sname)
+            except RuntimeError:
+                rows.append({"graph": name, "shape": sname, "template": "no occurrence found"})
+                continue
+            tid = ctx.load_templates([t])
+            ctx.prune(tid)
+            ms, (r, e, st) = wall(lambda: ctx.prune(tid))
+            r = r.clone()
+            bits = int(np.unpackbits(e[0].cpu().numpy().view(np.uint8)).sum())
+            cms, cnt = wall(lambda: ctx.count_matches(tid, state=r, max_maps=1 << 34))
             rows.append({"graph": name, "abc": abc, "n": g.n, "m": g.m,
-                         "template": "no occurrence of the shape found"})
-            ctx.close()
-            continue
-        tid = ctx.load_templates([t])
-        ctx.prune(tid)
-        ms, (r, e, st) = wall(lambda: ctx.prune(tid))
-        r = r.clone()
-        bits = int(np.unpackbits(e[0].cpu().numpy().view(np.uint8)).sum())
-        cms, cnt = wall(lambda: ctx.count_matches(tid, state=r))
-        rows.append({"graph": name, "abc": abc, "n": g.n, "m": g.m,
-                     "d_max": int(np.diff(g.row_ptr).max()), "labels": int(g.labels.max()) + 1,
-                     "template_labels": list(t.labels),
-                     "result_vertices": int((r[0] != 0).sum().item()),
-                     "result_entries": bits, "maps": cnt["maps"], "matches": cnt["subgraphs"],
-                     "prune_ms": round(ms, 2), "count_ms": round(cms, 2),
-                     "phases_ms": {k: round(v, 3) for k, v in st.items()
-                                   if k.startswith("ms_")}})
+                         "d_max": int(np.diff(g.row_ptr).max()),
+                         "labels": int(g.labels.max()) + 1, "shape": sname,
+                         "template_labels": list(t.labels),
+                         "result_vertices": int((r[0] != 0).sum().item()),
+                         "result_entries": bits, "maps": cnt["maps"],
+                         "count_complete": bool(cnt["complete"]),
+                         "matches": cnt["subgraphs"] if cnt["complete"] else None,
+                         "prune_ms": round(ms, 2), "count_ms": round(cms, 2),
+                         "phases_ms": {k: round(v, 3) for k, v in st.items()
+                                       if k.startswith("ms_")}})
         ctx.close()
         del g
     t = I.template_tri_square(g22, 0)

@@ -482,10 +482,10 @@ int pm_prune_noalloc(pm_ctx *ctx, int32_t id, uint64_t *role_mask, uint64_t *edg
    Match enumeration and counting run on the reduced graph that pruning
    leaves (termination and output section): a full-template walk with
    aggregation off, every match verified.  Here: depth-first searches from
-   every background edge that can hold one chosen template edge (both
-   orientations counted separately), restricted to the role sets of
-   `state`, counting every injective label-preserving map (Definition 1)
-   once. */
+   every background CSR entry u -> w whose ends hold the roles of one chosen
+   template edge (a, b), with a pinned at u and b at w, restricted to the
+   role sets of `state`: every injective label-preserving map (Definition 1)
+   puts (a, b) on exactly one entry, so each map is counted once. */
 typedef struct {
     uint64_t maps;             /* matches as maps phi (Definition 1)            */
     uint64_t automorphisms;    /* label-preserving automorphisms of G0 (0 if
@@ -495,6 +495,9 @@ typedef struct {
     int64_t written;           /* maps written to the output array            */
     int64_t roots;             /* edge-rooted searches run                    */
     double ms_total;           /* device time of the whole call               */
+    int32_t complete;          /* 1: maps is the exact count; 0: the searches
+                                  stopped at max_maps (maps is a lower bound) */
+    int32_t pad_;
 } pm_match_count;
 
 /* Count (and optionally list) the matches of template `id` within state
@@ -503,9 +506,13 @@ typedef struct {
    the label roles, which counts over the whole graph).  Role bits whose
    label differs from the vertex's are ignored.  maps_out: device
    int32[cap][n0] or NULL; receives min(cap, maps) maps (images of template
-   vertices 0 .. n0-1), in no particular order.  Result in *out (host). */
+   vertices 0 .. n0-1), in no particular order.  max_maps > 0 stops the
+   searches soon after that many maps are counted (out->complete = 0; the
+   count of a template with very many matches grows with the matches, so a
+   caller that only needs "at least" can bound the time).  Result in *out
+   (host). */
 int pm_count_matches(pm_ctx *ctx, int32_t id, const uint64_t *state, int32_t *maps_out,
-                     int64_t cap, pm_match_count *out);
+                     int64_t cap, uint64_t max_maps, pm_match_count *out);
 
 #ifdef __cplusplus
 }

@@ -238,6 +238,7 @@ enum : int {
     C_ENTRIES_U64 = 18,   // byte offset 72: unsigned long long
     C_COUNT_U64 = 64,     // byte offset 256: maps counted (unsigned long long)
     C_WRITTEN_U64 = 66,   // byte offset 264: maps written
+    C_STOP = 68,          // byte offset 272: counting stopped at its limit
     C_TOTAL_BYTES = 512,      // bytes 128..255: query statistics [16]
 };
 
@@ -996,9 +997,11 @@ struct Pruner {
     // the pruned graph) ----------------------------------------------------
     // Maps of the full template within omega0 AND state, counted from every
     // compacted entry that can hold the chosen template edge.
-    pm_match_count count_matches(const uint64_t *state, int32_t *maps_out, int64_t cap) {
+    pm_match_count count_matches(const uint64_t *state, int32_t *maps_out, int64_t cap,
+                                 uint64_t limit) {
         Timer total(s);
         pm_match_count r{};
+        r.complete = 1;
         init_state = state;
         zero_counters();
         init_state_and_first_sweep(false);
@@ -1061,7 +1064,8 @@ struct Pruner {
                 }
                 launch_count_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(), ne, om,
                                        w->edge_plan_ids.as<int32_t>(), a, maps_out,
-                                       maps_out ? cap : 0, wrt, tot, c->grid_search);
+                                       maps_out ? cap : 0, wrt, tot, limit, ctr + C_STOP,
+                                       c->grid_search);
                 if (c->split_budget > 0) {
                     int cur = 0;
                     int64_t rounds = 0;
@@ -1077,12 +1081,14 @@ struct Pruner {
                         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
                         launch_count_split<M>(s, in, nt, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                               om, w->edge_plan_ids.as<int32_t>(), a, maps_out,
-                                              maps_out ? cap : 0, wrt, tot, c->grid_search);
+                                              maps_out ? cap : 0, wrt, tot, limit, ctr + C_STOP,
+                                              c->grid_search);
                     }
                 }
             }
             unsigned long long both[2] = {0, 0};
             d2h(s, both, tot, 2);
+            r.complete = read_ctr(C_STOP) ? 0 : 1;
             r.maps = both[0];
             r.written = maps_out ? (int64_t)std::min<unsigned long long>(both[1], (unsigned long long)std::max<int64_t>(cap, 0)) : 0;
         }
@@ -1874,7 +1880,7 @@ int pm_prune_noalloc(pm_ctx *c, int32_t id, uint64_t *role_mask, uint64_t *edge_
 }
 
 int pm_count_matches(pm_ctx *c, int32_t id, const uint64_t *state, int32_t *maps_out,
-                     int64_t cap, pm_match_count *out) {
+                     int64_t cap, uint64_t max_maps, pm_match_count *out) {
     return guarded([&] {
         if (!c || !out) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
         if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
@@ -1892,10 +1898,10 @@ int pm_count_matches(pm_ctx *c, int32_t id, const uint64_t *state, int32_t *maps
         const CompiledTemplate &T = *c->templates[(size_t)id];
         pm_match_count r{};
         switch (T.mask_bytes) {
-        case 1: { Pruner<uint8_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
-        case 2: { Pruner<uint16_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
-        case 4: { Pruner<uint32_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
-        default: { Pruner<uint64_t> p(c, w, T); r = p.count_matches(state, maps_out, cap); break; }
+        case 1: { Pruner<uint8_t> p(c, w, T); r = p.count_matches(state, maps_out, cap, max_maps); break; }
+        case 2: { Pruner<uint16_t> p(c, w, T); r = p.count_matches(state, maps_out, cap, max_maps); break; }
+        case 4: { Pruner<uint32_t> p(c, w, T); r = p.count_matches(state, maps_out, cap, max_maps); break; }
+        default: { Pruner<uint64_t> p(c, w, T); r = p.count_matches(state, maps_out, cap, max_maps); break; }
         }
         r.automorphisms = count_automorphisms(T);
         r.subgraphs = r.automorphisms ? r.maps / r.automorphisms : 0;

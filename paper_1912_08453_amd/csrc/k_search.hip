@@ -231,11 +231,31 @@ __device__ __forceinline__ int64_t rl_end(const SearchArgs &a, int32_t y, int q)
 enum { kSearchMiss = 0, kSearchFound = 1 };
 
 struct CountSink {
-    unsigned long long n = 0;           // maps counted by this wavefront
+    unsigned long long n = 0;           // maps counted by this wavefront, not yet added
     int32_t *maps = nullptr;            // [cap][n0] or null
     int64_t cap = 0;
     unsigned long long *written = nullptr;
+    unsigned long long *total = nullptr;   // device total of all wavefronts
+    unsigned long long limit = 0;       // > 0: stop every search once total >= limit
+    int32_t *stop = nullptr;            // set when the limit is reached
+    int since = 0;
 };
+
+// Counting with a limit: every kCountPoll steps the wavefront adds its
+// count to the total and polls the stop flag.  Returns true to stop.
+constexpr int kCountPoll = 1024;
+__device__ __forceinline__ bool count_poll(CountSink *cs) {
+    if (!cs->limit || ++cs->since < kCountPoll) return false;
+    cs->since = 0;
+    int st = 0;
+    if (lane_id() == 0) {
+        const unsigned long long before = atomicAdd(cs->total, cs->n);
+        if (before + cs->n >= cs->limit) atomicExch(cs->stop, 1);
+        st = __hip_atomic_load(cs->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    cs->n = 0;
+    return __shfl(st, 0) != 0;
+}
 
 // Write the maps completed at the last level: the placed images, with
 // template vertex q at each passing candidate x.
@@ -403,6 +423,9 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
     }
     int64_t steps = 0;
     for (;;) {
+        if constexpr (kCount) {
+            if (count_poll(cs)) return kSearchMiss;
+        }
         if (split && ++steps > a.split_budget) {
             steps = 0;
             split = hand_off(lvl);
@@ -1169,18 +1192,29 @@ void launch_count_tasks(hipStream_t s, int64_t c_m, const int32_t *c_own, const 
 // One wavefront per task (chunks of a.task_chunk per fetch), the full
 // template pinned at the task's entry; searches past the step budget hand
 // on parts of their tree as split tasks (a.split_out).
+__device__ __forceinline__ bool count_stopped(const CountSink &cs) {
+    int st = 0;
+    if (cs.limit && lane_id() == 0)
+        st = __hip_atomic_load(cs.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __shfl(st, 0) != 0;
+}
+
 template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void count_search_kernel(
     const int32_t *eu, const int32_t *ew, int64_t n_tasks, const M *om, const int32_t *plan_id,
     SearchArgs a, int32_t *maps, int64_t cap, unsigned long long *written,
-    unsigned long long *total) {
+    unsigned long long *total, unsigned long long limit, int32_t *stop) {
     const int lane = lane_id();
     CountSink cs;
     cs.maps = maps;
     cs.cap = cap;
     cs.written = written;
+    cs.total = total;
+    cs.limit = limit;
+    cs.stop = stop;
     const SearchPlan *P = a.plans + plan_id[0];
     for (;;) {
+        if (count_stopped(cs)) break;
         int t0 = 0;
         if (lane == 0) t0 = atomicAdd(a.task_counter, a.task_chunk);
         t0 = __shfl(t0, 0);
@@ -1200,14 +1234,19 @@ template <typename M>
 __global__ __launch_bounds__(kSearchBlock) void count_split_kernel(
     const SplitTask *tasks, int64_t n_tasks, const int32_t *eu, const int32_t *ew, const M *om,
     const int32_t *plan_id, SearchArgs a, int32_t *maps, int64_t cap,
-    unsigned long long *written, unsigned long long *total) {
+    unsigned long long *written, unsigned long long *total, unsigned long long limit,
+    int32_t *stop) {
     const int lane = lane_id();
     CountSink cs;
     cs.maps = maps;
     cs.cap = cap;
     cs.written = written;
+    cs.total = total;
+    cs.limit = limit;
+    cs.stop = stop;
     const SearchPlan *P = a.plans + plan_id[0];
     for (;;) {
+        if (count_stopped(cs)) break;
         int i = 0;
         if (lane == 0) i = atomicAdd(a.task_counter, 1);
         i = __shfl(i, 0);
@@ -1224,22 +1263,25 @@ template <typename M>
 void launch_count_search(hipStream_t s, const int32_t *eu, const int32_t *ew, int64_t n_tasks,
                          const M *omega, const int32_t *plan_id, const SearchArgs &a,
                          int32_t *maps, int64_t cap, unsigned long long *written,
-                         unsigned long long *total, int grid) {
+                         unsigned long long *total, unsigned long long limit, int32_t *stop,
+                         int grid) {
     if (n_tasks <= 0) return;
     hipLaunchKernelGGL(count_search_kernel<M>, dim3(grid), dim3(kSearchBlock), 0, s, eu, ew,
-                       n_tasks, omega, plan_id, a, maps, cap, written, total);
+                       n_tasks, omega, plan_id, a, maps, cap, written, total, limit, stop);
 }
 
 template <typename M>
 void launch_count_split(hipStream_t s, const SplitTask *tasks, int64_t n_tasks, const int32_t *eu,
                         const int32_t *ew, const M *omega, const int32_t *plan_id,
                         const SearchArgs &a, int32_t *maps, int64_t cap,
-                        unsigned long long *written, unsigned long long *total, int grid) {
+                        unsigned long long *written, unsigned long long *total,
+                        unsigned long long limit, int32_t *stop, int grid) {
     if (n_tasks <= 0) return;
     int64_t g = (n_tasks * kWave + kSearchBlock - 1) / kSearchBlock;
     if (g > grid) g = grid;
     hipLaunchKernelGGL(count_split_kernel<M>, dim3((unsigned)g), dim3(kSearchBlock), 0, s, tasks,
-                       n_tasks, eu, ew, omega, plan_id, a, maps, cap, written, total);
+                       n_tasks, eu, ew, omega, plan_id, a, maps, cap, written, total, limit,
+                       stop);
 }
 
 #define PM_INSTANTIATE_SEARCH(M)                                                                  \
@@ -1273,11 +1315,13 @@ void launch_count_split(hipStream_t s, const SplitTask *tasks, int64_t n_tasks, 
     template void launch_count_search<M>(hipStream_t, const int32_t *, const int32_t *, int64_t, \
                                          const M *, const int32_t *, const SearchArgs &,          \
                                          int32_t *, int64_t, unsigned long long *,                \
-                                         unsigned long long *, int);                              \
+                                         unsigned long long *, unsigned long long, int32_t *,     \
+                                         int);                                                    \
     template void launch_count_split<M>(hipStream_t, const SplitTask *, int64_t, const int32_t *, \
                                         const int32_t *, const M *, const int32_t *,              \
                                         const SearchArgs &, int32_t *, int64_t,                   \
-                                        unsigned long long *, unsigned long long *, int);
+                                        unsigned long long *, unsigned long long *,               \
+                                        unsigned long long, int32_t *, int);
 
 PM_INSTANTIATE_SEARCH(uint8_t)
 PM_INSTANTIATE_SEARCH(uint16_t)

@@ -428,16 +428,20 @@ void launch_count_tasks(hipStream_t s, int64_t c_m, const int32_t *c_own, const 
 // Every map of the full template with plan *plan_id's pins at (eu[t],
 // ew[t]) (or within split task ranges) is counted into *total; up to cap
 // of them are written to maps[cap][n0] through *written.
+// limit > 0: searches stop once the total reaches limit (*stop is set;
+// the total is then a lower bound of the maps).
 template <typename M>
 void launch_count_search(hipStream_t s, const int32_t *eu, const int32_t *ew, int64_t n_tasks,
                          const M *omega, const int32_t *plan_id, const SearchArgs &a,
                          int32_t *maps, int64_t cap, unsigned long long *written,
-                         unsigned long long *total, int grid);
+                         unsigned long long *total, unsigned long long limit, int32_t *stop,
+                         int grid);
 template <typename M>
 void launch_count_split(hipStream_t s, const SplitTask *tasks, int64_t n_tasks, const int32_t *eu,
                         const int32_t *ew, const M *omega, const int32_t *plan_id,
                         const SearchArgs &a, int32_t *maps, int64_t cap,
-                        unsigned long long *written, unsigned long long *total, int grid);
+                        unsigned long long *written, unsigned long long *total,
+                        unsigned long long limit, int32_t *stop, int grid);
 
 void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t n, uint64_t v);
 void launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);

@@ -261,7 +261,7 @@ def frequent_labels(labels: np.ndarray, frac: float = 0.01) -> List[int]:
 
 def extract_template(graph: "Graph", n0: int, edges, seed: int, repeat_pairs=(),
                      allowed_labels=None, name: str = "", max_attempts: int = 20000,
-                     fanout: int = 24, budget: int = 4000) -> Template:
+                     fanout: int = 24, budget: int = 4000, distinct: bool = True) -> Template:
     """Labels for a template shape taken from one occurrence of the shape in
     the background graph (query generation by seeded random search, as is
     usual for subgraph-matching workloads).  Vertices in repeat_pairs share a
@@ -272,7 +272,8 @@ def extract_template(graph: "Graph", n0: int, edges, seed: int, repeat_pairs=(),
     `fanout` neighbours of its parent's image, checking injectivity, the
     shape's other edges and the label pattern; it gives up on a start after
     `budget` proposals.  If allowed_labels is given, only vertices with those
-    labels are used."""
+    labels are used.  With distinct=False the labels are whatever the
+    occurrence carries (repeats allowed anywhere)."""
     rng = np.random.Generator(np.random.Philox(seed))
     rp, col, lab = graph.row_ptr, graph.col, graph.labels
     ok_lab = np.ones(int(lab.max()) + 1 if lab.size else 1, dtype=bool)
@@ -328,7 +329,7 @@ def extract_template(graph: "Graph", n0: int, edges, seed: int, repeat_pairs=(),
                     if r in adj[q] and r != parent[q] and not has_edge(x, v):
                         ok = False; break
                     eq = lab[x] == lab[v]
-                    if (r in same.get(q, ())) != eq:
+                    if distinct and (r in same.get(q, ())) != eq:
                         ok = False; break
                 if not ok:
                     continue

@@ -119,7 +119,8 @@ class pm_graph_info_t(ctypes.Structure):
 class pm_match_count(ctypes.Structure):
     _fields_ = [("maps", ctypes.c_uint64), ("automorphisms", ctypes.c_uint64),
                 ("subgraphs", ctypes.c_uint64), ("written", ctypes.c_int64),
-                ("roots", ctypes.c_int64), ("ms_total", ctypes.c_double)]
+                ("roots", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("complete", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -170,7 +171,8 @@ def load_library():
     lib.pm_set_workspace.argtypes = [P, P, ctypes.c_size_t]
     lib.pm_prune_noalloc.argtypes = [P, I32, P, P, ctypes.POINTER(pm_options),
                                      ctypes.POINTER(pm_stats)]
-    lib.pm_count_matches.argtypes = [P, I32, P, P, I64, ctypes.POINTER(pm_match_count)]
+    lib.pm_count_matches.argtypes = [P, I32, P, P, I64, ctypes.c_uint64,
+                                     ctypes.POINTER(pm_match_count)]
     lib.pm_build_count_index.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.pm_graph_info.argtypes = [P, ctypes.POINTER(pm_graph_info_t)]
     for name in SYMBOLS[2:]:
@@ -446,10 +448,11 @@ class PM:
                                                    ctypes.byref(opt), ctypes.byref(st)))
         return st.as_dict()
 
-    def count_matches(self, tid: int, state=None, cap: int = 0):
+    def count_matches(self, tid: int, state=None, cap: int = 0, max_maps: int = 0):
         """Match count of template tid within state ([n] or [1, n] device
         int64 role masks, None: label roles).  With cap > 0 also returns up
-        to cap maps as an int32 tensor [k, n0]."""
+        to cap maps as an int32 tensor [k, n0]; max_maps > 0 stops counting
+        soon after that many (then "complete" is 0)."""
         torch = self.torch
         n0 = len(self.templates[tid].labels)
         sp = None
@@ -463,7 +466,9 @@ class PM:
             maps = torch.empty((cap, n0), dtype=torch.int32, device=self.device)
             mp = ctypes.c_void_p(maps.data_ptr())
         out = pm_match_count()
-        _check(self.lib, self.lib.pm_count_matches(self.h, tid, sp, mp, int(cap), ctypes.byref(out)))
+        _check(self.lib, self.lib.pm_count_matches(self.h, tid, sp, mp, int(cap),
+                                                   ctypes.c_uint64(int(max_maps)),
+                                                   ctypes.byref(out)))
         res = out.as_dict()
         if maps is not None:
             res["maps_out"] = maps[:out.written]

@@ -227,7 +227,16 @@ def test_match_count_with_split_searches(pmmod, torch_dev):
     r, _, _ = ctx.prune(tid)
     for budget in (1, 5, 0):
         ctx.set_param("split_budget", budget)
-        assert ctx.count_matches(tid, state=r)["maps"] == cnt
+        res = ctx.count_matches(tid, state=r)
+        assert res["maps"] == cnt and res["complete"] == 1
+    # a limit stops the searches early with a lower bound; far above the
+    # count it changes nothing
+    ctx.set_param("split_budget", 8192)
+    assert cnt > 100000
+    low = ctx.count_matches(tid, state=r, max_maps=1000)
+    assert low["complete"] == 0 and 1000 <= low["maps"] <= cnt
+    high = ctx.count_matches(tid, state=r, max_maps=10 * cnt + 1)
+    assert high["complete"] == 1 and high["maps"] == cnt
     ctx.close()
 
 

@@ -139,6 +139,7 @@ int main(void) {
     F(pm_graph_info_t, index_labels); F(pm_graph_info_t, index_bytes); F(pm_graph_info_t, ms_count_index);
     F(pm_match_count, maps); F(pm_match_count, automorphisms); F(pm_match_count, subgraphs);
     F(pm_match_count, written); F(pm_match_count, roots); F(pm_match_count, ms_total);
+    F(pm_match_count, complete);
     return 0;
 }
 ''')
