@@ -53,7 +53,7 @@ def main():
                     help="theta8-s26 (default): the scale-26 batch of a base template and its "
                          "relaxations; tri-square-s22: one template at scale 22")
     ap.add_argument("--legs",
-                    default="single,batched,learned,incremental,count,explore,topology",
+                    default="single,batched,learned,autotune,incremental,count,explore,topology",
                     help="comma-separated legs on a resident scale-22 graph; '' for none")
     ap.add_argument("--batch-streams", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -96,6 +96,7 @@ def main():
         if "single" in legs:
             leg_out["single_template_s22"] = single_leg(ctx22, g22, args, primary=False)
     for name, fn in (("batched", batched_leg), ("learned", learned_leg),
+                     ("autotune", autotune_leg),
                      ("incremental", incremental_leg), ("count", count_leg),
                      ("explore", explore_leg), ("topology", topology_leg)):
         if name in legs:
@@ -537,6 +538,33 @@ def learned_leg(ctx, g, args, seed=4, count=64):
     f = tot["fixed"]["ms_total"]
     res["speedup_vs_fixed"] = {m: round(f / tot[m]["ms_total"], 4) for m in modes}
     return res
+
+
+# ------------------------------------------------------------- autotuner
+def autotune_leg(ctx, g, args):
+    """Coordinate search of the settings (search switches and grid, LCC bin
+    bounds) on the config-2 template, best of 3 prunes per candidate; the
+    tuned time against the defaults' on the same timer, same output.  The
+    defaults are restored afterwards."""
+    import torch
+    from paper_1912_08453_amd import autotune
+    from paper_1912_08453_amd import inputs as I
+    t = I.template_tri_square(g, 0)
+    tid = ctx.load_templates([t])
+    start = ctx.params()
+    r0, e0, _ = ctx.prune(tid)
+    r0, e0 = r0.clone(), e0.clone()
+    best, table = autotune.autotune(ctx, [tid], reps=3)
+    timer = autotune.prune_timer(ctx, [tid], reps=5)
+    tuned_ms = timer()
+    r1, e1, _ = ctx.prune(tid)
+    same = bool(torch.equal(r0, r1) and torch.equal(e0, e1))
+    for k, v in start.items():
+        ctx.set_param(k, v)
+    default_ms = timer()
+    return {"defaults": start, "tuned": {k: v for k, v in best.items() if v != start[k]},
+            "candidates_timed": len(table) - 1, "default_ms": round(default_ms, 2),
+            "tuned_ms": round(tuned_ms, 2), "outputs_identical": same}
 
 
 # ----------------------------------------------------- incremental (f2)

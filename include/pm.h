@@ -375,6 +375,11 @@ int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
      "split_capacity" c    split tasks one launch may hand on; a search
                            that finds no room carries on unsplit (2^18)
      "read_first"    1/0   read certificate words before setting them (0)
+     "lcc_bin_small" d     LCC sweeps and compaction: vertices of degree <= d
+                           take 4 lanes (8; 0 <= d <= lcc_bin_mid)
+     "lcc_bin_mid"   d     ... degree <= d take 16 lanes, larger ones up to
+                           4096 a wavefront, hubs 4096-entry segments
+                           (64; lcc_bin_small <= d <= 4096)
    The environment variables listed at the top seed these defaults when the
    context is created.  PM_ERR_INVALID_ARG for an unknown name or a value
    out of range. */

@@ -1,8 +1,9 @@
 """Empirical tuning of the library's work-saving settings.
 
-The settings (pm_set_param) change only how the final search spends its
-time, never which roles and edges survive, so they can be chosen by timing
-alone.  `autotune` runs a coordinate search: for each setting in turn it
+The settings (pm_set_param: the final search's work-saving switches and
+grid, the LCC sweeps' degree-bin bounds) change only how the prune spends
+its time, never which roles and edges survive, so they can be chosen by
+timing alone.  `autotune` runs a coordinate search: for each setting in turn it
 times the prune of the given templates with every candidate value, the
 others held at their best so far, and keeps the fastest; one or more
 passes over all settings.  The winning values are left set on the context.
@@ -31,6 +32,8 @@ def default_space(ctx) -> Dict[str, List[int]]:
         "split_budget": [0, 2048, 8192, 32768],
         "edge_tail": [0, 16384, 65536],
         "read_first": [0, 1],
+        "lcc_bin_small": [4, 8, 16],
+        "lcc_bin_mid": [32, 64, 128, 256],
     }
 
 

@@ -204,6 +204,8 @@ struct pm_ctx {
     int exp_log2 = kExpSeenLog2;
     int64_t split_cap = kSplitCap;
     int read_first = 0;
+    int64_t bin_small = kBinSmallMaxDeg;   // LCC degree-bin bounds (settings)
+    int64_t bin_mid = kBinMidMaxDeg;
     int64_t wall_khz = 0;
     // caller-owned workspace (pm_set_workspace); null: library-owned scratch
     char *ws = nullptr;
@@ -333,6 +335,8 @@ struct Pruner {
         wl.capacity = n;
         wl.hub_capacity = hubs;
         wl.seg_capacity = segs;
+        wl.bin_small = c->bin_small;
+        wl.bin_mid = c->bin_mid;
     }
 
     void zero_counters() { PM_HIP(hipMemsetAsync(ctr, 0, C_TOTAL_BYTES, s)); }
@@ -1926,6 +1930,9 @@ int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
         else if (k == "expand_table_log2" && value >= 10 && value <= 30) c->exp_log2 = (int)value;
         else if (k == "split_capacity" && value >= 1 && value <= ((int64_t)1 << 28)) c->split_cap = value;
         else if (k == "read_first") c->read_first = value ? 1 : 0;
+        else if (k == "lcc_bin_small" && value >= 0 && value <= c->bin_mid) c->bin_small = value;
+        else if (k == "lcc_bin_mid" && value >= c->bin_small && value <= kBinWaveMaxDeg)
+            c->bin_mid = value;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter or value out of range: " + k);
     });
 }
@@ -1946,6 +1953,8 @@ int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
         else if (k == "expand_table_log2") *value = c->exp_log2;
         else if (k == "split_capacity") *value = c->split_cap;
         else if (k == "read_first") *value = c->read_first;
+        else if (k == "lcc_bin_small") *value = c->bin_small;
+        else if (k == "lcc_bin_mid") *value = c->bin_mid;
         else throw Error(PM_ERR_INVALID_ARG, "unknown parameter: " + k);
     });
 }

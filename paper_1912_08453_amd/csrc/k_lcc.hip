@@ -146,8 +146,12 @@ __device__ __forceinline__ void mark_changed(int32_t *changed) {
     if (__atomic_load_n(changed, __ATOMIC_RELAXED) == 0) atomicExch(changed, 1);
 }
 
-__device__ __forceinline__ int degree_bin(int64_t d) {
-    return d <= kBinSmallMaxDeg ? 0 : d <= kBinMidMaxDeg ? 1 : d <= kBinWaveMaxDeg ? 2 : 3;
+// Bins: 4 lanes per vertex up to wl.bin_small entries, 16 up to
+// wl.bin_mid, a wavefront up to kBinWaveMaxDeg, hub segments above (every
+// group kernel loops over its row, so the first two bounds are free
+// settings; the last is fixed by the hub segmentation).
+__device__ __forceinline__ int degree_bin(int64_t d, const Worklists &wl) {
+    return d <= wl.bin_small ? 0 : d <= wl.bin_mid ? 1 : d <= kBinWaveMaxDeg ? 2 : 3;
 }
 
 // Appends are staged in LDS: a block gathers the selected vertices of a
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(const int32_t *in, int64_t 
             const int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
             const bool act = valid && omega[v] != 0;
             const int64_t d = act ? rp[v + 1] - rp[v] : 0;
-            const int b = act ? degree_bin(d) : -1;
+            const int b = act ? degree_bin(d, wl) : -1;
             tot += (unsigned long long)d;
 #pragma unroll
             for (int k = 0; k < kNumBins; ++k) stage_append(b == k, v, buf[k], &cnt[k]);

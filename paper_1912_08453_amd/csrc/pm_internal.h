@@ -157,6 +157,8 @@ struct Worklists {
     int64_t capacity;               // per list
     int64_t hub_capacity;           // hub slots
     int64_t seg_capacity;
+    int64_t bin_small;              // largest degree of the 4-lane bin
+    int64_t bin_mid;                // largest degree of the 16-lane bin
 };
 
 // omega0(v) from the label LUT; bits (ceil(n/64) words, may be null)

@@ -477,7 +477,7 @@ class PM:
     # ------------------------------------------------------------ tuning
     TUNING = ("expand", "expand_max", "witness", "relist", "edge_chunk", "edge_stripes",
               "search_grid", "split_budget", "edge_tail", "expand_table_log2",
-              "split_capacity", "read_first")
+              "split_capacity", "read_first", "lcc_bin_small", "lcc_bin_mid")
 
     def set_param(self, name: str, value: int) -> None:
         _check(self.lib, self.lib.pm_set_param(self.h, name.encode(), int(value)))

@@ -70,8 +70,10 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
                  ("witness", 1), ("relist", 0), ("expand", 0)):
         ctx.set_param(k, v)
         assert ctx.get_param(k) == v
+    assert p["lcc_bin_small"] == 8 and p["lcc_bin_mid"] == 64
     for k, v in (("edge_chunk", 0), ("edge_stripes", 1 << 17), ("search_grid", 0),
                  ("split_budget", -1), ("split_capacity", 0), ("expand_table_log2", 31),
+                 ("lcc_bin_mid", 4097), ("lcc_bin_small", 65), ("lcc_bin_small", -1),
                  ("nope", 1)):
         with pytest.raises(pmmod.PMError):
             ctx.set_param(k, v)
@@ -86,7 +88,9 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
     {"witness": 1, "expand_max": 8, "edge_chunk": 64, "edge_stripes": 1024},
     {"split_budget": 1}, {"split_budget": 2, "search_grid": 3}, {"split_budget": 0},
     {"split_budget": 1, "split_capacity": 20}, {"expand_table_log2": 10},
-    {"read_first": 1, "witness": 1}])
+    {"read_first": 1, "witness": 1},
+    {"lcc_bin_small": 0, "lcc_bin_mid": 0}, {"lcc_bin_mid": 4096, "lcc_bin_small": 4096},
+    {"lcc_bin_small": 1, "lcc_bin_mid": 2}])
 def test_extreme_settings_keep_the_complete_set(pmmod, torch_dev, case, setting):
     g, ts, refs = case
     ctx, tid = _ctx(pmmod, torch_dev, g, ts)
