@@ -200,6 +200,11 @@ def theta8_s26(args, scale=26, seed=26, template_seed=0):
     ms_load, ctx = wall(lambda: load(g))
     first = ctx.load_templates(ts)
     ctx.load_model(OT.load_model())
+    # settings the project's autotuner chose for this workload (search
+    # switches and grid, LCC bin bounds; results do not depend on them),
+    # used by the batched and the plain path alike
+    from paper_1912_08453_amd import autotune
+    tuned = autotune.apply_tuned(ctx, "theta8-s26")
     thr = OT.load_threshold()
     dev = torch.device("cuda", 0)
     n, words = g.n, (g.m + 63) // 64
@@ -275,7 +280,7 @@ def theta8_s26(args, scale=26, seed=26, template_seed=0):
                                f"1-2 edge-deletion relaxations ({T} templates), one batch",
                    "n": n, "m_directed": g.m, "templates": T, "base_labels": base.labels,
                    "batch_streams": args.batch_streams, "order": "learned (every constraint "
-                   "checked)", "parallelism": "single GPU"},
+                   "checked)", "settings": tuned, "parallelism": "single GPU"},
         "time_to_fixpoint_ms": round(ms_step, 3),
         "plain_one_template_per_call_ms": round(float(np.mean(plain_ms)), 2),
         "speedup_vs_plain": round(float(np.mean(plain_ms)) / ms_step, 4),

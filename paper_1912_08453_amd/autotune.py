@@ -13,6 +13,8 @@ passes over all settings.  The winning values are left set on the context.
 """
 from __future__ import annotations
 
+import json
+import os
 import time
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
@@ -109,3 +111,26 @@ def autotune(ctx, tids: Sequence[int], space: Optional[Dict[str, Sequence[int]]]
     timer = prune_timer(ctx, tids, batch=batch, reps=reps, **prune_kw)
     timer()   # warm-up: workspaces sized, kernels loaded
     return coordinate_search(ctx.set_param, timer, start, space, passes=passes, log=log)
+
+
+TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_settings.json")
+
+
+def load_tuned(workload: str, path: str = TUNED_PATH) -> Dict[str, int]:
+    """Settings the autotuner chose for a named workload (empty if none)."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return dict(json.load(f).get(workload, {}).get("settings", {}))
+
+
+def apply_tuned(ctx, workload: str) -> Dict[str, int]:
+    """Set the stored settings of `workload` on the context; returns them."""
+    s = load_tuned(workload)
+    # the bin bounds must stay ordered while they are set one at a time:
+    # raise the upper one first when the lower one grows past it
+    first = "lcc_bin_mid" if s.get("lcc_bin_small", 0) > ctx.get_param("lcc_bin_mid") \
+        else "lcc_bin_small"
+    for k in sorted(s, key=lambda k: (k != first, k)):
+        ctx.set_param(k, int(s[k]))
+    return s

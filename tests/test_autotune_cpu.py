@@ -41,3 +41,43 @@ def test_coupled_cost_improves_with_a_second_pass():
     state, set_value, timer = _setup(cost)
     two, _ = autotune.coordinate_search(set_value, timer, {"a": 0, "b": 0}, space, passes=3)
     assert one == {"a": 1, "b": 0} and cost(two) < cost(one)
+
+
+class _BinCtx:
+    """Stand-in for a context that, like the library, refuses a lower bin
+    bound above the upper one and the reverse."""
+
+    def __init__(self, small, mid):
+        self.p = {"lcc_bin_small": small, "lcc_bin_mid": mid}
+
+    def get_param(self, k):
+        return self.p[k]
+
+    def set_param(self, k, v):
+        if k == "lcc_bin_small" and not 0 <= v <= self.p["lcc_bin_mid"]:
+            raise ValueError(k)
+        if k == "lcc_bin_mid" and not self.p["lcc_bin_small"] <= v <= 4096:
+            raise ValueError(k)
+        self.p[k] = v
+
+
+def test_stored_settings_are_applied_in_an_order_the_bounds_accept(tmp_path, monkeypatch):
+    import json
+    path = tmp_path / "tuned.json"
+    path.write_text(json.dumps({"w": {"settings": {"lcc_bin_small": 300, "lcc_bin_mid": 500}},
+                                "v": {"settings": {"lcc_bin_small": 2, "lcc_bin_mid": 6}}}))
+    monkeypatch.setattr(autotune, "TUNED_PATH", str(path))
+    assert autotune.load_tuned("w", str(path)) == {"lcc_bin_small": 300, "lcc_bin_mid": 500}
+    assert autotune.load_tuned("missing", str(path)) == {}
+    ctx = _BinCtx(8, 64)
+    monkeypatch.setattr(autotune, "load_tuned", lambda w: json.loads(path.read_text())[w]["settings"])
+    autotune.apply_tuned(ctx, "w")   # the upper bound has to move first
+    assert ctx.p == {"lcc_bin_small": 300, "lcc_bin_mid": 500}
+    autotune.apply_tuned(ctx, "v")   # the lower bound has to move first
+    assert ctx.p == {"lcc_bin_small": 2, "lcc_bin_mid": 6}
+
+
+def test_shipped_settings_name_known_parameters():
+    from paper_1912_08453_amd import pm
+    s = autotune.load_tuned("theta8-s26")
+    assert s and set(s) <= set(pm.PM.TUNING)
