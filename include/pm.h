@@ -30,7 +30,8 @@
  *    is symmetric.
  *  - Environment variables read by pm_create (work-saving switches of the
  *    final search; none changes any result): PM_EXPAND=0 turns off the
- *    single-vertex swap scans of found matches, PM_EXPAND_MAX=k skips scans
+ *    single-vertex swap scans of found matches, PM_EXPAND_EDGES=0 only
+ *    those after edge-rooted finds, PM_EXPAND_MAX=k skips scans
  *    of lists longer than k (default 4096), PM_WITNESS=1 turns on certifying candidate
  *    edges by swaps of recorded witnesses (off by default: measured slower
  *    once the edge searches use relisted roles), PM_RELIST=0 keeps the edge
@@ -269,6 +270,9 @@ struct pm_stats {
                                       templates when count > 1               */
     int64_t workspace_bytes;       /* peak device scratch of one template's
                                       prune (largest over the templates)      */
+    int64_t join_edges;            /* candidate edges certified by joining the
+                                      recorded matches of their two ends
+                                      across a bridge of the template         */
 };
 
 /* Returns the message for the last error on this thread ("" if none). */
@@ -361,6 +365,8 @@ int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
    changes any result.  Names and values:
      "expand"        1/0   single-vertex swap scans of found matches (1)
      "expand_max"    k     skip swap scans of lists longer than k; -1: none (4096)
+     "expand_edges"  1/0   swap scans also after matches found by edge-rooted
+                           searches (1; "expand" 0 turns off both)
      "witness"       1/0   certify candidate edges by witness swaps (0)
      "relist"        1/0   edge searches on role lists of the exact roles (1)
      "edge_chunk"    k     edge tasks a wavefront takes at once (16)

@@ -27,6 +27,7 @@ def default_space(ctx) -> Dict[str, List[int]]:
         "edge_chunk": [4, 8, 16, 32, 64],
         "edge_stripes": [1, 16, 64, 256],
         "expand": [0, 1],
+        "expand_edges": [0, 1],
         "expand_max": [1024, 4096, 16384, -1],
         "witness": [0, 1],
         "relist": [0, 1],

@@ -194,6 +194,7 @@ struct pm_ctx {
     std::vector<std::unique_ptr<pm::Scratch>> scratch;
     int grid_search = 2048;
     int expand = 1;
+    int expand_edges = 1;   // swap scans after edge-rooted finds too
     int64_t expand_max = 4096;
     int witness = 0;
     int edge_chunk = 16;
@@ -531,6 +532,8 @@ struct Pruner {
         a.split_n = nullptr;
         a.split_cap = 0;
         a.aggregate = (ablate & PM_ABLATE_WORK_AGGREGATION) ? 0 : 1;
+        a.tside = T.d_tjoin;
+        a.tsame = T.d_tjoin + T.m0;
         return a;
     }
 
@@ -681,6 +684,7 @@ struct Pruner {
                 a.split_n = ctr + C_SPLIT;
                 a.split_cap = split_cap;
             }
+            if (!c->expand_edges) a.expand = 0;
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
                                   w->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
@@ -733,6 +737,7 @@ struct Pruner {
         st.expand_candidates += (int64_t)qs[12];
         st.expand_valid += (int64_t)qs[13];
         st.witness_edges += (int64_t)qs[14];
+        st.join_edges += (int64_t)qs[15];
         st.ms_exact += t.stop();
     }
 
@@ -1113,6 +1118,29 @@ void load_template_device(pm_ctx *c, CompiledTemplate &T) {
     PM_HIP(hipMalloc(&T.d_tedges, sizeof(int32_t) * std::max<size_t>(te.size(), 2)));
     if (!te.empty())
         PM_HIP(hipMemcpy(T.d_tedges, te.data(), sizeof(int32_t) * te.size(), hipMemcpyHostToDevice));
+    // bridges of G0: edge i is one iff its ends fall apart without it; the
+    // side of its first end is then kept (for joining two matches across it)
+    std::vector<uint64_t> join((size_t)T.m0 + (size_t)T.n0, 0ull);
+    for (int i = 0; i < T.m0; ++i) {
+        uint64_t seen = 1ull << T.edges[i].first, grow = seen;
+        while (grow) {
+            uint64_t next = 0;
+            for (int j = 0; j < T.m0; ++j) {
+                if (j == i) continue;
+                const uint64_t ea = 1ull << T.edges[j].first, eb = 1ull << T.edges[j].second;
+                if ((grow & ea) && !(seen & eb)) next |= eb;
+                if ((grow & eb) && !(seen & ea)) next |= ea;
+            }
+            seen |= next;
+            grow = next;
+        }
+        if (!((seen >> T.edges[i].second) & 1ull)) join[(size_t)i] = seen;
+    }
+    for (int q = 0; q < T.n0; ++q) join[(size_t)T.m0 + q] = T.label_mask_of[q] & ~(1ull << q);
+    PM_HIP(hipMalloc(&T.d_tjoin, sizeof(uint64_t) * std::max<size_t>(join.size(), 1)));
+    if (!join.empty())
+        PM_HIP(hipMemcpy(T.d_tjoin, join.data(), sizeof(uint64_t) * join.size(),
+                         hipMemcpyHostToDevice));
     int maxl = 0;
     for (int q = 0; q < T.n0; ++q) maxl = std::max(maxl, T.labels[q]);
     std::vector<uint64_t> lut((size_t)maxl + 1, 0);
@@ -1137,6 +1165,7 @@ void load_template_device(pm_ctx *c, CompiledTemplate &T) {
 void free_template_device(CompiledTemplate &T) {
     if (T.d_plans) (void)hipFree(T.d_plans);
     if (T.d_tedges) (void)hipFree(T.d_tedges);
+    if (T.d_tjoin) (void)hipFree(T.d_tjoin);
     if (T.d_init_lut) (void)hipFree(T.d_init_lut);
     if (T.d_cdesc) (void)hipFree(T.d_cdesc);
     if (T.d_need) (void)hipFree(T.d_need);
@@ -1144,6 +1173,7 @@ void free_template_device(CompiledTemplate &T) {
     T.d_need = nullptr;
     T.d_plans = nullptr;
     T.d_tedges = nullptr;
+    T.d_tjoin = nullptr;
     T.d_init_lut = nullptr;
 }
 
@@ -1498,6 +1528,7 @@ void prune_impl(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask,
         total.expand_valid += st.expand_valid;
         total.first_sweep_bytes += st.first_sweep_bytes;
         total.witness_edges += st.witness_edges;
+        total.join_edges += st.join_edges;
         total.split_tasks += st.split_tasks;
         total.trace_entries += st.trace_entries;
         total.done_mask |= st.done_mask;
@@ -1539,6 +1570,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
                 c->wall_khz = khz;
             const char *ex = getenv("PM_EXPAND");
             if (ex) c->expand = atoi(ex);
+            const char *ee = getenv("PM_EXPAND_EDGES");
+            if (ee) c->expand_edges = atoi(ee) ? 1 : 0;
             const char *em = getenv("PM_EXPAND_MAX");
             if (em) c->expand_max = atoll(em);
             const char *wn = getenv("PM_WITNESS");
@@ -1920,6 +1953,7 @@ int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
         const std::string k(name);
         if (k == "expand") c->expand = value ? 1 : 0;
         else if (k == "expand_max") c->expand_max = value < 0 ? INT64_MAX : value;
+        else if (k == "expand_edges") c->expand_edges = value ? 1 : 0;
         else if (k == "witness") c->witness = value ? 1 : 0;
         else if (k == "relist") c->relist = value ? 1 : 0;
         else if (k == "edge_chunk" && value >= 1 && value <= (1 << 16)) c->edge_chunk = (int)value;
@@ -1943,6 +1977,7 @@ int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
         const std::string k(name);
         if (k == "expand") *value = c->expand;
         else if (k == "expand_max") *value = c->expand_max == INT64_MAX ? -1 : c->expand_max;
+        else if (k == "expand_edges") *value = c->expand_edges;
         else if (k == "witness") *value = c->witness;
         else if (k == "relist") *value = c->relist;
         else if (k == "edge_chunk") *value = c->edge_chunk;

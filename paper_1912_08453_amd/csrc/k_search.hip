@@ -852,11 +852,51 @@ __device__ bool witness_swap(const SearchArgs &a, const LccTable &tab, uint64_t 
     return false;
 }
 
+// Some match uses edge {u, w} through a bridge of G0: the recorded witness
+// of (u, qa) on qa's side of bridge (qa, qb), that of (w, qb) on the other
+// side, and the edge between them form a match unless a vertex of one side
+// and one of the same label on the other side share an image (every edge
+// of G0 lies within one side or is the bridge itself, so it is kept).
+__device__ bool join_at(const SearchArgs &a, int32_t u, int qa, int32_t w, int qb,
+                        uint64_t side_u) {
+    const int64_t iu = (int64_t)a.rl_pos[u] * a.n0 + qa;
+    const int64_t iw = (int64_t)a.rl_pos[w] * a.n0 + qb;
+    if (!__atomic_load_n(a.wit_flag + iu, __ATOMIC_RELAXED) ||
+        !__atomic_load_n(a.wit_flag + iw, __ATOMIC_RELAXED))
+        return false;
+    const int32_t *Wu = a.wit + iu * a.n0;
+    const int32_t *Ww = a.wit + iw * a.n0;
+    for (uint64_t m = side_u; m; m &= m - 1) {
+        const int p = __builtin_ctzll(m);
+        const uint64_t other = a.tsame[p] & ~side_u;
+        if (!other) continue;
+        const int32_t x = Wu[p];
+        for (uint64_t mo = other; mo; mo &= mo - 1)
+            if (Ww[__builtin_ctzll(mo)] == x) return false;
+    }
+    return true;
+}
+
+__device__ bool witness_join(const SearchArgs &a, uint64_t cu, uint64_t cw, int32_t u,
+                             int32_t w, uint64_t vmask) {
+    for (int i = 0; i < a.m0; ++i) {
+        const uint64_t side = a.tside[i];
+        if (!side) continue;
+        const int ta = a.tedges[2 * i], tb = a.tedges[2 * i + 1];
+        if (((cu >> ta) & 1ull) && ((cw >> tb) & 1ull) && join_at(a, u, ta, w, tb, side))
+            return true;
+        if (((cu >> tb) & 1ull) && ((cw >> ta) & 1ull) && join_at(a, u, tb, w, ta, vmask & ~side))
+            return true;
+    }
+    return false;
+}
+
 // Candidate edges: entries a -> b (a < b) of the compacted subgraph whose
 // certified roles are adjacent in G0 and that no found match certified yet
 // (neither the bit of this entry nor that of its reverse b -> a is set; the
 // reverse entry's index goes with the task, e_idx holding both); those a
-// witness swap certifies are certified here instead.  One thread per
+// witness swap or a witness join across a bridge of G0 certifies are
+// certified here instead.  One thread per
 // compacted entry (c_own gives its row), so hub rows do not serialise on
 // one wavefront.
 template <typename M>
@@ -865,7 +905,8 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
     const int32_t *__restrict__ c_col, const M *cert, LccTable tab, uint64_t *c_cert, int32_t *eu,
     int32_t *ew, int64_t *e_idx, int32_t *n_out, int64_t cap, SearchArgs a) {
     const int lane = lane_id();
-    unsigned long long swapped = 0;
+    unsigned long long swapped = 0, joined = 0;
+    const uint64_t vmask = a.n0 == 64 ? ~0ull : ((1ull << a.n0) - 1ull);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // the loop bound is uniform over the block, so ballots see every lane
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < c_m; base += stride) {
@@ -890,6 +931,11 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
                     ++swapped;
                     p = false;
                 }
+                if (p && a.wit_on && witness_join(a, cu, cw, u, w, vmask)) {
+                    set_bit(c_cert, k);
+                    ++joined;
+                    p = false;
+                }
             }
         }
         const uint64_t m = ballot64(p);
@@ -907,8 +953,12 @@ __global__ __launch_bounds__(kSearchBlock) void edge_candidates_kernel(
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) swapped += __shfl_xor(swapped, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+        swapped += __shfl_xor(swapped, off, 64);
+        joined += __shfl_xor(joined, off, 64);
+    }
     if (lane == 0 && swapped && a.qstats) atomicAdd(a.qstats + 14, swapped);
+    if (lane == 0 && joined && a.qstats) atomicAdd(a.qstats + 15, joined);
 }
 
 template <typename M>

@@ -121,6 +121,10 @@ struct CompiledTemplate {
     // device copies
     SearchPlan *d_plans = nullptr;
     int32_t *d_tedges = nullptr;              // [2*m0] template edges (a, b)
+    // [m0] for a bridge (a, b) of G0 the vertices on a's side once it is
+    // removed (0 for an edge on a cycle), then [n0] the other vertices of
+    // q's label
+    uint64_t *d_tjoin = nullptr;
     uint64_t *d_init_lut = nullptr;           // label -> initial roles
     int64_t init_lut_len = 0;
     ConstraintDesc *d_cdesc = nullptr;        // [constraints]
@@ -291,6 +295,8 @@ struct SearchArgs {
     int64_t split_cap;
     int32_t aggregate;              // 0: a found embedding certifies only the
                                     // query it answers (work aggregation off)
+    const uint64_t *tside;          // [m0] side masks of template bridges (0: none)
+    const uint64_t *tsame;          // [n0] other template vertices of q's label
 };
 
 // Role lists of the vertices in tasks over the compacted subgraph: pass 1

@@ -85,7 +85,8 @@ class pm_stats(ctypes.Structure):
                  "edge_candidates", "vq_pos", "vq_neg", "eq_pos", "eq_neg", "trace_entries", "expand_scans",
                  "expand_candidates", "expand_valid", "first_sweep_bytes", "witness_edges",
                  "split_tasks")] + \
-               [("done_mask", ctypes.c_uint64), ("workspace_bytes", ctypes.c_int64)]
+               [("done_mask", ctypes.c_uint64), ("workspace_bytes", ctypes.c_int64),
+                ("join_edges", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -475,7 +476,7 @@ class PM:
         return res
 
     # ------------------------------------------------------------ tuning
-    TUNING = ("expand", "expand_max", "witness", "relist", "edge_chunk", "edge_stripes",
+    TUNING = ("expand", "expand_edges", "expand_max", "witness", "relist", "edge_chunk", "edge_stripes",
               "search_grid", "split_budget", "edge_tail", "expand_table_log2",
               "split_capacity", "read_first", "lcc_bin_small", "lcc_bin_mid")
 

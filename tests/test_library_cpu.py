@@ -133,7 +133,7 @@ int main(void) {
     F(pm_trace_entry, roles_before); F(pm_trace_entry, ms); F(pm_trace_entry, score);
     F(pm_trace_entry, predicted); F(pm_trace_entry, features);
     F(pm_stats, lcc_sweeps); F(pm_stats, trace_entries); F(pm_stats, split_tasks);
-    F(pm_stats, done_mask); F(pm_stats, workspace_bytes);
+    F(pm_stats, done_mask); F(pm_stats, workspace_bytes); F(pm_stats, join_edges);
     printf("pm_match_count %zu\n", sizeof(pm_match_count));
     printf("pm_graph_info_t %zu\n", sizeof(pm_graph_info_t));
     F(pm_graph_info_t, index_labels); F(pm_graph_info_t, index_bytes); F(pm_graph_info_t, ms_count_index);
