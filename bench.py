@@ -8,13 +8,16 @@ hops apart and all its connected 1- and 2-edge-deletion relaxations (28
 templates in all), pruned to their complete sets through the C ABI:
 
   * the neighbour-label count index (one streaming pass over the CSR; the
-    first LCC sweep of every template reads it), then
+    first LCC sweep of every template reads it),
+  * the label-pair subgraph of the batch (the entries whose label pair is
+    that of a template edge; every template's first compaction reads it
+    instead of the whole CSR), then
   * one batched pm_prune call for all 28 templates on 4 concurrent streams
     with the learned constraint order: first LCC sweep, compaction, LCC
     fixpoint, every non-local constraint, the exact final search.
 
 Inputs are resident in HBM before timing starts.  The plain path -- the
-same index pass, then one pm_prune call per template with the fixed order
+same two index passes, then one pm_prune call per template with the fixed order
 -- is timed beside it, and every template's output must be identical.
 
 Prints one JSON line: metric GTEPS = directed CSR entries x templates /
@@ -211,8 +214,13 @@ def theta8_s26(args, scale=26, seed=26, template_seed=0):
     rb = torch.empty((T, n), dtype=torch.int64, device=dev)
     eb = torch.empty((T, words), dtype=torch.int64, device=dev)
 
+    # per step: the graph's two indexes (neighbour-label counts, label-pair
+    # subgraph of the batch's template edges), then the batch
+    pair_ms = []
+
     def step(order="learned", min_score=None):
         k_ms = ctx.build_count_index()
+        pair_ms.append(ctx.build_pair_index(first, T))
         _, _, st = ctx.prune(first, count=T, role_mask=rb, edge_bits=eb,
                              batch_streams=args.batch_streams, order=order,
                              learned_min_score=min_score)
@@ -227,7 +235,8 @@ def theta8_s26(args, scale=26, seed=26, template_seed=0):
         times.append(ms)
         k_ms_list.append(k_ms)
         stats.append(st)
-        log(f"step {i}: {ms:.1f} ms (count index {k_ms:.2f} ms)")
+        log(f"step {i}: {ms:.1f} ms (count index {k_ms:.2f} ms, pair subgraph "
+            f"{pair_ms[-1]:.2f} ms)")
     ms_step = float(np.mean(times))
     value = g.m * T / (ms_step / 1e3) / 1e9
 
@@ -237,6 +246,7 @@ def theta8_s26(args, scale=26, seed=26, template_seed=0):
 
     def plain():
         ctx.build_count_index()
+        ctx.build_pair_index(first, T)
         per = []
         for i in range(T):
             _, _, st = ctx.prune(first + i, role_mask=r1[i:i + 1], edge_bits=e1[i:i + 1])
@@ -287,6 +297,8 @@ def theta8_s26(args, scale=26, seed=26, template_seed=0):
         "outputs_identical": identical,
         "other_batched_modes": alt,
         "count_index_ms": round(float(np.mean(k_ms_list)), 3),
+        "pair_index_ms": round(float(np.mean(pair_ms)), 3),
+        "pair_index_entries": ctx.graph_info()["pair_entries"],
         "graph_load_ms": round(ms_load, 1),
         "phases_ms_sum_over_templates": phases,
         "per_template_plain": per_variant,

@@ -314,6 +314,24 @@ int pm_load_graph(pm_ctx *ctx, int64_t n, int64_t m, const int64_t *row_ptr,
    64, or m >= 2^32). */
 int pm_build_count_index(pm_ctx *ctx, double *ms);
 
+/* Build the label-pair subgraph of the loaded graph for the templates
+   [first_id, first_id + count): the entries u -> x whose label pair
+   (label(u), label(x)) is that of an edge of one of them, each with its
+   offset in u's row (int64 row_ptr[n+1] plus two int32 arrays per entry,
+   device memory owned by the context, replacing any earlier one; count = 0
+   frees it).  An entry whose labels are not those of a template edge never
+   joins two adjacent roles, so the edge elimination of the LCC description
+   drops it in every prune: every later prune of a template whose edges'
+   label pairs the subgraph holds starts its first compaction from it
+   instead of from the whole graph (same results; with
+   PM_ABLATE_EDGE_ELIMINATION the whole graph is used).  Meant for batches
+   and sessions of templates over the same labels, e.g. a template and its
+   relaxations.  *ms (may be NULL) receives its device time.
+   PM_ERR_INVALID_ARG if the templates' edges use more than 64 labels or an
+   id is out of range; PM_ERR_CAPACITY if the subgraph would have 2^31
+   entries or more (no subgraph is kept then). */
+int pm_build_pair_index(pm_ctx *ctx, int32_t first_id, int32_t count, double *ms);
+
 /* Facts about the loaded graph. */
 typedef struct {
     int64_t n, m;
@@ -323,6 +341,8 @@ typedef struct {
     int64_t hubs;              /* rows longer than 4096 entries               */
     int64_t hub_segments;      /* their 4096-entry segments                   */
     double ms_count_index;     /* device time of the last index build         */
+    int64_t pair_entries;      /* entries of the label-pair subgraph (-1: none) */
+    double ms_pair_index;      /* device time of its build                    */
 } pm_graph_info_t;
 int pm_graph_info(pm_ctx *ctx, pm_graph_info_t *out);
 

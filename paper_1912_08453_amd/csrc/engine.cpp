@@ -187,6 +187,16 @@ struct pm_ctx {
     int64_t idx_hubs = 0, idx_segs = 0;
     int64_t cnt_stride = 0;
     double ms_count_index = 0.0;
+    // label-pair subgraph: the entries u -> x of the loaded graph whose label
+    // pair (label(u), label(x)) is that of a template edge of the templates
+    // it was built for (pair_adj[la * pair_nl + lb], labels < pair_nl);
+    // pair_off holds each entry's offset in its original row.  pair_m < 0:
+    // none.
+    DevBuf pair_rp, pair_col, pair_off;
+    int64_t pair_m = -1;
+    int pair_nl = 0;
+    std::vector<uint8_t> pair_adj;
+    double ms_pair_index = 0.0;
     int64_t hub_cap = 0, seg_cap = 0;
     // templates
     std::vector<std::unique_ptr<CompiledTemplate>> templates;
@@ -436,15 +446,59 @@ struct Pruner {
     int cbuf = 0;
     int64_t nA_compact = 0;   // active vertices when the subgraph was built
     static constexpr int64_t kRecompactEntries = 1 << 20;
+    // The label-pair subgraph holds every entry a compaction of this
+    // template can keep (a kept entry joins roles adjacent in G0, whose
+    // labels are those of a template edge), unless edge elimination is
+    // ablated.
+    bool pairs_cover() const {
+        if (c->pair_m < 0 || lcc.keep_all) return false;
+        for (const auto &e : T.edges) {
+            const int la = T.labels[(size_t)e.first], lb = T.labels[(size_t)e.second];
+            if (la >= c->pair_nl || lb >= c->pair_nl ||
+                !c->pair_adj[(size_t)la * (size_t)c->pair_nl + (size_t)lb])
+                return false;
+        }
+        return true;
+    }
+
+    // Candidate subgraph: from the current one, else from the label-pair
+    // subgraph when it covers the template, else from the loaded graph.
     void compact(bool from_candidate = false) {
+        if (from_candidate)
+            compact_from(c_rp, c_col, c_off, false);
+        else if (pairs_cover())
+            compact_from(c->pair_rp.as<int64_t>(), c->pair_col.as<int32_t>(),
+                         c->pair_off.as<int32_t>(), true);
+        else
+            compact_from(c->rp, c->col, nullptr, true);
+    }
+
+    // The label-pair subgraph: with one role per label (T's vertices are the
+    // labels, its local table their pair adjacency), initial roles from the
+    // labels and one compaction of the loaded graph keep exactly the entries
+    // whose label pair is adjacent.
+    void label_pair_compaction() {
+        const int64_t n = c->n;
+        zero_counters();
+        w->actbits.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>((n + 63) / 64, 1));
+        wl.act_bits = w->actbits.as<uint64_t>();
+        launch_init_roles<M>(s, n, c->labels, c->label_bytes, T.d_init_lut, T.init_lut_len, om,
+                             w->actbits.as<uint64_t>());
+        collect(true);
+        compact_from(c->rp, c->col, nullptr, true);
+    }
+
+    // Compaction of src (row_ptr, col and, for a subgraph of the loaded
+    // graph, every entry's offset in its original row; null: src is the
+    // loaded graph).  first: the prune's first compaction (it builds the
+    // coarse activity filter the later ones reuse).
+    void compact_from(const int64_t *src_rp, const int32_t *src_col, const int32_t *base_off,
+                      bool first) {
         Timer t(s);
         const int64_t n = c->n;
-        const int64_t *src_rp = from_candidate ? c_rp : c->rp;
-        const int32_t *src_col = from_candidate ? c_col : c->col;
-        const int32_t *base_off = from_candidate ? c_off : nullptr;
         Graph src{src_rp, src_col};
         bin(src);
-        const int nb = from_candidate ? 1 - cbuf : cbuf;
+        const int nb = first ? cbuf : 1 - cbuf;
         DevBuf &crp = nb ? w->crp2 : w->crp;
         DevBuf &ccol = nb ? w->ccol2 : w->ccol;
         DevBuf &coff = nb ? w->coff2 : w->coff;
@@ -453,7 +507,7 @@ struct Pruner {
         crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
         int64_t *deg = w->cdeg.as<int64_t>();
         PM_HIP(hipMemsetAsync(deg, 0, sizeof(int64_t) * (size_t)(n + 1), s));
-        if (!from_candidate) {
+        if (first) {
             // coarse filter of the active set; it stays valid (a superset)
             // for later compactions of this prune, since role sets only shrink
             w->afilt.ensure(sizeof(uint32_t) * (size_t)std::max<int64_t>((n + 255) / 256, 1));
@@ -1541,6 +1595,89 @@ void prune_impl(pm_ctx *c, int32_t first_id, int32_t count, uint64_t *role_mask,
         for (int32_t i = 0; i < count; ++i) opt->per_template[i] = per[(size_t)i];
 }
 
+// Label-pair subgraph for the label pairs of templates [first, first+count).
+void build_pair_index(pm_ctx *c, int32_t first, int32_t count) {
+    c->pair_m = -1;
+    c->pair_nl = 0;
+    c->pair_adj.clear();
+    int maxl = -1;
+    for (int32_t i = first; i < first + count; ++i)
+        for (int l : c->templates[(size_t)i]->labels) maxl = std::max(maxl, l);
+    const int nl = maxl + 1;
+    std::vector<uint8_t> adj((size_t)nl * (size_t)std::max(nl, 0), 0);
+    std::vector<int> role_of((size_t)std::max(nl, 1), -1);
+    std::vector<int> labs;
+    for (int32_t i = first; i < first + count; ++i) {
+        const CompiledTemplate &T = *c->templates[(size_t)i];
+        for (const auto &e : T.edges) {
+            const int la = T.labels[(size_t)e.first], lb = T.labels[(size_t)e.second];
+            adj[(size_t)la * nl + lb] = adj[(size_t)lb * nl + la] = 1;
+            for (int l : {la, lb})
+                if (role_of[(size_t)l] < 0) {
+                    role_of[(size_t)l] = (int)labs.size();
+                    labs.push_back(l);
+                }
+        }
+    }
+    if (labs.size() > (size_t)kMaxK)
+        throw Error(PM_ERR_INVALID_ARG, "the templates' edges use more than 64 labels");
+    // one role per label; its local table: the labels adjacent to it
+    CompiledTemplate P;
+    P.n0 = (int32_t)labs.size();
+    P.labels = labs;
+    P.mask_bytes = P.n0 <= 8 ? 1 : P.n0 <= 16 ? 2 : P.n0 <= 32 ? 4 : 8;
+    P.lcc.n0 = P.n0;
+    for (int i = 0; i < P.n0; ++i)
+        for (int j = 0; j < P.n0; ++j)
+            if (adj[(size_t)labs[(size_t)i] * nl + labs[(size_t)j]]) P.lcc.adj[i] |= 1ull << j;
+    std::vector<uint64_t> lut((size_t)std::max(nl, 1), 0ull);
+    for (int i = 0; i < P.n0; ++i) lut[(size_t)labs[(size_t)i]] = 1ull << i;
+    DevBuf d_lut;
+    d_lut.ensure(sizeof(uint64_t) * lut.size());
+    PM_HIP(hipMemcpy(d_lut.p, lut.data(), sizeof(uint64_t) * lut.size(), hipMemcpyHostToDevice));
+    P.d_init_lut = d_lut.as<uint64_t>();
+    P.init_lut_len = (int64_t)lut.size();
+    const int64_t n = c->n;
+    Timer t(c->stream);
+    Scratch tmp;
+    tmp.stream = c->stream;
+    auto go = [&](auto &p) {
+        p.label_pair_compaction();
+        c->pair_rp.ensure(sizeof(int64_t) * (size_t)(n + 1));
+        c->pair_col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(p.c_m, 1));
+        c->pair_off.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(p.c_m, 1));
+        PM_HIP(hipMemcpyAsync(c->pair_rp.p, p.c_rp, sizeof(int64_t) * (size_t)(n + 1),
+                              hipMemcpyDeviceToDevice, c->stream));
+        if (p.c_m > 0) {
+            PM_HIP(hipMemcpyAsync(c->pair_col.p, p.c_col, sizeof(int32_t) * (size_t)p.c_m,
+                                  hipMemcpyDeviceToDevice, c->stream));
+            PM_HIP(hipMemcpyAsync(c->pair_off.p, p.c_off, sizeof(int32_t) * (size_t)p.c_m,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        }
+        c->pair_m = p.c_m;
+    };
+    switch (P.mask_bytes) {
+    case 1: { Pruner<uint8_t> p(c, &tmp, P); go(p); break; }
+    case 2: { Pruner<uint16_t> p(c, &tmp, P); go(p); break; }
+    case 4: { Pruner<uint32_t> p(c, &tmp, P); go(p); break; }
+    default: { Pruner<uint64_t> p(c, &tmp, P); go(p); break; }
+    }
+    c->ms_pair_index = t.stop();
+    PM_HIP(hipStreamSynchronize(c->stream));
+    P.d_init_lut = nullptr;
+    c->pair_nl = nl;
+    c->pair_adj = std::move(adj);
+}
+
+void drop_pair_index(pm_ctx *c) {
+    c->pair_rp.release();
+    c->pair_col.release();
+    c->pair_off.release();
+    c->pair_m = -1;
+    c->pair_nl = 0;
+    c->pair_adj.clear();
+}
+
 }  // namespace
 
 extern "C" {
@@ -1606,6 +1743,7 @@ int pm_destroy(pm_ctx *c) {
         for (DevBuf *b : {&c->own_rp, &c->own_col, &c->own_labels, &c->lab_cnt, &c->idx_hub_v,
                           &c->idx_seg_slot, &c->idx_seg_b, &c->idx_seg_e, &c->idx_hub_cnt})
             b->release();
+        drop_pair_index(c);
         c->scratch.clear();
         for (DevBuf *b : {&c->model, &c->mlp_partial, &c->mlp_ploss, &c->mlp_grad, &c->mlp_m,
                           &c->mlp_v, &c->mlp_loss})
@@ -1647,6 +1785,7 @@ int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const
         c->own_col.release();
         c->own_labels.release();
         c->lab_cnt.release();
+        drop_pair_index(c);
         for (DevBuf *b : {&c->idx_hub_v, &c->idx_seg_slot, &c->idx_seg_b, &c->idx_seg_e, &c->idx_hub_cnt})
             b->release();
         c->nlab = 0;
@@ -1743,6 +1882,28 @@ int pm_load_graph(pm_ctx *c, int64_t n, int64_t m, const int64_t *row_ptr, const
     });
 }
 
+int pm_build_pair_index(pm_ctx *c, int32_t first_id, int32_t count, double *ms) {
+    return guarded([&] {
+        if (!c || count < 0) throw Error(PM_ERR_INVALID_ARG, "bad arguments");
+        if (!c->has_graph) throw Error(PM_ERR_NO_GRAPH, "no graph loaded");
+        set_device(c);
+        drop_pair_index(c);
+        if (count == 0) {
+            if (ms) *ms = 0.0;
+            return;
+        }
+        if (first_id < 0 || (size_t)first_id + (size_t)count > c->templates.size())
+            throw Error(PM_ERR_INVALID_ARG, "template id out of range");
+        try {
+            build_pair_index(c, first_id, count);
+        } catch (...) {
+            drop_pair_index(c);
+            throw;
+        }
+        if (ms) *ms = c->ms_pair_index;
+    });
+}
+
 int pm_build_count_index(pm_ctx *c, double *ms) {
     return guarded([&] {
         if (!c) throw Error(PM_ERR_INVALID_ARG, "null context");
@@ -1769,6 +1930,8 @@ int pm_graph_info(pm_ctx *c, pm_graph_info_t *out) {
         g.hubs = c->idx_hubs;
         g.hub_segments = c->idx_segs;
         g.ms_count_index = c->ms_count_index;
+        g.pair_entries = c->pair_m;
+        g.ms_pair_index = c->pair_m >= 0 ? c->ms_pair_index : 0.0;
         *out = g;
     });
 }
@@ -1782,6 +1945,7 @@ int pm_unload_graph(pm_ctx *c) {
         c->own_col.release();
         c->own_labels.release();
         c->lab_cnt.release();
+        drop_pair_index(c);
         c->nlab = 0;
         c->rp = nullptr;
         c->col = nullptr;

@@ -45,7 +45,7 @@ SYMBOLS = ["pm_last_error", "pm_version", "pm_create", "pm_destroy", "pm_load_gr
            "pm_inspect_template", "pm_prune", "pm_load_model", "pm_mlp_forward", "pm_mlp_grad",
            "pm_mlp_train", "pm_set_param", "pm_get_param", "pm_export_state",
            "pm_import_state", "pm_workspace_size", "pm_set_workspace", "pm_prune_noalloc",
-           "pm_count_matches", "pm_build_count_index", "pm_graph_info"]
+           "pm_count_matches", "pm_build_count_index", "pm_graph_info", "pm_build_pair_index"]
 
 
 class PMError(RuntimeError):
@@ -111,7 +111,8 @@ class pm_graph_info_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("label_bytes", ctypes.c_int32),
                 ("index_labels", ctypes.c_int32), ("index_bytes", ctypes.c_int64),
                 ("hubs", ctypes.c_int64), ("hub_segments", ctypes.c_int64),
-                ("ms_count_index", ctypes.c_double)]
+                ("ms_count_index", ctypes.c_double), ("pair_entries", ctypes.c_int64),
+                ("ms_pair_index", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -175,6 +176,7 @@ def load_library():
     lib.pm_count_matches.argtypes = [P, I32, P, P, I64, ctypes.c_uint64,
                                      ctypes.POINTER(pm_match_count)]
     lib.pm_build_count_index.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    lib.pm_build_pair_index.argtypes = [P, I32, I32, ctypes.POINTER(ctypes.c_double)]
     lib.pm_graph_info.argtypes = [P, ctypes.POINTER(pm_graph_info_t)]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = ctypes.c_int
@@ -252,6 +254,14 @@ class PM:
         """Rebuild the neighbour-label count index; returns its device ms."""
         ms = ctypes.c_double()
         _check(self.lib, self.lib.pm_build_count_index(self.h, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def build_pair_index(self, first_id: int, count: int = 1) -> float:
+        """Build the label-pair subgraph for templates [first_id,
+        first_id + count) (count 0 frees it); returns its device ms."""
+        ms = ctypes.c_double()
+        _check(self.lib, self.lib.pm_build_pair_index(self.h, int(first_id), int(count),
+                                                      ctypes.byref(ms)))
         return float(ms.value)
 
     def graph_info(self) -> dict:

@@ -137,6 +137,7 @@ int main(void) {
     printf("pm_match_count %zu\n", sizeof(pm_match_count));
     printf("pm_graph_info_t %zu\n", sizeof(pm_graph_info_t));
     F(pm_graph_info_t, index_labels); F(pm_graph_info_t, index_bytes); F(pm_graph_info_t, ms_count_index);
+    F(pm_graph_info_t, pair_entries); F(pm_graph_info_t, ms_pair_index);
     F(pm_match_count, maps); F(pm_match_count, automorphisms); F(pm_match_count, subgraphs);
     F(pm_match_count, written); F(pm_match_count, roots); F(pm_match_count, ms_total);
     F(pm_match_count, complete);
