@@ -106,6 +106,68 @@ struct Timer {
     }
 };
 
+// Phase timing without waits: each span records an event pair on the
+// stream, and the pairs are read once the prune has finished, so timing a
+// phase never stalls the host between launches.
+struct TimeLog {
+    struct Ent {
+        hipEvent_t a, b;
+        double *dst, *dst2;
+        double sign;
+    };
+    std::vector<Ent> ents;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take() {
+        hipEvent_t e{};
+        if (pool.empty()) {
+            PM_HIP(hipEventCreate(&e));
+        } else {
+            e = pool.back();
+            pool.pop_back();
+        }
+        return e;
+    }
+    // Adds every recorded span to its destinations (waits for the last).
+    void resolve() {
+        for (Ent &x : ents) {
+            PM_HIP(hipEventSynchronize(x.b));
+            float ms = 0;
+            PM_HIP(hipEventElapsedTime(&ms, x.a, x.b));
+            *x.dst += x.sign * ms;
+            if (x.dst2) *x.dst2 += x.sign * ms;
+            pool.push_back(x.a);
+            pool.push_back(x.b);
+        }
+        ents.clear();
+    }
+    ~TimeLog() {
+        for (Ent &x : ents) {
+            (void)hipEventDestroy(x.a);
+            (void)hipEventDestroy(x.b);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct Span {
+    TimeLog &log;
+    hipStream_t s;
+    hipEvent_t a;
+    bool done = false;
+    Span(TimeLog &l, hipStream_t st) : log(l), s(st), a(l.take()) { PM_HIP(hipEventRecord(a, s)); }
+    // The span's device time is added (times sign) to dst, and to *dst2,
+    // when the log resolves.
+    void stop(double &dst, double *dst2 = nullptr, double sign = 1.0) {
+        hipEvent_t b = log.take();
+        PM_HIP(hipEventRecord(b, s));
+        log.ents.push_back(TimeLog::Ent{a, b, &dst, dst2, sign});
+        done = true;
+    }
+    ~Span() {
+        if (!done) log.pool.push_back(a);
+    }
+};
+
 // Device scratch of one pruning worker (one template at a time) and the
 // stream its kernels run on.
 struct Scratch {
@@ -296,6 +358,7 @@ struct Pruner {
     uint64_t done_mask = 0;
     int exp_log2;
     int64_t split_cap;
+    TimeLog tl;                     // phase times, read when the prune ends
 
     Pruner(pm_ctx *ctx, Scratch *scr, const CompiledTemplate &t, const pm_options *o = nullptr)
         : c(ctx), w(scr), T(t), s(scr->stream), opt(o), lcc(t.lcc), exp_log2(ctx->exp_log2),
@@ -370,40 +433,48 @@ struct Pruner {
         nA = read_ctr(C_ACTIVE);
     }
 
-    // Degree bins of the active list in graph g, hub segments, host counts.
-    int64_t binned_entries = 0;
-    void bin(const Graph &g) {
+    // The loop-control words of the counter block (bins, hub segments,
+    // change flag, active count, binned entries), read in one round trip.
+    struct Ctl {
+        int32_t w[C_ENTRIES_U64];
+        unsigned long long entries;
+    };
+    Ctl read_control() {
+        Ctl cb;
+        d2h(s, reinterpret_cast<char *>(&cb), w->counters.as<char>(), sizeof(Ctl));
+        return cb;
+    }
+    void take_bins(const Ctl &cb) {
+        for (int b = 0; b < 4; ++b) hc[b] = cb.w[C_BINS + b];
+        nseg = cb.w[C_NSEG];
+        binned_entries = (int64_t)cb.entries;
+        if (hc[3] > wl.hub_capacity || nseg > wl.seg_capacity)
+            throw Error(PM_ERR_CAPACITY, "hub segment capacity exceeded");
+    }
+    // Bins (and hub segments) of the vertices of the active list that hold
+    // a role in graph g; launched only, the counts are read with the next
+    // control read.
+    void launch_bins(const Graph &g) {
         PM_HIP(hipMemsetAsync(ctr + C_BINS, 0, sizeof(int32_t) * 5, s));
         PM_HIP(hipMemsetAsync(wl.entries, 0, sizeof(unsigned long long), s));
         launch_bin<M>(s, A, nA, g.rp, om, wl);
         launch_hub_segments(s, g.rp, wl, 0);
-        int32_t h[5];
-        d2h(s, h, ctr + C_BINS, 5);
-        for (int b = 0; b < 4; ++b) hc[b] = h[b];
-        nseg = h[4];
-        unsigned long long ent = 0;
-        d2h(s, &ent, wl.entries, 1);
-        binned_entries = (int64_t)ent;
-        if (hc[3] > wl.hub_capacity || nseg > wl.seg_capacity)
-            throw Error(PM_ERR_CAPACITY, "hub segment capacity exceeded");
+    }
+
+    // Degree bins of the active list in graph g, hub segments, host counts.
+    int64_t binned_entries = 0;
+    void bin(const Graph &g) {
+        launch_bins(g);
+        take_bins(read_control());
     }
 
     int32_t sweep(const Graph &g, bool full = false) {
         PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
         if (full) {
             // device time of the sweep kernel alone (the HBM-bound step)
-            hipEvent_t a, b;
-            PM_HIP(hipEventCreate(&a));
-            PM_HIP(hipEventCreate(&b));
-            PM_HIP(hipEventRecord(a, s));
+            Span k(tl, s);
             launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, lcc, ctr + C_CHANGED, true);
-            PM_HIP(hipEventRecord(b, s));
-            PM_HIP(hipEventSynchronize(b));
-            float ms = 0;
-            PM_HIP(hipEventElapsedTime(&ms, a, b));
-            st.ms_sweep_kernel += ms;
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
+            k.stop(st.ms_sweep_kernel);
         } else {
             launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, lcc, ctr + C_CHANGED, false);
         }
@@ -418,25 +489,39 @@ struct Pruner {
     // compacted again first (entries to eliminated vertices go), so later
     // sweeps and the role lists read only live entries.
     void lcc_fixpoint() {
-        Timer t(s);
+        Span t(tl, s);
+        Graph g{c_rp, c_col};
+        bin(g);
         for (;;) {
-            Graph g{c_rp, c_col};
-            bin(g);
             if (nA * 2 < nA_compact && binned_entries > kRecompactEntries &&
                 binned_entries > 4 * nA) {
-                const double ms_before = st.ms_compact;
+                Span rc(tl, s);   // counted as compaction, not LCC
                 compact(true);
-                st.ms_lcc -= st.ms_compact - ms_before;   // counted as compaction
+                rc.stop(st.ms_lcc, nullptr, -1.0);
                 g = Graph{c_rp, c_col};
                 bin(g);
             }
-            int32_t ch = sweep(g);
-            if (!ch) break;
+            // the sweep, then the next active list and its bins, whose
+            // counts come back with the change flag in one round trip (if
+            // nothing changed they are discarded: the set is the same)
+            PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
+            launch_lcc_sweep<M>(s, g.rp, g.col, om, wl, hc, nseg, lcc, ctr + C_CHANGED, false);
+            st.lcc_sweeps++;
+            PM_HIP(hipMemsetAsync(ctr + C_ACTIVE, 0, sizeof(int32_t), s));
+            launch_collect<M>(s, A, nA, om, Aalt, ctr + C_ACTIVE);
+            launch_bins(g);
+            const Ctl cb = read_control();
+            if (!cb.w[C_CHANGED]) {
+                take_bins(cb);
+                break;
+            }
+            std::swap(A, Aalt);
+            nA = cb.w[C_ACTIVE];
+            take_bins(cb);
             rl_valid = false;
-            collect(false);
             if (nA == 0) break;
         }
-        st.ms_lcc += t.stop();
+        t.stop(st.ms_lcc);
     }
 
     // Compacted candidate subgraph of the current state (edge elimination),
@@ -494,7 +579,7 @@ struct Pruner {
     // coarse activity filter the later ones reuse).
     void compact_from(const int64_t *src_rp, const int32_t *src_col, const int32_t *base_off,
                       bool first) {
-        Timer t(s);
+        Span t(tl, s);
         const int64_t n = c->n;
         Graph src{src_rp, src_col};
         bin(src);
@@ -542,7 +627,7 @@ struct Pruner {
         nA_compact = nA;
         rl_valid = false;
         st.candidate_entries = c_m;
-        st.ms_compact += t.stop();
+        t.stop(st.ms_compact);
     }
 
     SearchArgs search_args(int mode, uint64_t heads, const int32_t *plan_of_head,
@@ -621,24 +706,34 @@ struct Pruner {
         rl_valid = true;
     }
 
-    // One non-local constraint (snapshot semantics); returns vertices changed.
+    // One non-local constraint (snapshot semantics); returns the vertices
+    // changed, with the active list already updated.
     int32_t nlcc(const Constraint &k) {
-        Timer t(s);
+        Span t(tl, s);
         if (!rl_valid) role_lists();
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         SearchArgs a = search_args(0, k.heads, k.plan_of_head, nullptr);
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
         PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
         launch_apply<M>(s, A, nA, om, sat, k.heads, ctr + C_CHANGED);
-        int32_t ch = read_ctr(C_CHANGED);
-        if (ch) rl_valid = false;
+        // the next active list comes back with the change count in one
+        // round trip (discarded when nothing changed: the set is the same)
+        PM_HIP(hipMemsetAsync(ctr + C_ACTIVE, 0, sizeof(int32_t), s));
+        launch_collect<M>(s, A, nA, om, Aalt, ctr + C_ACTIVE);
+        const Ctl cb = read_control();
+        const int32_t ch = cb.w[C_CHANGED];
+        if (ch) {
+            rl_valid = false;
+            std::swap(A, Aalt);
+            nA = cb.w[C_ACTIVE];
+        }
         st.constraints++;
-        st.ms_nlcc += t.stop();
+        t.stop(st.ms_nlcc);
         return ch;
     }
 
     void exact(uint64_t *role_out, uint64_t *edge_out) {
-        Timer t(s);
+        Span t(tl, s);
         const int64_t n = c->n;
         // certified roles live in sat (cleared by every apply and at start)
         const uint64_t all = T.n0 == 64 ? ~0ull : ((1ull << T.n0) - 1ull);
@@ -792,7 +887,7 @@ struct Pruner {
         st.expand_valid += (int64_t)qs[13];
         st.witness_edges += (int64_t)qs[14];
         st.join_edges += (int64_t)qs[15];
-        st.ms_exact += t.stop();
+        t.stop(st.ms_exact);
     }
 
     // ---- constraint loop -----------------------------------------------------
@@ -902,13 +997,12 @@ struct Pruner {
                     }
                 }
             }
-            Timer tt(s);
+            // per-step device time only for the trace (it waits)
+            std::unique_ptr<Timer> tt;
+            if (trace && n_trace < cap) tt.reset(new Timer(s));
             int32_t ch = nlcc(T.constraints[(size_t)k]);
-            if (ch) {
-                collect(false);
-                if (nA > 0) lcc_fixpoint();
-            }
-            const double ms = tt.stop();
+            if (ch && nA > 0) lcc_fixpoint();
+            const double ms = tt ? tt->stop() : 0.0;
             remaining &= ~(1ull << k);
             done_mask |= 1ull << k;
             ++done;
@@ -942,23 +1036,14 @@ struct Pruner {
         if (counted) {
             // first LCC sweep from the neighbour-label count index (it also
             // initialises omega)
-            Timer t(s);
-            hipEvent_t a, b;
-            PM_HIP(hipEventCreate(&a));
-            PM_HIP(hipEventCreate(&b));
-            PM_HIP(hipEventRecord(a, s));
+            Span t(tl, s);
+            Span k(tl, s);
             const int32_t *nd = T.d_need;
             launch_first_sweep_counts<M>(s, n, c->cnt_stride, (const uint8_t *)c->labels, T.d_init_lut,
                                          (int)std::min<int64_t>(T.init_lut_len, 256),
                                          c->lab_cnt.as<uint8_t>(), c->nlab, nd, nd + T.n0 + 1,
                                          nd + T.n0 + 1 + T.need_lab.size(), T.n0, om);
-            PM_HIP(hipEventRecord(b, s));
-            PM_HIP(hipEventSynchronize(b));
-            float ms = 0;
-            PM_HIP(hipEventElapsedTime(&ms, a, b));
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-            st.ms_sweep_kernel += ms;
+            k.stop(st.ms_sweep_kernel);
             // compulsory bytes: every label, for each vertex the count bytes
             // of the labels its initial roles need (a function of its
             // label), and omega written
@@ -976,11 +1061,10 @@ struct Pruner {
             if (init_state) launch_and_state<M>(s, n, om, init_state);
             PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
             collect(true);
-            st.ms_first_sweep = t.stop();
-            st.ms_lcc += st.ms_first_sweep;
+            t.stop(st.ms_first_sweep, &st.ms_lcc);
             st.lcc_sweeps++;
         } else {
-            Timer t(s);
+            Span t(tl, s);
             w->actbits.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>((n + 63) / 64, 1));
             wl.act_bits = w->actbits.as<uint64_t>();
             launch_init_roles<M>(s, n, c->labels, c->label_bytes, T.d_init_lut, T.init_lut_len, om,
@@ -988,14 +1072,14 @@ struct Pruner {
             if (init_state) launch_and_state<M>(s, n, om, init_state);
             PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
             collect(true);
-            st.ms_init += t.stop();
+            t.stop(st.ms_init);
         }
         return counted;
     }
 
     // Whole prune.  edge_out may be null (state export: no edge output).
     void run(uint64_t *role_out, uint64_t *edge_out) {
-        Timer total(s);
+        Span total(tl, s);
         const int64_t n = c->n, m = c->m;
         if (opt) {
             init_state = opt->init_state;
@@ -1009,13 +1093,12 @@ struct Pruner {
         Graph full{c->rp, c->col};
         if (!counted && T.n0 > 1 && nA > 0) {
             // first sweep over the full graph
-            Timer t(s);
+            Span t(tl, s);
             bin(full);
             st.first_sweep_vertices = nA;
             st.first_sweep_entries = binned_entries;
             int32_t ch = sweep(full, true);
-            st.ms_first_sweep = t.stop();
-            st.ms_lcc += st.ms_first_sweep;
+            t.stop(st.ms_first_sweep, &st.ms_lcc);
             if (ch) collect(false);
         }
         // candidate subgraph (edge elimination) and the rest of LCC on it
@@ -1052,7 +1135,8 @@ struct Pruner {
             exact(role_out, edge_out);
         }
         st.done_mask = done_mask;
-        st.ms_total = total.stop();
+        total.stop(st.ms_total);
+        tl.resolve();
         st.workspace_bytes = (int64_t)w->bytes_held();
     }
 
@@ -1062,7 +1146,7 @@ struct Pruner {
     // compacted entry that can hold the chosen template edge.
     pm_match_count count_matches(const uint64_t *state, int32_t *maps_out, int64_t cap,
                                  uint64_t limit) {
-        Timer total(s);
+        Span total(tl, s);
         pm_match_count r{};
         r.complete = 1;
         init_state = state;
@@ -1155,7 +1239,10 @@ struct Pruner {
             r.maps = both[0];
             r.written = maps_out ? (int64_t)std::min<unsigned long long>(both[1], (unsigned long long)std::max<int64_t>(cap, 0)) : 0;
         }
-        r.ms_total = total.stop();
+        double ms_total = 0.0;
+        total.stop(ms_total);
+        tl.resolve();
+        r.ms_total = ms_total;
         return r;
     }
 };

@@ -1134,20 +1134,20 @@ void launch_split_search(hipStream_t s, const SplitTask *tasks, int64_t n_tasks,
 }
 
 // Output edge bits from certified compacted entries (a certified edge holds
-// the bit of one or both of its entries).  One thread per entry u -> w with
-// u < w (c_own gives its row): the reverse entry is found in w's compacted
-// row, and if either bit is set both CSR entries of the edge are set.
+// the bit of one or both of its entries).  One thread per entry u -> w:
+// entries not certified are skipped after one coalesced read of their
+// certificate word; a certified one sets its own CSR entry's bit and, found
+// by a search of w's compacted row, that of its reverse entry.  The searches
+// scale with the certified entries, not with the candidate subgraph.
 __global__ __launch_bounds__(kSearchBlock) void edges_from_cert_kernel(
     int64_t c_m, const int64_t *c_rp, const int32_t *c_col, const int32_t *c_own,
     const int32_t *c_off, const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < c_m;
          k += (int64_t)gridDim.x * blockDim.x) {
+        if (!test_bit(c_cert, k)) continue;
         const int32_t u = c_own[k], w = c_col[k];
-        if (u >= w) continue;
-        const bool fwd = test_bit(c_cert, k);
-        const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
-        if (!fwd && (kr < 0 || !test_bit(c_cert, kr))) continue;
         set_bit(edge_bits, rp[u] + c_off[k]);
+        const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
         if (kr >= 0) set_bit(edge_bits, rp[w] + c_off[kr]);
     }
 }

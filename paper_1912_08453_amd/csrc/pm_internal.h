@@ -312,8 +312,8 @@ void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, cons
                       const int32_t *c_col, const M *omega, int n0, const int64_t *rl_off,
                       int32_t *rl_col, int32_t *rl_ent);
 
-// Output edge bits (both entries) from certified compacted entries u -> w,
-// u < w; one thread per 64 compacted entries (c_own gives each entry's row).
+// Output edge bits (both entries) from certified compacted entries; one
+// thread per compacted entry (c_own gives each entry's row).
 void launch_edges_from_cert(hipStream_t s, int64_t c_m, const int64_t *c_rp, const int32_t *c_col,
                             const int32_t *c_own, const int32_t *c_off, const int64_t *rp,
                             const uint64_t *c_cert, uint64_t *edge_bits);

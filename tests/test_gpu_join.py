@@ -3,8 +3,10 @@ certified without a search when the recorded matches of its two ends,
 joined across a bridge of the template, form a match.  The complete sets
 must equal the oracle's with the joins on, on a hand-built graph where the
 only join on offer puts two vertices of one label on the same image (it
-must be refused), on trees and one-cycle templates with repeated labels,
-and on the theta8 relaxations (mostly trees) at two scales."""
+must be refused), on a cycle whose two recorded matches share a vertex but
+cannot be spliced, on tiny random graphs over few labels with cyclic
+templates, on trees and one-cycle templates with repeated labels, and on
+the theta8 relaxations (mostly trees) at two scales."""
 import sys
 
 import numpy as np
@@ -92,6 +94,58 @@ def test_join_refuses_two_images_of_one_label(pmmod, torch_dev, settings):
     ctx = ctx_on(pmmod, torch_dev, g, settings)
     check_all(pmmod, ctx, g, [t], [ref], f"hand case {settings}")
     ctx.close()
+
+
+@pytest.mark.parametrize("settings", JOIN_ON)
+def test_cycle_edge_between_two_recorded_matches(pmmod, torch_dev, settings):
+    # 6-cycle template a-b-c-d-e-f labelled A B Z D Z F.  The only match
+    # through a=u (vertex 0) is (0, 2, 4, 7, 5, 8), the only one through b=w
+    # (vertex 1) is (3, 1, 5, 7, 6, 9).  Both put d on vertex 7, so the
+    # edge {0, 1} would close a cycle from halves of the two -- but e (from
+    # the first) and c (from the second) are both vertex 5, and no match
+    # uses the edge: neither a swap nor a join may certify it.
+    E = [(0, 2), (2, 4), (4, 7), (7, 5), (5, 8), (8, 0), (3, 1), (1, 5), (7, 6), (6, 9),
+         (9, 3), (0, 1)]
+    rp, col = csr(10, E)
+    g = I.Graph(rp, col, np.array([0, 1, 1, 0, 2, 2, 2, 3, 4, 4], dtype=np.uint8))
+    t = I.Template([0, 1, 2, 3, 2, 4], [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 0)])
+    ref = oracle.prune(g.row_ptr, g.col, g.labels, t.labels, t.edges)
+    k01 = int(np.nonzero(g.col[g.row_ptr[0]:g.row_ptr[1]] == 1)[0][0])
+    assert not (int(ref.edge_bits[0]) >> k01) & 1, "the oracle keeps edge {0, 1}"
+    ctx = ctx_on(pmmod, torch_dev, g, settings)
+    check_all(pmmod, ctx, g, [t], [ref], f"cycle case {settings}")
+    ctx.close()
+
+
+def random_cyclic_case(seed):
+    # tiny random graphs over 1-3 labels (many same-label pairs, so joins
+    # that would reuse an image are frequent) and cyclic templates
+    rng = np.random.Generator(np.random.Philox(seed + 5000))
+    n = int(rng.integers(10, 48))
+    p = float(rng.uniform(0.08, 0.35))
+    nl = int(rng.integers(1, 4))
+    g = I.random_graph(n, p, nl, seed + 5000)
+    n0 = int(rng.integers(3, 8))
+    kind = seed % 3
+    if kind == 0:
+        edges = I.shape_one_cycle(rng, n0)
+    elif kind == 1:
+        edges = I.shape_two_cycles(rng, max(n0, 5))
+    else:
+        edges = I.shape_tree(rng, n0)
+    n0 = max(max(a, b) for a, b in edges) + 1
+    labels = [int(x) for x in rng.integers(0, nl, size=n0)]
+    return g, I.Template(labels, edges)
+
+
+@pytest.mark.parametrize("seed", range(90))
+def test_random_tiny_cases_with_joins(pmmod, torch_dev, seed):
+    g, t = random_cyclic_case(seed)
+    ref = oracle.prune(g.row_ptr, g.col, g.labels, t.labels, t.edges)
+    for settings in JOIN_ON[:2]:
+        ctx = ctx_on(pmmod, torch_dev, g, settings)
+        check_all(pmmod, ctx, g, [t], [ref], f"seed {seed} {t.labels}/{t.edges} {settings}")
+        ctx.close()
 
 
 @pytest.fixture(scope="module")
