@@ -179,13 +179,13 @@ struct Scratch {
         coff2, cown2,
         segcnt, segscan, segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
-        actbits, ord, afilt, split[2];
+        rlv, actbits, ord, afilt, split[2];
     std::vector<DevBuf *> all() {
         return {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
                 &ccol, &coff, &cown, &crp2, &ccol2, &coff2, &cown2, &segcnt, &segscan, &segbits,
                 &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids, &ccert, &expseen, &wit, &witflag,
-                &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &actbits, &ord, &afilt, &split[0],
-                &split[1]};
+                &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &rlv, &actbits, &ord,
+                &afilt, &split[0], &split[1]};
     }
     // Draw every buffer from [base, base + cap) from now on (library-owned
     // buffers are freed first), or, with base == nullptr, return to
@@ -642,6 +642,7 @@ struct Pruner {
         a.tedges = T.d_tedges;
         a.m0 = T.m0;
         a.rl_off = w->rloff.as<int64_t>();
+        a.rl_v = w->rlv.as<int32_t>();
         a.rl_col = w->rlcol.as<int32_t>();
         a.rl_ent = w->rlent.as<int32_t>();
         a.rl_pos = w->rlpos.as<int32_t>();
@@ -703,6 +704,8 @@ struct Pruner {
         w->rlent.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(rl_total, 1));
         launch_role_fill<M>(s, A, nA, c_rp, c_col, om, T.n0, w->rloff.as<int64_t>(),
                             w->rlcol.as<int32_t>(), w->rlent.as<int32_t>());
+        w->rlv.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c->n, 1) * (size_t)(T.n0 + 1));
+        launch_role_rows(s, A, nA, T.n0, w->rloff.as<int64_t>(), w->rlv.as<int32_t>());
         rl_valid = true;
     }
 
@@ -801,6 +804,7 @@ struct Pruner {
                 std::swap(om, sat);
                 rl_valid = false;   // lists of the certified sets, not of omega
                 a.rl_off = w->rloff.as<int64_t>();
+                a.rl_v = w->rlv.as<int32_t>();
                 a.rl_col = w->rlcol.as<int32_t>();
                 a.rl_ent = w->rlent.as<int32_t>();
                 a.rl_pos = w->rlpos.as<int32_t>();
@@ -1459,6 +1463,7 @@ size_t workspace_bound(const pm_ctx *c, const CompiledTemplate &T, int exp_log2,
     }
     add(8 * (nt * n0 + 1)); add(8 * (nt * n0 + 1));           // role-list counts, offsets
     add(4 * n);                                               // list positions
+    add(4 * n * (n0 + 1));                                    // list bounds by vertex
     add(4 * mt * maxmult); add(4 * mt * maxmult);             // role lists, entries
     add(8 * scan_scratch_len(nt * n0));
     add((int64_t)sizeof(unsigned long long) * 2 * kMaxK + (int64_t)sizeof(OrderPick) + 64);

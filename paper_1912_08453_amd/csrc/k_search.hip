@@ -145,6 +145,29 @@ void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, cons
                        tasks, n_tasks, c_rp, c_col, omega, n0, rl_off, rl_col, rl_ent);
 }
 
+// Per-vertex copy of the list bounds: rl_v[v * (n0 + 1) + q] = start of
+// v's role-q list (q = n0: end of its last list), so a search reaches a
+// vertex's lists from its id without the task-position lookup.
+__global__ __launch_bounds__(kSearchBlock) void role_rows_kernel(const int32_t *tasks,
+                                                                 int64_t n_tasks, int n0,
+                                                                 const int64_t *rl_off,
+                                                                 int32_t *rl_v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = n0 + 1;
+    if (i >= n_tasks * w) return;
+    const int64_t t = i / w;
+    const int64_t q = i - t * w;
+    rl_v[(int64_t)tasks[t] * w + q] = (int32_t)rl_off[t * n0 + q];
+}
+
+void launch_role_rows(hipStream_t s, const int32_t *tasks, int64_t n_tasks, int n0,
+                      const int64_t *rl_off, int32_t *rl_v) {
+    const int64_t total = n_tasks * (n0 + 1);
+    if (total <= 0) return;
+    hipLaunchKernelGGL(role_rows_kernel, dim3((unsigned)((total + kSearchBlock - 1) / kSearchBlock)),
+                       dim3(kSearchBlock), 0, s, tasks, n_tasks, n0, rl_off, rl_v);
+}
+
 // ----------------------------------------------------- sorted-list search
 // Membership of each lane's key x in one sorted list col[lo, hi) shared by
 // the whole wavefront (all lanes call with the same bounds; lanes with
@@ -192,10 +215,10 @@ __device__ __forceinline__ int64_t wave_find(const int32_t *__restrict__ col, in
 // Every vertex a search reaches holds a role, so it is in the task list the
 // role lists were built from and has a list position.
 __device__ __forceinline__ int64_t rl_begin(const SearchArgs &a, int32_t y, int q) {
-    return a.rl_off[(int64_t)a.rl_pos[y] * a.n0 + q];
+    return a.rl_v[(int64_t)y * (a.n0 + 1) + q];
 }
 __device__ __forceinline__ int64_t rl_end(const SearchArgs &a, int32_t y, int q) {
-    return a.rl_off[(int64_t)a.rl_pos[y] * a.n0 + q + 1];
+    return a.rl_v[(int64_t)y * (a.n0 + 1) + q + 1];
 }
 
 // Depth-first search for an embedding of plan P's substructure with the
@@ -292,7 +315,7 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
         if (lane == q) img_r = rt->px[i];
         placed |= 1ull << q;
     }
-    rb_r = img_r >= 0 ? a.rl_pos[img_r] * a.n0 : 0;
+    rb_r = img_r >= 0 ? img_r : 0;
     const int base_lvl = npin + rt_np;
     if (!rt && k <= npin) {
         if constexpr (kCount) {
@@ -302,7 +325,9 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
         return kSearchFound;
     }
     const int32_t *__restrict__ rlc = a.rl_col;
-    const int64_t *__restrict__ rlo = a.rl_off;
+    // role-list bounds of vertex x: rlv[x * (n0 + 1) + q .. + q + 1]
+    const int32_t *__restrict__ rlv = a.rl_v;
+    const int64_t stride = a.n0 + 1;
     // role-list positions fit in 32 bits (checked when the lists are built)
     int32_t cur_r = 0, end_r = 0, base_r = 0;
     uint64_t pend_r = 0;
@@ -313,9 +338,9 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
         uint64_t key = ~0ull;
         for (uint64_t mj = placed; mj; mj &= mj - 1) {
             const int j = __builtin_ctzll(mj);
-            const int32_t rbj = read_lane32(rb_r, j);
+            const int64_t rowj = (int64_t)read_lane32(rb_r, j) * stride;
             if ((nbr >> j) & 1ull) {
-                const int64_t len = rlo[rbj + lane + 1] - rlo[rbj + lane];
+                const int64_t len = rlv[rowj + lane + 1] - rlv[rowj + lane];
                 const uint64_t kv = ((uint64_t)len << 12) | ((uint64_t)lane << 6) | (uint64_t)j;
                 if (kv < key) key = kv;
             }
@@ -329,7 +354,7 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
         if (key != ~0ull) {
             bp = (int)((key >> 6) & 63ull);
             bj = (int)(key & 63ull);
-            bb = (int32_t)rlo[read_lane32(rb_r, bj) + bp];
+            bb = rlv[(int64_t)read_lane32(rb_r, bj) * stride + bp];
             be = bb + (int32_t)(key >> 12);
         }
         if (lane == l) {
@@ -453,8 +478,8 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
             }
             for (uint64_t m = back; m; m &= m - 1) {
                 if (!ballot64(ok)) break;
-                const int32_t rbj = read_lane32(rb_r, __builtin_ctzll(m));
-                ok = wave_find(rlc, rlo[rbj + q], rlo[rbj + q + 1], x, ok) >= 0;
+                const int64_t rowj = (int64_t)read_lane32(rb_r, __builtin_ctzll(m)) * stride;
+                ok = wave_find(rlc, rlv[rowj + q], rlv[rowj + q + 1], x, ok) >= 0;
             }
             const uint64_t b = ballot64(ok);
             if constexpr (kCount) {
@@ -481,7 +506,7 @@ __device__ int dfs_search(const SearchArgs &a, const SearchPlan *__restrict__ P,
         if (lane == lvl) pend_r = pend;
         if (lane == q) {
             img_r = x;
-            rb_r = a.rl_pos[x] * a.n0;
+            rb_r = x;
         }
         placed |= 1ull << q;
         if (lvl == k - 1) return kSearchFound;
@@ -541,16 +566,16 @@ __device__ __forceinline__ void certify_pair(const SearchArgs &a, int32_t u, int
 // Record the match (images img_r, with x in place of template vertex q
 // when q >= 0) as the witness of (lane's vertex, lane's role) for every
 // lane with `claim` whose (vertex, role) has none yet.
+// pos_v: the role-list position of the witnessed vertex (loaded by the
+// caller, early, so that its latency overlaps the caller's other loads).
 __device__ void record_witness(const SearchArgs &a, uint64_t vmask, int32_t img_r, bool claim,
-                               int32_t v, int role, int q, int32_t x) {
-    if (claim) {
-        const int64_t idx = (int64_t)a.rl_pos[v] * a.n0 + role;
-        claim = atomicCAS(a.wit_flag + idx, 0u, 1u) == 0u;
-    }
+                               int32_t pos_v, int role, int q, int32_t x) {
+    const int64_t idx = (int64_t)pos_v * a.n0 + role;
+    if (claim) claim = atomicCAS(a.wit_flag + idx, 0u, 1u) == 0u;
     for (uint64_t m = vmask; m; m &= m - 1) {
         const int p = __builtin_ctzll(m);
         const int32_t y = p == q ? x : read_lane32(img_r, p);
-        if (claim) a.wit[((int64_t)a.rl_pos[v] * a.n0 + role) * a.n0 + p] = y;
+        if (claim) a.wit[idx * a.n0 + p] = y;
     }
 }
 
@@ -560,7 +585,10 @@ __device__ void certify_match(const SearchArgs &a, const SearchPlan *__restrict_
                               int32_t img_r, M *cert) {
     const int lane = lane_id();
     if ((P->vmask >> lane) & 1ull) atomic_or_elem<M>(cert, img_r, 1ull << lane);
-    if (a.wit_on) record_witness(a, P->vmask, img_r, (P->vmask >> lane) & 1ull, img_r, lane, -1, 0);
+    if (a.wit_on) {
+        const bool mine = (P->vmask >> lane) & 1ull;
+        record_witness(a, P->vmask, img_r, mine, mine ? a.rl_pos[img_r] : 0, lane, -1, 0);
+    }
     for (int base = 0; base < a.m0; base += kWave) {
         const int i = base + lane;
         int ta = 0, tb = 0;
@@ -608,8 +636,9 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
         // of its image
         int32_t lb_r = 0, le_r = 0;
         if ((nb >> lane) & 1ull) {
-            lb_r = (int32_t)a.rl_off[rb_r + q];
-            le_r = (int32_t)a.rl_off[rb_r + q + 1];
+            const int64_t row = (int64_t)rb_r * (a.n0 + 1);
+            lb_r = a.rl_v[row + q];
+            le_r = a.rl_v[row + q + 1];
         }
         // scan the shortest list; test the others shortest first (the most
         // selective), at most kOrd of them in that order, the rest by index
@@ -662,6 +691,8 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
             const int32_t kk = base + lane;
             const bool in = kk < e;
             const int32_t x = in ? rlc[kk] : -1;
+            // x's list position for its witness, loaded before the tests
+            const int32_t px = (a.wit_on && in) ? a.rl_pos[x] : 0;
             bool ok = in && (!a.check_om || (((uint64_t)om[x] >> q) & 1ull));
             for (uint64_t m = same; m; m &= m - 1) {
                 const int32_t y = read_lane32(img_r, __builtin_ctzll(m));
@@ -687,7 +718,7 @@ __device__ void expand_match(const SearchArgs &a, const SearchPlan *__restrict__
                 ok = wave_find(rlc, y0, y1, x, ok) >= 0;
             }
             ec.valid += (unsigned long long)__popcll(ballot64(ok));
-            if (a.wit_on) record_witness(a, P->vmask, img_r, ok, x, q, q, x);
+            if (a.wit_on) record_witness(a, P->vmask, img_r, ok, px, q, q, x);
             if (ok) {
                 certify_role<M>(a, cert, x, q);
                 // every edge at x is certified through its entry y -> x in

@@ -252,6 +252,7 @@ struct SearchArgs {
     const int32_t *tedges;          // template edges (a, b) pairs
     int32_t m0;
     const int64_t *rl_off;          // role lists: [tasks * n0 + 1] offsets into rl_col
+    const int32_t *rl_v;            // the same bounds by vertex id: [n * (n0 + 1)]
     const int32_t *rl_col;
     const int32_t *rl_ent;          // compacted entry index of each list entry
     const int32_t *rl_pos;          // list position (task index) of each listed vertex
@@ -311,6 +312,10 @@ template <typename M>
 void launch_role_fill(hipStream_t s, const int32_t *tasks, int64_t n_tasks, const int64_t *c_rp,
                       const int32_t *c_col, const M *omega, int n0, const int64_t *rl_off,
                       int32_t *rl_col, int32_t *rl_ent);
+
+// rl_v[tasks[t] * (n0 + 1) + q] = rl_off[t * n0 + q] for q <= n0.
+void launch_role_rows(hipStream_t s, const int32_t *tasks, int64_t n_tasks, int n0,
+                      const int64_t *rl_off, int32_t *rl_v);
 
 // Output edge bits (both entries) from certified compacted entries; one
 // thread per compacted entry (c_own gives each entry's row).
