@@ -1011,7 +1011,7 @@ struct QueryCount {
     ExpandCount ec;
 };
 
-template <typename M>
+template <typename M, bool kExpand = true>
 __device__ bool edge_query(const SearchArgs &a, const SearchPlan *__restrict__ P,
                            const M *__restrict__ om, M *cert, int32_t u, int32_t w,
                            const SplitTask *rt, int64_t t, int plan, QueryCount &qc) {
@@ -1034,7 +1034,7 @@ __device__ bool edge_query(const SearchArgs &a, const SearchPlan *__restrict__ P
         return true;
     }
     certify_match<M>(a, P, img, cert);
-    if (a.expand) {
+    if (kExpand && a.expand) {
         const uint64_t c2 = wall_clock64();
         expand_match<M>(a, P, img, rb, om, cert, qc.ec);
         qc.texp += wall_clock64() - c2;
@@ -1072,8 +1072,12 @@ __device__ __forceinline__ bool edge_certified(const SearchArgs &a, const int64_
     return ((wk >> (k & 63)) | (wq >> (kq & 63))) & 1ull;
 }
 
-template <typename M>
-__global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
+// kExpand false: compiled without the swap scans (the edge-rooted phase
+// runs without them by default), which frees enough registers for five
+// wavefronts per SIMD instead of four.
+template <typename M, bool kExpand>
+__global__ __launch_bounds__(kSearchBlock) __attribute__((amdgpu_waves_per_eu(kExpand ? 1 : 5)))
+void edge_search_kernel(
     const int32_t *eu, const int32_t *ew, const int64_t *e_idx, int64_t n_edges, const M *om,
     M *cert, const int32_t *edge_plan, int32_t n_edge_plans, SearchArgs a) {
     const int lane = lane_id();
@@ -1113,7 +1117,7 @@ __global__ __launch_bounds__(kSearchBlock) void edge_search_kernel(
                 if (edge_certified(a, e_idx, t)) break;
                 const SearchPlan *P = a.plans + edge_plan[i];
                 if (!((cu >> P->pin[0]) & 1ull) || !((cw >> P->pin[1]) & 1ull)) continue;
-                if (edge_query<M>(a, P, om, cert, u, w, nullptr, t, i, qc)) break;
+                if (edge_query<M, kExpand>(a, P, om, cert, u, w, nullptr, t, i, qc)) break;
             }
         }
     }
@@ -1126,8 +1130,12 @@ void launch_edge_search(hipStream_t s, const int32_t *eu, const int32_t *ew,
                         const int32_t *edge_plan_dev, int32_t n_edge_plans, const SearchArgs &a,
                         int grid) {
     if (n_edges <= 0) return;
-    hipLaunchKernelGGL(edge_search_kernel<M>, dim3(grid), dim3(kSearchBlock), 0, s, eu, ew,
-                       e_idx, n_edges, omega, cert, edge_plan_dev, n_edge_plans, a);
+    if (a.expand)
+        hipLaunchKernelGGL((edge_search_kernel<M, true>), dim3(grid), dim3(kSearchBlock), 0, s, eu, ew,
+                           e_idx, n_edges, omega, cert, edge_plan_dev, n_edge_plans, a);
+    else
+        hipLaunchKernelGGL((edge_search_kernel<M, false>), dim3(grid), dim3(kSearchBlock), 0, s, eu, ew,
+                           e_idx, n_edges, omega, cert, edge_plan_dev, n_edge_plans, a);
 }
 
 // Split tasks, one per fetch (each is a long search); skipped once their
