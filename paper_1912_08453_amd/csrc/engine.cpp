@@ -745,7 +745,7 @@ struct Pruner {
         w->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
         w->expseen.ensure(sizeof(uint64_t) << exp_log2);
         uint64_t *c_cert = w->ccert.as<uint64_t>();
-        role_lists();
+        if (!rl_valid) role_lists();
         launch_fill_u64(s, c_cert, cwords, 0ull);
         launch_fill_u64(s, w->expseen.as<uint64_t>(), 1ll << exp_log2, 0ull);
         // roles and edges known to be in the complete set count as
@@ -1135,7 +1135,11 @@ struct Pruner {
                 launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, lcc, edge_out);
             st.result_vertices = nA;
         } else {
-            if (nA > 0) compact(true);
+            // a fresh candidate subgraph only when the active set has shrunk
+            // by a quarter since the last one (any superset of the edges
+            // between active vertices serves the final search; otherwise the
+            // current one and its role lists are reused)
+            if (nA > 0 && nA * 4 < nA_compact * 3) compact(true);
             exact(role_out, edge_out);
         }
         st.done_mask = done_mask;
