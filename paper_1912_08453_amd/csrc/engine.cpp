@@ -626,6 +626,7 @@ struct Pruner {
         cbuf = nb;
         nA_compact = nA;
         rl_valid = false;
+        rl_graph_ok = false;
         st.candidate_entries = c_m;
         t.stop(st.ms_compact);
     }
@@ -684,6 +685,9 @@ struct Pruner {
     // one reuse them.
     int64_t rl_total = 0;
     bool rl_valid = false;
+    int64_t nA_lists = 0;       // tasks of the current lists (their positions)
+    bool rl_graph_ok = false;   // the lists index the current candidate subgraph
+    bool rl_stale = false;      // they may hold roles lost since: searches test omega
     void role_lists() {
         const int64_t nn = std::max<int64_t>(nA, 1) * T.n0;
         w->rlcnt.ensure(sizeof(int64_t) * (size_t)(nn + 1));
@@ -707,15 +711,34 @@ struct Pruner {
         w->rlv.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c->n, 1) * (size_t)(T.n0 + 1));
         launch_role_rows(s, A, nA, T.n0, w->rloff.as<int64_t>(), w->rlv.as<int32_t>());
         rl_valid = true;
+        rl_stale = false;
+        rl_graph_ok = true;
+        nA_lists = nA;
+    }
+
+    // Lists for the next search: the current ones while valid; after role
+    // sets shrank, still the current ones (a superset: the searches then
+    // test every candidate's role set) if they index the current subgraph
+    // and the active set has lost less than a quarter since they were
+    // built; otherwise new ones.
+    void ensure_lists() {
+        if (rl_valid) return;
+        if (rl_graph_ok && nA * 4 >= nA_lists * 3) {
+            rl_valid = true;
+            rl_stale = true;
+            return;
+        }
+        role_lists();
     }
 
     // One non-local constraint (snapshot semantics); returns the vertices
     // changed, with the active list already updated.
     int32_t nlcc(const Constraint &k) {
         Span t(tl, s);
-        if (!rl_valid) role_lists();
+        ensure_lists();
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         SearchArgs a = search_args(0, k.heads, k.plan_of_head, nullptr);
+        a.check_om = rl_stale ? 1 : 0;
         launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
         PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
         launch_apply<M>(s, A, nA, om, sat, k.heads, ctr + C_CHANGED);
@@ -745,7 +768,7 @@ struct Pruner {
         w->ccert.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(cwords, 1));
         w->expseen.ensure(sizeof(uint64_t) << exp_log2);
         uint64_t *c_cert = w->ccert.as<uint64_t>();
-        if (!rl_valid) role_lists();
+        ensure_lists();
         launch_fill_u64(s, c_cert, cwords, 0ull);
         launch_fill_u64(s, w->expseen.as<uint64_t>(), 1ll << exp_log2, 0ull);
         // roles and edges known to be in the complete set count as
@@ -756,16 +779,18 @@ struct Pruner {
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
         SearchArgs a = search_args(1, all, T.vertex_plan, edge_out);
+        a.check_om = rl_stale ? 1 : 0;
         a.c_cert = c_cert;
         a.exp_seen = w->expseen.as<unsigned long long>();
         a.exp_log2 = exp_log2;
         // witnesses of certified (vertex, role) pairs, for single-swap
         // certification of candidate edges (small templates only)
-        const int64_t wit_words = nA * (int64_t)T.n0 * T.n0;
+        // (indexed by list position: nA_lists slots)
+        const int64_t wit_words = nA_lists * (int64_t)T.n0 * T.n0;
         if (c->witness && T.n0 <= 16 && nA > 0 && wit_words <= (int64_t)1 << 29) {
             w->wit.ensure(sizeof(int32_t) * (size_t)wit_words);
-            w->witflag.ensure(sizeof(uint32_t) * (size_t)(nA * T.n0));
-            launch_fill_i32(s, w->witflag.as<int32_t>(), nA * T.n0, 0);
+            w->witflag.ensure(sizeof(uint32_t) * (size_t)(nA_lists * T.n0));
+            launch_fill_i32(s, w->witflag.as<int32_t>(), nA_lists * T.n0, 0);
             a.wit = w->wit.as<int32_t>();
             a.wit_flag = w->witflag.as<uint32_t>();
             a.wit_on = 1;
