@@ -75,7 +75,8 @@ def check_all(pmmod, ctx, g, ts, refs, what):
 
 
 JOIN_ON = [{"witness": 1}, {"witness": 1, "expand_edges": 0},
-           {"witness": 1, "expand": 0, "search_grid": 3}]
+           {"witness": 1, "expand": 0, "search_grid": 3},
+           {"witness": 1, "relist": 0, "expand_max": -1}]
 
 
 @pytest.mark.parametrize("settings", JOIN_ON)
