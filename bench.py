@@ -51,7 +51,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="theta8-s26", choices=["theta8-s26", "tri-square-s22"],
                     help="theta8-s26 (default): the scale-26 batch of a base template and its "
                          "relaxations; tri-square-s22: one template at scale 22")
