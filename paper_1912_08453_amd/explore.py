@@ -125,7 +125,11 @@ class ExploreResult:
     level: int                       # first level with a match, -1 if none
     variants: List[List[Tuple[int, int]]] = field(default_factory=list)
     matched: List[bool] = field(default_factory=list)
-    role_union: object = None        # int64 tensor [n]: OR of the role masks
+    # int64 tensor [n]: OR of the role masks of the matched variants, one
+    # representative per label-preserving isomorphism class; its bits are
+    # that representative's template vertices, so read it as an indicator of
+    # the vertices in some match (nonzero) rather than per role
+    role_union: object = None
     edge_union: object = None        # int64 tensor [ceil(m/64)]: OR of the edge bits
     levels: List[dict] = field(default_factory=list)   # per level: variants, matched, ms
 
