@@ -14,7 +14,13 @@
  * non-local constraint (cycle, path and template-driven-search constraints
  * generated per the constraint-generation table) run non-local constraint
  * checking (NLCC) followed by LCC when anything changed, and finish with a
- * full-template search that certifies every surviving role and edge.
+ * full-template search that certifies every surviving role and edge.  For
+ * an acyclic template whose labels are unique except for one pair of
+ * vertices the finish is exact without searches: at the LCC fixpoint a
+ * role is in a match iff the homomorphisms of the template path between the
+ * pair through it can put the pair on two different vertices, decided by
+ * sweeps that carry the smallest and largest reachable end vertex along the
+ * path (setting "tree_exact").
  *
  * Conventions
  *  - All functions return PM_OK (0) or a negative PM_ERR_* code; the message
@@ -42,7 +48,9 @@
  *    its unexplored candidate ranges on (default 8192; 0 never),
  *    PM_EDGE_TAIL=k the trailing edge tasks dealt singly (default 0),
  *    PM_EXPAND_TABLE_LOG2=t the swap-scan table size (default 22),
- *    PM_READ_FIRST=1 reads certificate words before setting them.  These seed
+ *    PM_READ_FIRST=1 reads certificate words before setting them,
+ *    PM_TREE_EXACT=0 runs the search-based finish for one-repeated-pair
+ *    trees too.  These seed
  *    the settings of pm_set_param.  Read by pm_load_graph:
  *    PM_NO_COUNT_INDEX=1 skips the neighbour-label count index (the first
  *    LCC sweep then gathers over the CSR).
@@ -169,7 +177,9 @@ typedef struct {
                                       final search                            */
     int32_t batch_streams;         /* count > 1: prune up to this many
                                       templates concurrently, each on its own
-                                      stream and scratch (0/1: one at a time)  */
+                                      stream and scratch (0/1: one at a time).
+                                      Templates are dealt longest-first by
+                                      independent cycles, edges, vertices    */
     float learned_min_score;       /* PM_ORDER_LEARNED with learned_stop: end
                                       the constraint loop when the best
                                       remaining score is below this (the
@@ -388,10 +398,17 @@ int pm_prune(pm_ctx *ctx, int32_t first_id, int32_t count, uint64_t *role_mask,
      "expand_edges"  1/0   swap scans also after matches found by edge-rooted
                            searches (1; "expand" 0 turns off both)
      "witness"       1/0   certify candidate edges by witness swaps (0)
+     "tree_exact"    1/0   finish acyclic templates with one repeated-label
+                           pair by path sweeps instead of searches (1)
      "relist"        1/0   edge searches on role lists of the exact roles (1)
      "edge_chunk"    k     edge tasks a wavefront takes at once (16)
      "edge_stripes"  s     stripes the edge task list is dealt in (64)
      "search_grid"   b     blocks of the persistent search kernels (8 per CU)
+     "search_grid_solo" b  blocks shared by the searches that run at once:
+                           a search launched while k workers of a batch
+                           search (itself included) takes max(search_grid,
+                           b / k) blocks, so one searching alone or at the
+                           tail of a batch can fill the GPU; 0: off (0)
      "split_budget"  s     steps after which an edge-rooted search hands its
                            unexplored candidate ranges on to other
                            wavefronts; 0: never (8192; four times more in

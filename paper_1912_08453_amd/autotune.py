@@ -21,7 +21,9 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 def default_space(ctx) -> Dict[str, List[int]]:
     """Candidate values per setting; the search grid is offered at half,
-    one and two times its default (which scales with the compute units)."""
+    one and two times its current value (by default 8 blocks per compute
+    unit), the grid shared by concurrent searches off or at two and four
+    times it."""
     g = ctx.get_param("search_grid")
     return {
         "edge_chunk": [4, 8, 16, 32, 64],
@@ -32,6 +34,7 @@ def default_space(ctx) -> Dict[str, List[int]]:
         "witness": [0, 1],
         "relist": [0, 1],
         "search_grid": sorted({max(1, g // 2), g, 2 * g}),
+        "search_grid_solo": [0, 2 * g, 4 * g],
         "split_budget": [0, 2048, 8192, 32768],
         "edge_tail": [0, 16384, 65536],
         "read_first": [0, 1],

@@ -179,13 +179,13 @@ struct Scratch {
         coff2, cown2,
         segcnt, segscan, segbits, scan_scratch;
     DevBuf eu, ew, eidx, edge_plan_ids, ccert, expseen, wit, witflag, rlcnt, rloff, rlpos, rlcol, rlent, rlscan,
-        rlv, actbits, ord, afilt, split[2];
+        rlv, actbits, ord, afilt, split[2], tsum;
     std::vector<DevBuf *> all() {
         return {&omega, &sat, &alist[0], &alist[1], &bins, &counters, &hub, &cdeg, &crp,
                 &ccol, &coff, &cown, &crp2, &ccol2, &coff2, &cown2, &segcnt, &segscan, &segbits,
                 &scan_scratch, &eu, &ew, &eidx, &edge_plan_ids, &ccert, &expseen, &wit, &witflag,
                 &rlcnt, &rloff, &rlpos, &rlcol, &rlent, &rlscan, &rlv, &actbits, &ord,
-                &afilt, &split[0], &split[1]};
+                &afilt, &split[0], &split[1], &tsum};
     }
     // Draw every buffer from [base, base + cap) from now on (library-owned
     // buffers are freed first), or, with base == nullptr, return to
@@ -265,8 +265,14 @@ struct pm_ctx {
     // per-worker scratch; worker 0 runs on the context stream
     std::vector<std::unique_ptr<pm::Scratch>> scratch;
     int grid_search = 2048;
+    // blocks shared by the searches that run at once (0: every search
+    // launch takes grid_search); `searching` counts the workers whose last
+    // search launch the host has not yet seen finish
+    int grid_search_solo = 0;
+    std::atomic<int> searching{0};
     int expand = 1;
     int expand_edges = 1;   // swap scans after edge-rooted finds too
+    int tree_exact = 1;     // final step of one-repeated-pair trees by path sweeps
     int64_t expand_max = 4096;
     int witness = 0;
     int edge_chunk = 16;
@@ -293,6 +299,25 @@ struct pm_ctx {
 namespace {
 
 void set_device(pm_ctx *c) { PM_HIP(hipSetDevice(c->device)); }
+
+// Blocks for one search launch, held from the launch until the host has
+// seen the search finish.  A search launched while k workers of a batch
+// search (itself included) takes search_grid_solo / k blocks, never fewer
+// than search_grid: a search that runs alone, or at the tail of a batch,
+// fills the GPU, and concurrent ones split it.  The search kernels pull
+// their tasks from a counter, so any grid gives the same result.
+struct SearchShare {
+    pm_ctx *c;
+    int grid;
+    explicit SearchShare(pm_ctx *cc) : c(cc) {
+        const int k = ++c->searching;
+        grid = c->grid_search;
+        if (c->grid_search_solo > grid) grid = std::max(grid, c->grid_search_solo / k);
+    }
+    ~SearchShare() { --c->searching; }
+    SearchShare(const SearchShare &) = delete;
+    SearchShare &operator=(const SearchShare &) = delete;
+};
 
 template <typename T>
 void d2h(hipStream_t s, T *dst, const T *src, size_t count) {
@@ -739,7 +764,8 @@ struct Pruner {
         PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
         SearchArgs a = search_args(0, k.heads, k.plan_of_head, nullptr);
         a.check_om = rl_stale ? 1 : 0;
-        launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
+        SearchShare share(c);   // until read_control below
+        launch_vertex_search<M>(s, A, nA, om, sat, a, share.grid);
         PM_HIP(hipMemsetAsync(ctr + C_CHANGED, 0, sizeof(int32_t), s));
         launch_apply<M>(s, A, nA, om, sat, k.heads, ctr + C_CHANGED);
         // the next active list comes back with the change count in one
@@ -797,8 +823,11 @@ struct Pruner {
         }
         a.qstats = qstats;
         a.expand = a.aggregate ? c->expand : 0;
-        launch_vertex_search<M>(s, A, nA, om, sat, a, c->grid_search);
-        d2h(s, &q0, queries, 1);
+        {
+            SearchShare share(c);
+            launch_vertex_search<M>(s, A, nA, om, sat, a, share.grid);
+            d2h(s, &q0, queries, 1);
+        }
         // edge part over vertices with certified roles
         std::swap(om, sat);   // collect() reads `om`: use the certified sets
         collect(false);
@@ -843,8 +872,9 @@ struct Pruner {
             PM_HIP(hipMemsetAsync(queries, 0, sizeof(unsigned long long), s));
             // the dealing counter is 32-bit: it must stay below 2^31 after
             // every chunk and every wave's final fetch
+            SearchShare share(c);   // until the split rounds are done
             int64_t chunk = c->edge_chunk;
-            const int64_t waves = (int64_t)c->grid_search * 4;
+            const int64_t waves = (int64_t)share.grid * 4;
             const int64_t tail = std::min<int64_t>(c->edge_tail, std::min<int64_t>(ne, 1 << 24));
             while ((ne + chunk - 1) / chunk + tail + c->edge_stripes + waves >= INT32_MAX)
                 chunk *= 2;
@@ -866,7 +896,7 @@ struct Pruner {
             launch_edge_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                   w->eidx.as<int64_t>(), ne, sat, sat,
                                   w->edge_plan_ids.as<int32_t>(), (int32_t)T.edge_plans.size(),
-                                  a, c->grid_search);
+                                  a, share.grid);
             if (c->split_budget > 0) {
                 int cur = 0;
                 int64_t rounds = 0;
@@ -888,7 +918,7 @@ struct Pruner {
                     PM_HIP(hipMemsetAsync(ctr + C_TASK, 0, sizeof(int32_t), s));
                     launch_split_search<M>(s, in, nt, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                            w->eidx.as<int64_t>(), sat, sat,
-                                           w->edge_plan_ids.as<int32_t>(), a, c->grid_search);
+                                           w->edge_plan_ids.as<int32_t>(), a, share.grid);
                 }
                 a.split_budget = 0;
             }
@@ -1106,6 +1136,29 @@ struct Pruner {
         return counted;
     }
 
+    // Final step of an acyclic template with one repeated-label pair: the
+    // complete set from sweeps along the path between the pair over the
+    // LCC fixpoint (launch_tree_exact), no searches.  The list positions
+    // are overwritten, so the role lists are no longer valid.
+    void tree_final(uint64_t *role_out, uint64_t *edge_out) {
+        Span t(tl, s);
+        const int64_t n = c->n;
+        const TreePlan &tp = T.tree;
+        w->rlpos.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+        w->tsum.ensure(sizeof(int2) * 2 * (size_t)(tp.k + 1) * (size_t)std::max<int64_t>(nA, 1));
+        rl_valid = false;
+        rl_graph_ok = false;
+        PM_HIP(hipMemsetAsync(sat, 0, sizeof(M) * (size_t)n, s));
+        launch_tree_exact<M>(s, A, nA, om, c_m, c_own, c_col, c_off, c->rp, tp,
+                             w->rlpos.as<int32_t>(), w->tsum.as<int2>(), sat, edge_out);
+        launch_widen<M>(s, n, sat, role_out);
+        std::swap(om, sat);   // collect() reads `om`: count the vertices kept
+        collect(false);
+        std::swap(om, sat);
+        st.result_vertices = nA;
+        t.stop(st.ms_exact);
+    }
+
     // Whole prune.  edge_out may be null (state export: no edge output).
     void run(uint64_t *role_out, uint64_t *edge_out) {
         Span total(tl, s);
@@ -1159,6 +1212,9 @@ struct Pruner {
             if (T.n0 > 1 && edge_out)
                 launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, lcc, edge_out);
             st.result_vertices = nA;
+        } else if (T.tree_pair && c->tree_exact) {
+            if (nA > 0 && nA * 4 < nA_compact * 3) compact(true);
+            tree_final(role_out, edge_out);
         } else {
             // a fresh candidate subgraph only when the active set has shrunk
             // by a quarter since the last one (any superset of the edges
@@ -1242,10 +1298,11 @@ struct Pruner {
                     a.split_n = ctr + C_SPLIT;
                     a.split_cap = split_cap;
                 }
+                SearchShare share(c);
                 launch_count_search<M>(s, w->eu.as<int32_t>(), w->ew.as<int32_t>(), ne, om,
                                        w->edge_plan_ids.as<int32_t>(), a, maps_out,
                                        maps_out ? cap : 0, wrt, tot, limit, ctr + C_STOP,
-                                       c->grid_search);
+                                       share.grid);
                 if (c->split_budget > 0) {
                     int cur = 0;
                     int64_t rounds = 0;
@@ -1262,7 +1319,7 @@ struct Pruner {
                         launch_count_split<M>(s, in, nt, w->eu.as<int32_t>(), w->ew.as<int32_t>(),
                                               om, w->edge_plan_ids.as<int32_t>(), a, maps_out,
                                               maps_out ? cap : 0, wrt, tot, limit, ctr + C_STOP,
-                                              c->grid_search);
+                                              share.grid);
                     }
                 }
             }
@@ -1500,6 +1557,7 @@ size_t workspace_bound(const pm_ctx *c, const CompiledTemplate &T, int exp_log2,
         add((int64_t)sizeof(SplitTask) * split_cap);
         add((int64_t)sizeof(SplitTask) * split_cap);
     }
+    if (T.tree_pair) add(16 * n0 * nt);                       // path summaries
     return total;
 }
 
@@ -1830,6 +1888,8 @@ int pm_create(pm_ctx **out, int device, void *hip_stream) {
             if (ex) c->expand = atoi(ex);
             const char *ee = getenv("PM_EXPAND_EDGES");
             if (ee) c->expand_edges = atoi(ee) ? 1 : 0;
+            const char *te = getenv("PM_TREE_EXACT");
+            if (te) c->tree_exact = atoi(te) ? 1 : 0;
             const char *em = getenv("PM_EXPAND_MAX");
             if (em) c->expand_max = atoll(em);
             const char *wn = getenv("PM_WITNESS");
@@ -2239,11 +2299,14 @@ int pm_set_param(pm_ctx *c, const char *name, int64_t value) {
         if (k == "expand") c->expand = value ? 1 : 0;
         else if (k == "expand_max") c->expand_max = value < 0 ? INT64_MAX : value;
         else if (k == "expand_edges") c->expand_edges = value ? 1 : 0;
+        else if (k == "tree_exact") c->tree_exact = value ? 1 : 0;
         else if (k == "witness") c->witness = value ? 1 : 0;
         else if (k == "relist") c->relist = value ? 1 : 0;
         else if (k == "edge_chunk" && value >= 1 && value <= (1 << 16)) c->edge_chunk = (int)value;
         else if (k == "edge_stripes" && value >= 1 && value <= (1 << 16)) c->edge_stripes = (int)value;
         else if (k == "search_grid" && value >= 1 && value <= (1 << 16)) c->grid_search = (int)value;
+        else if (k == "search_grid_solo" && value >= 0 && value <= (1 << 16))
+            c->grid_search_solo = (int)value;
         else if (k == "split_budget" && value >= 0) c->split_budget = value;
         else if (k == "edge_tail" && value >= 0) c->edge_tail = value;
         else if (k == "expand_table_log2" && value >= 10 && value <= 30) c->exp_log2 = (int)value;
@@ -2263,11 +2326,13 @@ int pm_get_param(pm_ctx *c, const char *name, int64_t *value) {
         if (k == "expand") *value = c->expand;
         else if (k == "expand_max") *value = c->expand_max == INT64_MAX ? -1 : c->expand_max;
         else if (k == "expand_edges") *value = c->expand_edges;
+        else if (k == "tree_exact") *value = c->tree_exact;
         else if (k == "witness") *value = c->witness;
         else if (k == "relist") *value = c->relist;
         else if (k == "edge_chunk") *value = c->edge_chunk;
         else if (k == "edge_stripes") *value = c->edge_stripes;
         else if (k == "search_grid") *value = c->grid_search;
+        else if (k == "search_grid_solo") *value = c->grid_search_solo;
         else if (k == "split_budget") *value = c->split_budget;
         else if (k == "edge_tail") *value = c->edge_tail;
         else if (k == "expand_table_log2") *value = c->exp_log2;

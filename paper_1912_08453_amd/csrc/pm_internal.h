@@ -39,6 +39,20 @@ struct LccTable {
     int32_t cneed[kMaxCount];       // |cmask| >= 2
 };
 
+// Acyclic template whose labels are unique except for one pair a, b: the
+// path p_0 = a .. p_k = b between them and, off the path, each vertex's
+// neighbour towards it.  Passed by value as a kernel argument.
+struct TreePlan {
+    int32_t k;                      // path length in edges (>= 1)
+    int32_t depth;                  // largest distance of a vertex from the path
+    int32_t m0;
+    int8_t path[kMaxK];             // p_i
+    int8_t pos[kMaxK];              // i for q = p_i, -1 off the path
+    int8_t par[kMaxK];              // off the path: neighbour towards it; -1 on it
+    int8_t ea[kMaxK], eb[kMaxK];    // template edges
+    uint64_t depmask[kMaxK + 1];    // vertices at distance d from the path
+};
+
 // One search plan: a substructure of G0 (vertex set and its own edges) with
 // one or two template vertices pinned (the head, or both ends of an edge).
 // The search order is chosen per partial match at run time.
@@ -133,6 +147,10 @@ struct CompiledTemplate {
     std::vector<int32_t> need_off, need_lab, need_min;
     std::vector<uint64_t> need_labmask;       // labels < 64 that q needs
     int32_t *d_need = nullptr;                // need_off | need_lab | need_min
+    // acyclic with exactly one pair of vertices sharing a label: the final
+    // step can run as sweeps along the path between the pair (tree)
+    bool tree_pair = false;
+    TreePlan tree{};
 };
 
 // Template compiler (host).  Returns an empty string on success, otherwise
@@ -367,6 +385,16 @@ void launch_active_edges(hipStream_t s, const int32_t *tasks, int64_t n_tasks,
 
 template <typename M>
 void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst);
+
+// Final step of a template with a TreePlan (exact, no searches): sat
+// (zeroed by the caller) receives the roles in some match, edge_bits (if
+// not null) the entries that carry a template edge of one.  pos: int32[n]
+// (overwritten: active-list positions); sum: int2[2 * (k + 1) * nA].
+template <typename M>
+void launch_tree_exact(hipStream_t s, const int32_t *A, int64_t nA, const M *om,
+                       int64_t c_m, const int32_t *c_own, const int32_t *c_col,
+                       const int32_t *c_off, const int64_t *rp, const TreePlan &tp,
+                       int32_t *pos, int2 *sum, M *sat, uint64_t *edge_bits);
 
 // Neighbour-label count index of a graph with uint8 labels below nlab:
 // cnt[L * np + v] = min(255, neighbours of v with label L), np = n rounded

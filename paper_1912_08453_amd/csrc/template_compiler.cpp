@@ -243,6 +243,58 @@ std::string compile_template(int n0, int m0, const uint16_t *labels, const uint3
     for (int q = 0; q < n0; ++q) lab_count[T.labels[q]]++;
     bool unique = (int)lab_count.size() == n0;
     T.acyclic_unique = unique && m0 == n0 - 1;
+    // acyclic, one label on two vertices a, b, every other label on one:
+    // the path a .. b and, off it, every vertex's neighbour towards it
+    T.tree_pair = false;
+    if (m0 == n0 - 1 && n0 >= 2 && (int)lab_count.size() == n0 - 1) {
+        int a = -1, b = -1;
+        for (int q = 0; q < n0 && b < 0; ++q)
+            for (int r = q + 1; r < n0; ++r)
+                if (T.labels[q] == T.labels[r]) { a = q; b = r; break; }
+        auto adj = adjacency(n0, T.edges);
+        std::vector<int> from(n0, -1);
+        std::deque<int> dq{a};
+        from[a] = a;
+        while (!dq.empty()) {
+            int x = dq.front();
+            dq.pop_front();
+            for (int y : adj[x])
+                if (from[y] < 0) { from[y] = x; dq.push_back(y); }
+        }
+        std::vector<int> path;
+        for (int x = b; x != a; x = from[x]) path.push_back(x);
+        path.push_back(a);
+        std::reverse(path.begin(), path.end());
+        TreePlan &tp = T.tree;
+        tp = TreePlan{};
+        tp.k = (int)path.size() - 1;
+        tp.m0 = m0;
+        for (int q = 0; q < n0; ++q) { tp.pos[q] = -1; tp.par[q] = -1; }
+        for (int i = 0; i <= tp.k; ++i) {
+            tp.path[i] = (int8_t)path[(size_t)i];
+            tp.pos[path[(size_t)i]] = (int8_t)i;
+        }
+        // distances from the path (breadth first from all its vertices)
+        std::vector<int> dist(n0, -1);
+        for (int x : path) { dist[x] = 0; dq.push_back(x); }
+        while (!dq.empty()) {
+            int x = dq.front();
+            dq.pop_front();
+            for (int y : adj[x])
+                if (dist[y] < 0) {
+                    dist[y] = dist[x] + 1;
+                    tp.par[y] = (int8_t)x;
+                    tp.depmask[dist[y]] |= 1ull << y;
+                    tp.depth = std::max(tp.depth, dist[y]);
+                    dq.push_back(y);
+                }
+        }
+        for (int j = 0; j < m0; ++j) {
+            tp.ea[j] = (int8_t)T.edges[(size_t)j].first;
+            tp.eb[j] = (int8_t)T.edges[(size_t)j].second;
+        }
+        T.tree_pair = true;
+    }
     for (int q = 0; q < n0; ++q) {
         T.label_mask_of[q] = 0;
         for (int r = 0; r < n0; ++r)

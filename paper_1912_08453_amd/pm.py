@@ -486,8 +486,9 @@ class PM:
         return res
 
     # ------------------------------------------------------------ tuning
-    TUNING = ("expand", "expand_edges", "expand_max", "witness", "relist", "edge_chunk", "edge_stripes",
-              "search_grid", "split_budget", "edge_tail", "expand_table_log2",
+    TUNING = ("expand", "expand_edges", "expand_max", "witness", "tree_exact", "relist", "edge_chunk",
+              "edge_stripes",
+              "search_grid", "search_grid_solo", "split_budget", "edge_tail", "expand_table_log2",
               "split_capacity", "read_first", "lcc_bin_small", "lcc_bin_mid")
 
     def set_param(self, name: str, value: int) -> None:

@@ -66,12 +66,14 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
     assert p["expand"] == 1 and p["witness"] == 0 and p["relist"] == 1
     assert p["edge_chunk"] == 16 and p["edge_stripes"] == 64 and p["expand_max"] == 4096
     assert p["search_grid"] >= 256 and p["split_budget"] == 8192
+    assert p["search_grid_solo"] == 0
     for k, v in (("edge_chunk", 3), ("edge_stripes", 5), ("expand_max", -1), ("search_grid", 9),
-                 ("witness", 1), ("relist", 0), ("expand", 0)):
+                 ("witness", 1), ("relist", 0), ("expand", 0), ("search_grid_solo", 5000)):
         ctx.set_param(k, v)
         assert ctx.get_param(k) == v
     assert p["lcc_bin_small"] == 8 and p["lcc_bin_mid"] == 64
     for k, v in (("edge_chunk", 0), ("edge_stripes", 1 << 17), ("search_grid", 0),
+                 ("search_grid_solo", -1), ("search_grid_solo", 1 << 17),
                  ("split_budget", -1), ("split_capacity", 0), ("expand_table_log2", 31),
                  ("lcc_bin_mid", 4097), ("lcc_bin_small", 65), ("lcc_bin_small", -1),
                  ("nope", 1)):
@@ -90,7 +92,8 @@ def test_params_round_trip_and_refusals(pmmod, torch_dev, case):
     {"split_budget": 1, "split_capacity": 20}, {"expand_table_log2": 10},
     {"read_first": 1, "witness": 1},
     {"lcc_bin_small": 0, "lcc_bin_mid": 0}, {"lcc_bin_mid": 4096, "lcc_bin_small": 4096},
-    {"lcc_bin_small": 1, "lcc_bin_mid": 2}])
+    {"lcc_bin_small": 1, "lcc_bin_mid": 2},
+    {"search_grid": 2, "search_grid_solo": 8192}, {"search_grid": 3, "search_grid_solo": 5}])
 def test_extreme_settings_keep_the_complete_set(pmmod, torch_dev, case, setting):
     g, ts, refs = case
     ctx, tid = _ctx(pmmod, torch_dev, g, ts)

@@ -80,7 +80,8 @@ def test_size_and_parity_of_relaxation_batches(pmmod, torch_dev, relax_case):
     want = pair_entries(g, ts)
     log(f"scale {scale}: pair subgraph {info['pair_entries']} of {g.m} entries, {ms:.2f} ms")
     assert info["pair_entries"] == want and info["ms_pair_index"] > 0
-    for settings in ({}, {"witness": 1, "expand_edges": 0, "relist": 0}):
+    for settings in ({}, {"witness": 1, "expand_edges": 0, "relist": 0},
+                     {"search_grid": 64, "search_grid_solo": 2048}):
         for k, v in settings.items():
             ctx.set_param(k, v)
         T = len(ts)

@@ -245,7 +245,8 @@ def test_error_codes(pmmod, torch_dev):
 
 def test_concurrent_batch_equals_one_at_a_time(pmmod, torch_dev):
     """Batched prune (templates on concurrent streams with separate scratch)
-    gives the same masks as one template at a time, and as the oracle."""
+    gives the same masks as one template at a time, and as the oracle, also
+    with the searches of concurrent templates sharing one grid."""
     rp, col = I.rmat_csr(14, seed=6)
     g = I.Graph(rp, col, I.labels_log2deg(rp))
     ts = I.templates_batch(g, 4, count=24)
@@ -255,6 +256,11 @@ def test_concurrent_batch_equals_one_at_a_time(pmmod, torch_dev):
     r1, e1 = pmmod.to_u64(r1), pmmod.to_u64(e1)
     r4, e4, _ = ctx.prune(tid, count=len(ts), batch_streams=4)
     assert np.array_equal(pmmod.to_u64(r4), r1) and np.array_equal(pmmod.to_u64(e4), e1)
+    # searches sharing a grid that a lone one fills
+    ctx.set_param("search_grid", 16)
+    ctx.set_param("search_grid_solo", 4096)
+    r5, e5, _ = ctx.prune(tid, count=len(ts), batch_streams=3)
+    assert np.array_equal(pmmod.to_u64(r5), r1) and np.array_equal(pmmod.to_u64(e5), e1)
     for i in (0, 7, 13, 23):
         ref = oracle.prune(g.row_ptr, g.col, g.labels, ts[i].labels, ts[i].edges)
         assert np.array_equal(r1[i], ref.role_mask) and np.array_equal(e1[i], ref.edge_bits)
