@@ -1204,7 +1204,19 @@ struct Pruner {
         } else {
             for (int i = 0; i < K; ++i) order.push_back(i);
         }
-        if (!candidate) constraint_loop(order, learned, stop_after);
+        // An acyclic template with one repeated-label pair a, b has at most
+        // one non-local constraint, the path constraint between a and b
+        // (heads at both ends; none when they are under three hops apart); the
+        // path sweeps of tree_final are that token walk with the tokens at a
+        // vertex aggregated to the smallest and largest origin, run at the
+        // LCC fixpoint, and they give the complete set directly (a tree at
+        // the fixpoint leaves injectivity as the only open condition).  So a
+        // full prune of such a template goes from the LCC fixpoint straight
+        // to the sweeps; a run that stops after some constraints (state
+        // export, ablations) keeps the search-based loop.
+        const bool swept = T.tree_pair && c->tree_exact && stop_after < 0 && !candidate &&
+                           edge_out && !(opt && opt->limit_checks);
+        if (!candidate && !swept) constraint_loop(order, learned, stop_after);
         if (candidate || stop_after >= 0 || T.acyclic_unique || T.n0 == 1 || !edge_out) {
             // omega and its implied edge state (exact for acyclic unique-label
             // templates: LCC alone suffices)

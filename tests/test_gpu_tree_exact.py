@@ -5,7 +5,8 @@ between the pair can only close on one vertex (LCC keeps those roles, no
 match uses them), on tiny random graphs over few labels with random trees
 of 2-8 vertices, on trees extracted from R-MAT graphs, and on the theta8
 relaxations (19 of 28 are trees), with the setting on and off; with it on
-no search runs for such templates."""
+no search runs for such templates, neither a non-local check nor a final
+search.  A prune that stops after some constraints still checks them."""
 import sys
 
 import numpy as np
@@ -78,6 +79,9 @@ def check(pmmod, torch_dev, g, ts, what, tree_exact_values=(1, 0)):
             if te and one_pair_tree(t):
                 assert st["vertex_queries"] == 0 and st["edge_queries"] == 0, \
                     f"{tag}: a search ran"
+                # the path sweeps decide the path constraint: no search-based
+                # non-local check runs either
+                assert st["constraints"] == 0, f"{tag}: a non-local check ran"
     ctx.close()
     return refs
 
