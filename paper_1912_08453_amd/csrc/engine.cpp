@@ -258,6 +258,12 @@ struct pm_ctx {
     int64_t pair_m = -1;
     int pair_nl = 0;
     std::vector<uint8_t> pair_adj;
+    // count index of the label-pair subgraph (same layout as lab_cnt; for
+    // a label pair of the subgraph its counts are those of the graph);
+    // pair_cnt_nlab = 0: none
+    DevBuf pair_cnt;
+    int pair_cnt_nlab = 0;
+    int64_t pair_cnt_stride = 0;
     double ms_pair_index = 0.0;
     int64_t hub_cap = 0, seg_cap = 0;
     // templates
@@ -1091,17 +1097,24 @@ struct Pruner {
     // Returns true when the first sweep has been applied.
     bool init_state_and_first_sweep(bool allow_counted) {
         const int64_t n = c->n;
-        const bool counted = allow_counted && c->nlab > 0 && T.n0 > 1 && !candidate;
+        // the counts of the label-pair subgraph when it covers the template
+        // (the sweep reads a vertex's counts only for labels of template
+        // neighbours of its roles, pairs the subgraph keeps whole), else
+        // the count index of the graph
+        const bool from_pairs = c->pair_cnt_nlab > 0 && pairs_cover();
+        const int cnl = from_pairs ? c->pair_cnt_nlab : c->nlab;
+        const bool counted = allow_counted && cnl > 0 && T.n0 > 1 && !candidate;
         if (counted) {
             // first LCC sweep from the neighbour-label count index (it also
             // initialises omega)
             Span t(tl, s);
             Span k(tl, s);
             const int32_t *nd = T.d_need;
-            launch_first_sweep_counts<M>(s, n, c->cnt_stride, (const uint8_t *)c->labels, T.d_init_lut,
-                                         (int)std::min<int64_t>(T.init_lut_len, 256),
-                                         c->lab_cnt.as<uint8_t>(), c->nlab, nd, nd + T.n0 + 1,
-                                         nd + T.n0 + 1 + T.need_lab.size(), T.n0, om);
+            launch_first_sweep_counts<M>(
+                s, n, from_pairs ? c->pair_cnt_stride : c->cnt_stride, (const uint8_t *)c->labels,
+                T.d_init_lut, (int)std::min<int64_t>(T.init_lut_len, 256),
+                from_pairs ? c->pair_cnt.as<uint8_t>() : c->lab_cnt.as<uint8_t>(), cnl, nd,
+                nd + T.n0 + 1, nd + T.n0 + 1 + T.need_lab.size(), T.n0, om);
             k.stop(st.ms_sweep_kernel);
             // compulsory bytes: every label, for each vertex the count bytes
             // of the labels its initial roles need (a function of its
@@ -1111,7 +1124,7 @@ struct Pruner {
                 uint64_t used = 0;
                 for (int q = 0; q < T.n0; ++q)
                     if (T.labels[(size_t)q] == (int)L) used |= T.need_labmask[(size_t)q];
-                const uint64_t in_index = c->nlab >= 64 ? ~0ull : ((1ull << c->nlab) - 1ull);
+                const uint64_t in_index = cnl >= 64 ? ~0ull : ((1ull << cnl) - 1ull);
                 reads += c->label_freq[L] * (int64_t)__builtin_popcountll(used & in_index);
             }
             st.first_sweep_vertices = n;
@@ -1791,6 +1804,7 @@ void build_pair_index(pm_ctx *c, int32_t first, int32_t count) {
     c->pair_m = -1;
     c->pair_nl = 0;
     c->pair_adj.clear();
+    c->pair_cnt_nlab = 0;
     int maxl = -1;
     for (int32_t i = first; i < first + count; ++i)
         for (int l : c->templates[(size_t)i]->labels) maxl = std::max(maxl, l);
@@ -1846,6 +1860,17 @@ void build_pair_index(pm_ctx *c, int32_t first, int32_t count) {
                                   hipMemcpyDeviceToDevice, c->stream));
         }
         c->pair_m = p.c_m;
+        if (c->index_nlab > 0) {
+            // its count index: one pass over its rows
+            const int64_t np = (n + 255) / 256 * 256;
+            c->pair_cnt.ensure((size_t)np * (size_t)c->index_nlab);
+            launch_label_count_rows(c->stream, n, np, c->pair_rp.as<int64_t>(),
+                                    c->pair_col.as<int32_t>(), (const uint8_t *)c->labels,
+                                    c->index_nlab, c->pair_cnt.as<uint8_t>());
+            PM_HIP(hipGetLastError());
+            c->pair_cnt_stride = np;
+            c->pair_cnt_nlab = c->index_nlab;
+        }
     };
     switch (P.mask_bytes) {
     case 1: { Pruner<uint8_t> p(c, &tmp, P); go(p); break; }
@@ -1864,6 +1889,8 @@ void drop_pair_index(pm_ctx *c) {
     c->pair_rp.release();
     c->pair_col.release();
     c->pair_off.release();
+    c->pair_cnt.release();
+    c->pair_cnt_nlab = 0;
     c->pair_m = -1;
     c->pair_nl = 0;
     c->pair_adj.clear();

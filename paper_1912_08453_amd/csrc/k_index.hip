@@ -30,6 +30,10 @@ constexpr int kIdxTile = 256;        // vertices per block = threads per block
 constexpr int kIdxUnroll = 8;        // entries per thread in flight
 constexpr int kIdxPairs = kCountLabels / 2;
 
+// kSat: rows may hold more than 65,535 entries of one label; a 16-bit
+// counter that already holds 255 gives its increment back, so it never
+// exceeds 255 + (threads of the block) and never carries into its neighbour.
+template <bool kSat>
 __global__ __launch_bounds__(kIdxTile) void label_count_tiles_kernel(
     int64_t n, int64_t np, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const uint8_t *__restrict__ labels, int nlab, uint8_t *__restrict__ cnt, int64_t hub_min) {
@@ -98,7 +102,13 @@ __global__ __launch_bounds__(kIdxTile) void label_count_tiles_kernel(
                     if (s_off[mid] <= k[u]) a = mid;
                     else b = mid;
                 }
-                atomicAdd(&s_h[lab[u] >> 1][a], 1u << ((lab[u] & 1) * 16));
+                const int sh = (lab[u] & 1) * 16;
+                if (kSat) {
+                    const uint32_t was = atomicAdd(&s_h[lab[u] >> 1][a], 1u << sh);
+                    if (((was >> sh) & 0xffffu) >= 255u) atomicSub(&s_h[lab[u] >> 1][a], 1u << sh);
+                } else {
+                    atomicAdd(&s_h[lab[u] >> 1][a], 1u << sh);
+                }
             }
         }
     }
@@ -170,8 +180,8 @@ void launch_label_count(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
                         const CountIndexHubs &h) {
     if (n <= 0) return;
     const int64_t tiles = (n + kIdxTile - 1) / kIdxTile;
-    hipLaunchKernelGGL(label_count_tiles_kernel, dim3((unsigned)tiles), dim3(kIdxTile), 0, s, n,
-                       np, rp, col, labels, nlab, cnt, (int64_t)kBinWaveMaxDeg);
+    hipLaunchKernelGGL(label_count_tiles_kernel<false>, dim3((unsigned)tiles), dim3(kIdxTile), 0, s,
+                       n, np, rp, col, labels, nlab, cnt, (int64_t)kBinWaveMaxDeg);
     if (h.n_segs > 0) {
         launch_fill_i32(s, reinterpret_cast<int32_t *>(h.hub_cnt), h.n_hubs * kCountLabels, 0);
         hipLaunchKernelGGL(label_count_hub_kernel,
@@ -181,6 +191,17 @@ void launch_label_count(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
                            dim3((unsigned)((h.n_hubs * kCountLabels + kIdxTile - 1) / kIdxTile)),
                            dim3(kIdxTile), 0, s, h, np, nlab, cnt);
     }
+}
+
+// Every row in the tiles, with saturating counters (no hub pass): for a
+// subgraph whose rows are short enough that a tile's stretch stays below
+// 2^32 entries, such as the label-pair subgraph.
+void launch_label_count_rows(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
+                             const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt) {
+    if (n <= 0) return;
+    const int64_t tiles = (n + kIdxTile - 1) / kIdxTile;
+    hipLaunchKernelGGL(label_count_tiles_kernel<true>, dim3((unsigned)tiles), dim3(kIdxTile), 0, s,
+                       n, np, rp, col, labels, nlab, cnt, INT64_MAX);
 }
 
 }  // namespace pm

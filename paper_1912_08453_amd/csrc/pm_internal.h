@@ -415,6 +415,11 @@ struct CountIndexHubs {
 void launch_label_count(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
                         const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt,
                         const CountIndexHubs &h);
+// The same counts for every row of a subgraph given as CSR over all n
+// vertices (rows of up to 2^31 entries; counts saturate at 255), in one
+// pass without a hub list.
+void launch_label_count_rows(hipStream_t s, int64_t n, int64_t np, const int64_t *rp,
+                             const int32_t *col, const uint8_t *labels, int nlab, uint8_t *cnt);
 
 // First LCC sweep from the count index: omega(v) = roles q of label(v) with
 // cnt[L][v] >= need for every (L, need) of q (need_off[q] .. need_off[q+1]

@@ -223,7 +223,9 @@ def test_theta8_relaxations_scale26(pmmod, torch_dev):
     template with a repeated-label pair 4 hops apart and its connected
     1- and 2-edge-deletion relaxations, pruned as one batch on concurrent
     streams with the learned order (the benchmark's configuration): seeded
-    variants checked against the oracle."""
+    variants checked against the oracle, then every variant's output
+    unchanged when the batch's label-pair subgraph and its counts are
+    built first."""
     from paper_1912_08453_amd import order_training as OT
     torch, dev = torch_dev
     g = _graph(26, 26)
@@ -250,4 +252,15 @@ def test_theta8_relaxations_scale26(pmmod, torch_dev):
         log(f"  oracle state {time.time() - t0:.1f}s, {int((om != 0).sum())} vertices")
         check_final(pmmod, g, t, om, pmmod.to_u64(rb[i]), pmmod.to_u64(eb[i]), n_keep=300,
                     n_pruned=100, seed=200 + i)
+    # with the batch's label-pair subgraph (first sweeps from its counts,
+    # first compactions from its rows): every variant's output unchanged
+    ms = ctx.build_pair_index(first, len(ts))
+    log(f"label-pair subgraph {ctx.graph_info()['pair_entries']} entries, {ms:.1f} ms")
+    rb2 = torch.empty_like(rb)
+    eb2 = torch.empty_like(eb)
+    ctx.prune(first, count=len(ts), role_mask=rb2, edge_bits=eb2, batch_streams=4,
+              order="learned")
+    for i in range(len(ts)):
+        assert torch.equal(rb2[i], rb[i]) and torch.equal(eb2[i], eb[i]), \
+            f"variant {i}: output differs with the label-pair subgraph"
     ctx.close()

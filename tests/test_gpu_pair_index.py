@@ -4,7 +4,8 @@ here with numpy), prunes that start their first compaction from it give the
 oracle's complete sets (batched and one call per template, with the
 witness joins on), a template whose label pairs it does not hold and the
 edge-elimination ablation fall back to the whole graph, match counts are
-unchanged, and count 0 frees it."""
+unchanged, and count 0 frees it.  The first LCC sweep of a covered template
+reads the subgraph's own count index (also past 16-bit row counts)."""
 import sys
 
 import numpy as np
@@ -135,4 +136,52 @@ def test_counts_unchanged_and_count_zero_frees(pmmod, torch_dev):
     assert ctx.graph_info()["pair_entries"] == -1
     with pytest.raises(pmmod.PMError):
         ctx.build_pair_index(tid + 5, 1)
+    ctx.close()
+
+
+def test_first_sweep_from_pair_counts(pmmod, torch_dev, relax_case):
+    """With the label-pair subgraph built, the first LCC sweep of a covered
+    template reads the subgraph's own count index: the LCC fixpoint (no
+    non-local check) still equals the oracle's, and so does the state after
+    the first constraints."""
+    scale, g, ts, _ = relax_case
+    ctx = load(pmmod, torch_dev, g)
+    first = ctx.load_templates(ts)
+    ctx.build_pair_index(first, len(ts))
+    for i in (0, 1, 5, len(ts) - 1):
+        t = ts[i]
+        for k in (0, 1):
+            ref = oracle.prune(g.row_ptr, g.col, g.labels, t.labels, t.edges, stop_after=k)
+            role, edge, st = ctx.prune(first + i, stop_after=k)
+            same_as(pmmod, role[0], edge[0], ref, f"scale {scale} template {i} after {k}")
+    ctx.close()
+
+
+def test_pair_counts_saturate_on_rows_past_16_bits(pmmod, torch_dev):
+    """A row of the label-pair subgraph with more than 65,535 entries of one
+    label: the 16-bit tile counters must saturate instead of wrapping.  A
+    star whose centre (label 0) has 65,546 leaves (label 2); the template is
+    a star with 20 leaves of label 2, so the centre keeps its role only if
+    its count of label-2 neighbours reads at least 20 (a wrapped counter
+    would read 10)."""
+    leaves = 65546
+    n = leaves + 1
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1] = leaves
+    rp[2:] = leaves + np.arange(1, leaves + 1)
+    col = np.concatenate([np.arange(1, n, dtype=np.int32), np.zeros(leaves, dtype=np.int32)])
+    lab = np.full(n, 2, dtype=np.uint8)
+    lab[0] = 0
+    g = I.Graph(rp, col, lab)
+    t = I.Template([0] + [2] * 20, [(0, j) for j in range(1, 21)])
+    ref = oracle.prune(g.row_ptr, g.col, g.labels, t.labels, t.edges, stop_after=0)
+    assert ref.role_mask[0] == 1
+    ctx = load(pmmod, torch_dev, g)
+    tid = ctx.load_templates([t])
+    for built in (False, True):
+        if built:
+            ctx.build_pair_index(tid, 1)
+            assert ctx.graph_info()["pair_entries"] == 2 * leaves
+        role, edge, _ = ctx.prune(tid, stop_after=0)
+        same_as(pmmod, role[0], edge[0], ref, f"star, pair subgraph built: {built}")
     ctx.close()
