@@ -58,6 +58,30 @@ __device__ __forceinline__ void set_bit(uint64_t *bits, int64_t e) {
     atomicOr((unsigned long long *)(bits + (e >> 6)), 1ull << (e & 63));
 }
 
+// Bit e set for every lane with `valid`, with one atomic OR per run of
+// lanes that target the same 64-bit word (a segmented OR over the lanes).
+// All 64 lanes of the wavefront call it together; bit indices below 2^37.
+// Lanes whose indices ascend with the lane number share the most atomics.
+__device__ __forceinline__ void set_bits_wave(uint64_t *bits, int64_t e, bool valid) {
+    const int lane = lane_id();
+    const int32_t word = valid ? (int32_t)(e >> 6) : -1;
+    const int b = (int)(e & 63);
+    uint32_t lo = valid && b < 32 ? 1u << b : 0u;
+    uint32_t hi = valid && b >= 32 ? 1u << (b - 32) : 0u;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t wu = __shfl_up(word, off);
+        const uint32_t lu = __shfl_up(lo, off), hu = __shfl_up(hi, off);
+        if (lane >= off && wu == word) {
+            lo |= lu;
+            hi |= hu;
+        }
+    }
+    const int32_t wn = __shfl_down(word, 1);
+    if (valid && (lane == 63 || wn != word))
+        atomicOr((unsigned long long *)(bits + word), ((unsigned long long)hi << 32) | lo);
+}
+
 // Binary search of x in the sorted range col[lo, hi); returns index or -1.
 __device__ __forceinline__ int64_t find_sorted(const int32_t *col, int64_t lo, int64_t hi,
                                                int32_t x) {

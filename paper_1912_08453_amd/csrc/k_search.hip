@@ -1178,16 +1178,24 @@ void launch_split_search(hipStream_t s, const SplitTask *tasks, int64_t n_tasks,
 // certificate word; a certified one sets its own CSR entry's bit and, found
 // by a search of w's compacted row, that of its reverse entry.  The searches
 // scale with the certified entries, not with the candidate subgraph.
+// Entries go by wavefront-aligned chunks: the own bits of a chunk ascend
+// (rows in vertex order), so they take one atomic per output word.
 __global__ __launch_bounds__(kSearchBlock) void edges_from_cert_kernel(
     int64_t c_m, const int64_t *c_rp, const int32_t *c_col, const int32_t *c_own,
     const int32_t *c_off, const int64_t *rp, const uint64_t *c_cert, uint64_t *edge_bits) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < c_m;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        if (!test_bit(c_cert, k)) continue;
-        const int32_t u = c_own[k], w = c_col[k];
-        set_bit(edge_bits, rp[u] + c_off[k]);
-        const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
-        if (kr >= 0) set_bit(edge_bits, rp[w] + c_off[kr]);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < c_m;
+         base += stride) {
+        const int64_t k = base + lane_id();
+        const bool cert = k < c_m && test_bit(c_cert, k);
+        int64_t own = 0;
+        if (cert) {
+            const int32_t u = c_own[k], w = c_col[k];
+            own = rp[u] + c_off[k];
+            const int64_t kr = find_sorted(c_col, c_rp[w], c_rp[w + 1], u);
+            if (kr >= 0) set_bit(edge_bits, rp[w] + c_off[kr]);
+        }
+        set_bits_wave(edge_bits, own, cert);
     }
 }
 
@@ -1215,8 +1223,13 @@ __global__ __launch_bounds__(kSearchBlock) void active_edges_kernel(
         const uint64_t reach = reach_mask<M>((uint64_t)om[u], tab);
         if (!reach) continue;
         const int64_t s = c_rp[u], e = c_rp[u + 1], r0 = rp[u];
-        for (int64_t k = s + lane; k < e; k += kWave)
-            if ((uint64_t)om[c_col[k]] & reach) set_bit(edge_bits, r0 + c_off[k]);
+        // the row's entries go 64 at a time (bounds uniform over the
+        // wavefront): one atomic per output word
+        for (int64_t k0 = s; k0 < e; k0 += kWave) {
+            const int64_t k = k0 + lane;
+            const bool on = k < e && ((uint64_t)om[c_col[k]] & reach);
+            set_bits_wave(edge_bits, on ? r0 + c_off[k] : 0, on);
+        }
     }
 }
 

@@ -210,50 +210,67 @@ __global__ __launch_bounds__(kTreeBlock) void tree_branch_kernel(
 }
 
 // Edge output: the entry u -> w is set iff it can carry a template edge of
-// some match (both directions of an edge reach the same answer).
+// some match (both directions of an edge reach the same answer).  Entries
+// go by wavefront-aligned chunks, so the bits of a chunk (ascending within
+// each row, rows in vertex order) are set with one atomic per output word.
+template <typename M>
+__device__ __forceinline__ bool tree_edge_good(int32_t u, int32_t w, uint64_t ou,
+                                               const M *__restrict__ om,
+                                               const int32_t *__restrict__ pos,
+                                               const TreePlan &tp, const int2 *__restrict__ sum,
+                                               int64_t nA, const M *__restrict__ sat) {
+    const int k = tp.k;
+    const uint64_t ow = (uint64_t)om[w];
+    const uint64_t su = (uint64_t)sat[u], sw = (uint64_t)sat[w];
+    for (int j = 0; j < tp.m0; ++j) {
+        for (int o = 0; o < 2; ++o) {
+            const int x = o ? tp.eb[j] : tp.ea[j];   // on u
+            const int y = o ? tp.ea[j] : tp.eb[j];   // on w
+            if (!((ou >> x) & 1ull) || !((ow >> y) & 1ull)) continue;
+            const int px = tp.pos[x], py = tp.pos[y];
+            bool good;
+            if (px >= 0 && py >= 0) {
+                // path edge: the left part ends on the lower position
+                const int64_t tu = pos[u], tw = pos[w];
+                if ((uint64_t)tu >= (uint64_t)nA || (uint64_t)tw >= (uint64_t)nA) continue;
+                int2 l, r;
+                if (py == px + 1) {
+                    l = sum[((int64_t)px) * nA + tu];
+                    r = sum[((int64_t)(k + 1 + py)) * nA + tw];
+                } else {
+                    l = sum[((int64_t)py) * nA + tw];
+                    r = sum[((int64_t)(k + 1 + px)) * nA + tu];
+                }
+                good = distinct_ends(l, r);
+            } else if (tp.par[x] == y) {
+                good = (sw >> y) & 1ull;       // x off the path, y towards it
+            } else {
+                good = (su >> x) & 1ull;       // y off the path, x towards it
+            }
+            if (good) return true;
+        }
+    }
+    return false;
+}
+
 template <typename M>
 __global__ __launch_bounds__(kTreeBlock) void tree_edges_kernel(
     int64_t c_m, const int32_t *__restrict__ c_own, const int32_t *__restrict__ c_col,
     const int32_t *__restrict__ c_off, const int64_t *__restrict__ rp, const M *__restrict__ om,
     const int32_t *__restrict__ pos, TreePlan tp, const int2 *__restrict__ sum, int64_t nA,
     const M *__restrict__ sat, uint64_t *edge_bits) {
-    const int k = tp.k;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < c_m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t u = c_own[e];
-        const uint64_t ou = (uint64_t)om[u];
-        if (!ou) continue;
-        const int32_t w = c_col[e];
-        const uint64_t ow = (uint64_t)om[w];
-        const uint64_t su = (uint64_t)sat[u], sw = (uint64_t)sat[w];
+    TREE_FOR_CHUNKS(c_m, e) {
         bool good = false;
-        for (int j = 0; j < tp.m0 && !good; ++j) {
-            for (int o = 0; o < 2 && !good; ++o) {
-                const int x = o ? tp.eb[j] : tp.ea[j];   // on u
-                const int y = o ? tp.ea[j] : tp.eb[j];   // on w
-                if (!((ou >> x) & 1ull) || !((ow >> y) & 1ull)) continue;
-                const int px = tp.pos[x], py = tp.pos[y];
-                if (px >= 0 && py >= 0) {
-                    // path edge: the left part ends on the lower position
-                    const int64_t tu = pos[u], tw = pos[w];
-                    if ((uint64_t)tu >= (uint64_t)nA || (uint64_t)tw >= (uint64_t)nA) continue;
-                    int2 l, r;
-                    if (py == px + 1) {
-                        l = sum[((int64_t)px) * nA + tu];
-                        r = sum[((int64_t)(k + 1 + py)) * nA + tw];
-                    } else {
-                        l = sum[((int64_t)py) * nA + tw];
-                        r = sum[((int64_t)(k + 1 + px)) * nA + tu];
-                    }
-                    good = distinct_ends(l, r);
-                } else if (tp.par[x] == y) {
-                    good = (sw >> y) & 1ull;       // x off the path, y towards it
-                } else {
-                    good = (su >> x) & 1ull;       // y off the path, x towards it
-                }
+        int64_t bit = 0;
+        if (e < c_m) {
+            const int32_t u = c_own[e];
+            const uint64_t ou = (uint64_t)om[u];
+            if (ou && tree_edge_good<M>(u, c_col[e], ou, om, pos, tp, sum, nA, sat)) {
+                good = true;
+                bit = rp[u] + c_off[e];
             }
         }
-        if (good) set_bit(edge_bits, rp[u] + c_off[e]);
+        set_bits_wave(edge_bits, bit, good);
     }
 }
 
