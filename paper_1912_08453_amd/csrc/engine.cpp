@@ -1038,7 +1038,13 @@ struct Pruner {
                 k = order[pos++];
             }
             const int64_t active_before = nA;
-            if (featured) {
+            // the learned order has no choice to make for the last remaining
+            // constraint (unless a threshold or the trace needs its score)
+            const bool forced_last = learned && !trace && !(opt && opt->learned_stop) &&
+                                     __builtin_popcountll(remaining) == 1;
+            if (forced_last) {
+                k = __builtin_ctzll(remaining);
+            } else if (featured) {
                 pk = pick(learned ? -1 : k, remaining, done);
                 if (pending_after >= 0) {
                     trace[pending_after].roles_after = (int64_t)pk.roles;
