@@ -334,9 +334,15 @@ int pm_build_count_index(pm_ctx *ctx, double *ms);
    drops it in every prune: every later prune of a template whose edges'
    label pairs the subgraph holds starts its first compaction from it
    instead of from the whole graph (same results; with
-   PM_ABLATE_EDGE_ELIMINATION the whole graph is used).  Meant for batches
-   and sessions of templates over the same labels, e.g. a template and its
-   relaxations.  *ms (may be NULL) receives its device time.
+   PM_ABLATE_EDGE_ELIMINATION the whole graph is used).  On a graph eligible
+   for the count index, the call also counts the labels of every row of the
+   subgraph (same layout as the count index, labels x n bytes): the first
+   LCC sweep reads a vertex's counts only for labels of template neighbours
+   of its roles, label pairs the subgraph keeps whole, so a template it
+   covers takes its first sweep from these counts, with the same result as
+   from the graph's index.  Meant for batches and sessions of templates over
+   the same labels, e.g. a template and its relaxations.  *ms (may be NULL)
+   receives its device time (subgraph and counts).
    PM_ERR_INVALID_ARG if the templates' edges use more than 64 labels or an
    id is out of range; PM_ERR_CAPACITY if the subgraph would have 2^31
    entries or more (no subgraph is kept then). */

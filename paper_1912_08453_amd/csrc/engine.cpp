@@ -619,10 +619,12 @@ struct Pruner {
         DevBuf &ccol = nb ? w->ccol2 : w->ccol;
         DevBuf &coff = nb ? w->coff2 : w->coff;
         DevBuf &cown = nb ? w->cown2 : w->cown;
-        w->cdeg.ensure(sizeof(int64_t) * (size_t)(n + 1));
+        // kept entries per row, 32-bit (a candidate subgraph holds under
+        // 2^31 entries), scanned into the 64-bit row pointer
+        w->cdeg.ensure(sizeof(int32_t) * (size_t)(n + 1));
         crp.ensure(sizeof(int64_t) * (size_t)(n + 1));
-        int64_t *deg = w->cdeg.as<int64_t>();
-        PM_HIP(hipMemsetAsync(deg, 0, sizeof(int64_t) * (size_t)(n + 1), s));
+        int32_t *deg = w->cdeg.as<int32_t>();
+        PM_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t)(n + 1), s));
         if (first) {
             // coarse filter of the active set; it stays valid (a superset)
             // for later compactions of this prune, since role sets only shrink
@@ -1244,7 +1246,14 @@ struct Pruner {
                 launch_active_edges<M>(s, A, nA, c_rp, c_col, c_off, c->rp, om, lcc, edge_out);
             st.result_vertices = nA;
         } else if (T.tree_pair && c->tree_exact) {
-            if (nA > 0 && nA * 4 < nA_compact * 3) compact(true);
+            // the sweeps make k + depth + 2 passes of ~16 bytes per entry;
+            // a compaction costs ~20 bytes per vertex of the graph (row
+            // lengths cleared, counted, scanned into the row pointer) on
+            // top of its own entries, so it can pay only when the entries
+            // outweigh the vertices
+            const int64_t passes = T.tree.k + T.tree.depth + 2;
+            if (nA > 0 && nA * 4 < nA_compact * 3 && c_m * passes * 16 > c->n * 20)
+                compact(true);
             tree_final(role_out, edge_out);
         } else {
             // a fresh candidate subgraph only when the active set has shrunk
@@ -1564,7 +1573,7 @@ size_t workspace_bound(const pm_ctx *c, const CompiledTemplate &T, int exp_log2,
     add(C_TOTAL_BYTES);                                       // counters
     add(segs * (4 + 8 + 8 + 4) + hubs * (4 + 4 + 8 + 4 * kMaxCount + 4) + 256);
     add(8 * segs); add(8 * (segs + 1)); add(8 * segs * (kHubSegment / kWave));
-    add(8 * (n + 1)); add(8 * (n + 1)); add(8 * (n + 1));     // cdeg, crp, crp2
+    add(4 * (n + 1)); add(8 * (n + 1)); add(8 * (n + 1));     // cdeg, crp, crp2
     add(8 * scan_scratch_len(std::max<int64_t>(n, segs)));
     for (int i = 0; i < 6; ++i) add(4 * mt);                  // two sets of c_col/c_off/c_own
     add(4 * ((n + 255) / 256));                               // active filter

@@ -160,6 +160,7 @@ __device__ __forceinline__ int degree_bin(int64_t d, const Worklists &wl) {
 // atomic per list per chunk instead of one per wavefront: on graphs with
 // tens of millions of vertices the per-wavefront counter atomics serialise).
 constexpr int kStageChunk = 2048;
+constexpr int kStageRounds = kStageChunk / kBlock;   // entries per thread and chunk
 
 __device__ __forceinline__ void stage_append(bool pred, int32_t v, int32_t *buf, int32_t *cnt) {
     const uint64_t m = ballot64(pred);
@@ -184,16 +185,27 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(const int32_t *in, int64_t 
         if (threadIdx.x == 0) ent = 0;
         __syncthreads();
         unsigned long long tot = 0;
-        for (int r = 0; r < kStageChunk; r += kBlock) {
-            const int64_t i = c0 + r + threadIdx.x;
-            const bool valid = i < n_in;
-            const int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
-            const bool act = valid && omega[v] != 0;
-            const int64_t d = act ? rp[v + 1] - rp[v] : 0;
-            const int b = act ? degree_bin(d, wl) : -1;
-            tot += (unsigned long long)d;
+        // every round's loads issued before the first append: one latency
+        // per chain of dependent loads instead of one per round
+        int32_t vs[kStageRounds];
+        bool act[kStageRounds];
+        int64_t d[kStageRounds];
 #pragma unroll
-            for (int k = 0; k < kNumBins; ++k) stage_append(b == k, v, buf[k], &cnt[k]);
+        for (int r = 0; r < kStageRounds; ++r) {
+            const int64_t i = c0 + (int64_t)r * kBlock + threadIdx.x;
+            act[r] = i < n_in;
+            vs[r] = act[r] ? (in ? in[i] : (int32_t)i) : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) act[r] = act[r] && omega[vs[r]] != 0;
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) d[r] = act[r] ? rp[vs[r] + 1] - rp[vs[r]] : 0;
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) {
+            const int b = act[r] ? degree_bin(d[r], wl) : -1;
+            tot += (unsigned long long)d[r];
+#pragma unroll
+            for (int k = 0; k < kNumBins; ++k) stage_append(b == k, vs[r], buf[k], &cnt[k]);
         }
         for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
         if (lane_id() == 0 && tot) atomicAdd(&ent, tot);
@@ -220,12 +232,19 @@ __global__ __launch_bounds__(kBlock) void collect_kernel(const int32_t *in, int6
          c0 += (int64_t)gridDim.x * kStageChunk) {
         if (threadIdx.x == 0) cnt = 0;
         __syncthreads();
-        for (int r = 0; r < kStageChunk; r += kBlock) {
-            const int64_t i = c0 + r + threadIdx.x;
-            const bool valid = i < n_in;
-            const int32_t v = valid ? (in ? in[i] : (int32_t)i) : 0;
-            stage_append(valid && omega[v] != 0, v, buf, &cnt);
+        // loads of every round first, then the appends (see bin_kernel)
+        int32_t vs[kStageRounds];
+        bool live[kStageRounds];
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) {
+            const int64_t i = c0 + (int64_t)r * kBlock + threadIdx.x;
+            live[r] = i < n_in;
+            vs[r] = live[r] ? (in ? in[i] : (int32_t)i) : 0;
         }
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) live[r] = live[r] && omega[vs[r]] != 0;
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) stage_append(live[r], vs[r], buf, &cnt);
         __syncthreads();
         if (threadIdx.x == 0) base = cnt ? atomicAdd(counter, cnt) : 0;
         __syncthreads();
@@ -625,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void compact_count_group(const int64_t *__r
                                                               const int32_t *__restrict__ list,
                                                               int64_t count, LccTable tab,
                                                               const uint32_t *__restrict__ filt,
-                                                              int64_t *deg_out) {
+                                                              int32_t *deg_out) {
     const int sl = lane_id() & (G - 1);
     const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const bool valid = idx < count;
@@ -666,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
                                                             Worklists wl, int64_t n_seg,
                                                             LccTable tab,
                                                             const uint32_t *__restrict__ filt,
-                                                            int64_t *deg_out,
+                                                            int32_t *deg_out,
                                                             int64_t *seg_count,
                                                             uint64_t *seg_bits) {
     const int lane = lane_id();
@@ -702,7 +721,7 @@ __global__ __launch_bounds__(kBlock) void compact_count_hub(const int64_t *__res
     }
     if (lane == 0) {
         seg_count[seg] = c;
-        if (c) atomicAdd((unsigned long long *)&deg_out[v], (unsigned long long)c);
+        if (c) atomicAdd(&deg_out[v], (int32_t)c);
     }
 }
 
@@ -800,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void compact_fill_hub(
 template <typename M>
 void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                           const Worklists &wl, const int64_t *hc, int64_t n_seg,
-                          const LccTable &tab, const uint32_t *filt, int64_t *deg_out,
+                          const LccTable &tab, const uint32_t *filt, int32_t *deg_out,
                           int64_t *seg_count, uint64_t *seg_bits) {
     if (hc[0] > 0)
         hipLaunchKernelGGL((compact_count_group<M, 4>),
@@ -857,14 +876,14 @@ __global__ void fill_from_kernel(const int64_t *src, int64_t *dst) { *dst = *src
 constexpr int kScanPer = 16;
 constexpr int kScanTile = kBlock * kScanPer;
 
-__global__ __launch_bounds__(kBlock) void scan_tile_sums(const int64_t *in, int64_t n,
-                                                         int64_t *sums) {
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scan_tile_sums(const T *in, int64_t n, int64_t *sums) {
     __shared__ int64_t red[kBlock / kWave];
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     int64_t acc = 0;
     for (int j = 0; j < kScanPer; ++j) {
         int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
-        if (i < n) acc += in[i];
+        if (i < n) acc += (int64_t)in[i];
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
@@ -907,8 +926,9 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t *wsum
 // kScanPer elements padded by one, so a thread's row reads hit distinct
 // banks), each thread sums its row, the block scans the row sums, and the
 // exclusive prefixes go back through LDS to coalesced stores.  in may equal
-// out.  base_add is added to every output.
-__device__ __forceinline__ void scan_tile(const int64_t *in, int64_t *out, int64_t n,
+// out (64-bit input).  base_add is added to every output.
+template <typename T>
+__device__ __forceinline__ void scan_tile(const T *in, int64_t *out, int64_t n,
                                           int64_t tile0, int64_t base_add, int64_t *stage,
                                           int64_t *wsum, int64_t *tile_total) {
     constexpr int kPad = kScanPer + 1;
@@ -916,7 +936,7 @@ __device__ __forceinline__ void scan_tile(const int64_t *in, int64_t *out, int64
     for (int j = 0; j < kScanPer; ++j) {
         const int e = j * kBlock + threadIdx.x;          // element within the tile
         const int64_t i = tile0 + e;
-        stage[(e / kScanPer) * kPad + (e % kScanPer)] = i < n ? in[i] : 0;
+        stage[(e / kScanPer) * kPad + (e % kScanPer)] = i < n ? (int64_t)in[i] : 0;
     }
     __syncthreads();
     int64_t row = 0;
@@ -948,35 +968,43 @@ __global__ __launch_bounds__(kBlock) void scan_small_kernel(int64_t *a, int64_t 
     __shared__ int64_t stage[kBlock * (kScanPer + 1)];
     __shared__ int64_t wsum[kBlock / kWave];
     int64_t total = 0;
-    scan_tile(a, a, n, 0, 0, stage, wsum, &total);
+    scan_tile<int64_t>(a, a, n, 0, 0, stage, wsum, &total);
     if (threadIdx.x == 0) *total_out = total;
 }
 
-__global__ __launch_bounds__(kBlock) void scan_apply(const int64_t *in, int64_t n,
-                                                     const int64_t *sums, int64_t *out) {
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scan_apply(const T *in, int64_t n, const int64_t *sums,
+                                                     int64_t *out) {
     __shared__ int64_t stage[kBlock * (kScanPer + 1)];
     __shared__ int64_t wsum[kBlock / kWave];
     int64_t total = 0;
-    scan_tile(in, out, n, (int64_t)blockIdx.x * kScanTile, sums[blockIdx.x], stage, wsum, &total);
+    scan_tile<T>(in, out, n, (int64_t)blockIdx.x * kScanTile, sums[blockIdx.x], stage, wsum,
+                 &total);
 }
 
 // Tile sums, an exclusive scan of the tile sums (in one block when there
 // are at most kScanTile of them, else recursively), then every tile scanned
-// with its offset.  scratch holds scan_scratch_len(n) values.
-void launch_exclusive_scan(hipStream_t s, const int64_t *in, int64_t *out, int64_t n,
-                           int64_t *scratch, int64_t len) {
+// with its offset.  scratch holds scan_scratch_len(n) values.  T: int64_t
+// or int32_t input (the output is 64-bit either way).
+template <typename T>
+void launch_exclusive_scan(hipStream_t s, const T *in, int64_t *out, int64_t n, int64_t *scratch,
+                           int64_t len) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) nb = 1;
-    hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch);
+    hipLaunchKernelGGL(scan_tile_sums<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch);
     if (nb <= kScanTile) {
         hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kBlock), 0, s, scratch, nb, out + n);
     } else {
         // scratch[0, nb) scanned in place; its total to out[n]
-        launch_exclusive_scan(s, scratch, scratch, nb, scratch + nb + 1, len - nb - 1);
+        launch_exclusive_scan<int64_t>(s, scratch, scratch, nb, scratch + nb + 1, len - nb - 1);
         hipLaunchKernelGGL(fill_from_kernel, dim3(1), dim3(1), 0, s, scratch + nb, out + n);
     }
-    hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch, out);
+    hipLaunchKernelGGL(scan_apply<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch, out);
 }
+template void launch_exclusive_scan<int64_t>(hipStream_t, const int64_t *, int64_t *, int64_t,
+                                             int64_t *, int64_t);
+template void launch_exclusive_scan<int32_t>(hipStream_t, const int32_t *, int64_t *, int64_t,
+                                             int64_t *, int64_t);
 
 int64_t scan_scratch_len(int64_t n) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -1068,7 +1096,7 @@ void launch_widen(hipStream_t s, int64_t n, const M *src, uint64_t *dst) {
                                       const LccTable &, int32_t *, bool);                         \
     template void launch_compact_count<M>(hipStream_t, const int64_t *, const int32_t *,           \
                                           const M *, const Worklists &, const int64_t *, int64_t, \
-                                          const LccTable &, const uint32_t *, int64_t *,          \
+                                          const LccTable &, const uint32_t *, int32_t *,          \
                                           int64_t *, uint64_t *);                                 \
     template void launch_active_filter<M>(hipStream_t, int64_t, const M *, uint32_t *);          \
     template void launch_compact_fill<M>(hipStream_t, const int64_t *, const int32_t *, const M *, \

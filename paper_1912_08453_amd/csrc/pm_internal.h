@@ -213,8 +213,9 @@ void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *o
                       const LccTable &tab, int32_t *changed, bool full);
 
 // Candidate-subgraph compaction: keep the entries u->w of active u whose
-// roles are adjacent (edge elimination).  Count pass writes deg_out[v] for
-// binned v (deg_out must be zeroed; hubs accumulate per segment into
+// roles are adjacent (edge elimination).  Count pass writes deg_out[v]
+// (32-bit: a compacted graph holds under 2^31 entries) for binned v
+// (deg_out must be zeroed; hubs accumulate per segment into
 // seg_count and store each segment's keep bits in seg_bits, kHubSegment/64
 // words per segment), then an exclusive scan gives c_rp (n+1) and another
 // one over seg_count gives seg_scan, then the fill pass writes c_col, c_own
@@ -224,13 +225,16 @@ void launch_lcc_sweep(hipStream_t s, const int64_t *rp, const int32_t *col, M *o
 template <typename M>
 void launch_compact_count(hipStream_t s, const int64_t *rp, const int32_t *col, const M *omega,
                           const Worklists &wl, const int64_t *host_counts, int64_t n_seg,
-                          const LccTable &tab, const uint32_t *filt, int64_t *deg_out,
+                          const LccTable &tab, const uint32_t *filt, int32_t *deg_out,
                           int64_t *seg_count, uint64_t *seg_bits);
 // Coarse filter of the active vertices (bit g: one of vertices 8g..8g+7
 // has a non-empty role set), ceil(n / 256) 32-bit words, fully written.
 template <typename M>
 void launch_active_filter(hipStream_t s, int64_t n, const M *omega, uint32_t *filt);
-void launch_exclusive_scan(hipStream_t s, const int64_t *in, int64_t *out, int64_t n,
+// Exclusive scan of n values (T: int64_t, or int32_t) into 64-bit out[0, n),
+// their sum to out[n]; scratch holds scan_scratch_len(n) values.
+template <typename T>
+void launch_exclusive_scan(hipStream_t s, const T *in, int64_t *out, int64_t n,
                            int64_t *scratch, int64_t scratch_len);
 int64_t scan_scratch_len(int64_t n);
 template <typename M>
