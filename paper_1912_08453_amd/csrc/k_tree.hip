@@ -221,7 +221,9 @@ __device__ __forceinline__ bool tree_edge_good(int32_t u, int32_t w, uint64_t ou
                                                int64_t nA, const M *__restrict__ sat) {
     const int k = tp.k;
     const uint64_t ow = (uint64_t)om[w];
-    const uint64_t su = (uint64_t)sat[u], sw = (uint64_t)sat[w];
+    if (!ow) return false;
+    // the certified role sets and list positions are gathered only for
+    // the template edges the entry can carry
     for (int j = 0; j < tp.m0; ++j) {
         for (int o = 0; o < 2; ++o) {
             const int x = o ? tp.eb[j] : tp.ea[j];   // on u
@@ -243,9 +245,9 @@ __device__ __forceinline__ bool tree_edge_good(int32_t u, int32_t w, uint64_t ou
                 }
                 good = distinct_ends(l, r);
             } else if (tp.par[x] == y) {
-                good = (sw >> y) & 1ull;       // x off the path, y towards it
+                good = ((uint64_t)sat[w] >> y) & 1ull;   // x off the path, y towards it
             } else {
-                good = (su >> x) & 1ull;       // y off the path, x towards it
+                good = ((uint64_t)sat[u] >> x) & 1ull;   // y off the path, x towards it
             }
             if (good) return true;
         }
