@@ -222,29 +222,36 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(const int32_t *in, int64_t 
 }
 
 // Active list: the vertices of `in` (or 0..n-1) whose role set is not empty.
+// A block stages kCollectChunk entries in LDS (in groups of kStageRounds
+// per thread, each group's loads issued before its appends) and reserves
+// their place in the list with one global atomic: the counter is a single
+// address, so a pass over all n vertices of a large graph was bound by the
+// serialised atomics of 2,048-entry chunks.
+constexpr int kCollectChunk = 4 * kStageChunk;
 template <typename M>
 __global__ __launch_bounds__(kBlock) void collect_kernel(const int32_t *in, int64_t n_in,
                                                          const M *omega, int32_t *out,
                                                          int32_t *counter) {
-    __shared__ int32_t buf[kStageChunk];
+    __shared__ int32_t buf[kCollectChunk];
     __shared__ int32_t cnt, base;
-    for (int64_t c0 = (int64_t)blockIdx.x * kStageChunk; c0 < n_in;
-         c0 += (int64_t)gridDim.x * kStageChunk) {
+    for (int64_t c0 = (int64_t)blockIdx.x * kCollectChunk; c0 < n_in;
+         c0 += (int64_t)gridDim.x * kCollectChunk) {
         if (threadIdx.x == 0) cnt = 0;
         __syncthreads();
-        // loads of every round first, then the appends (see bin_kernel)
-        int32_t vs[kStageRounds];
-        bool live[kStageRounds];
+        for (int g = 0; g < kCollectChunk; g += kStageChunk) {
+            int32_t vs[kStageRounds];
+            bool live[kStageRounds];
 #pragma unroll
-        for (int r = 0; r < kStageRounds; ++r) {
-            const int64_t i = c0 + (int64_t)r * kBlock + threadIdx.x;
-            live[r] = i < n_in;
-            vs[r] = live[r] ? (in ? in[i] : (int32_t)i) : 0;
+            for (int r = 0; r < kStageRounds; ++r) {
+                const int64_t i = c0 + g + (int64_t)r * kBlock + threadIdx.x;
+                live[r] = i < n_in;
+                vs[r] = live[r] ? (in ? in[i] : (int32_t)i) : 0;
+            }
+#pragma unroll
+            for (int r = 0; r < kStageRounds; ++r) live[r] = live[r] && omega[vs[r]] != 0;
+#pragma unroll
+            for (int r = 0; r < kStageRounds; ++r) stage_append(live[r], vs[r], buf, &cnt);
         }
-#pragma unroll
-        for (int r = 0; r < kStageRounds; ++r) live[r] = live[r] && omega[vs[r]] != 0;
-#pragma unroll
-        for (int r = 0; r < kStageRounds; ++r) stage_append(live[r], vs[r], buf, &cnt);
         __syncthreads();
         if (threadIdx.x == 0) base = cnt ? atomicAdd(counter, cnt) : 0;
         __syncthreads();
@@ -362,8 +369,10 @@ template <typename M>
 void launch_collect(hipStream_t s, const int32_t *in, int64_t n_in, const M *omega,
                     int32_t *out, int32_t *counter) {
     if (n_in <= 0) return;
-    hipLaunchKernelGGL(collect_kernel<M>, dim3(stage_grid(n_in)), dim3(kBlock), 0, s, in, n_in,
-                       omega, out, counter);
+    int64_t g = (n_in + kCollectChunk - 1) / kCollectChunk;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(collect_kernel<M>, dim3((unsigned)g), dim3(kBlock), 0, s, in, n_in, omega,
+                       out, counter);
 }
 
 template <typename M>
